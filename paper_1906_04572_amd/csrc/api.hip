@@ -1,0 +1,915 @@
+// C ABI of libcorutv: contexts, workspace planning, the CoR-UTV pipeline
+// (Sec. 3.1, Algorithm 1), the single-step entry points and the serving
+// scheduler.  Every arithmetic step runs in the HIP kernels of this library;
+// the host only validates, plans buffers and enqueues.
+#include <hip/hip_runtime.h>
+
+#include <algorithm>
+#include <atomic>
+#include <chrono>
+#include <cmath>
+#include <condition_variable>
+#include <cstring>
+#include <deque>
+#include <map>
+#include <mutex>
+#include <new>
+#include <thread>
+#include <vector>
+
+#include "internal.hpp"
+
+using namespace corutv;
+
+// ---------------------------------------------------------------------------
+// workspace plan of one decomposition
+namespace {
+
+constexpr int kMaxQr = 64;  // status words (one per tall-skinny QR)
+
+struct Plan {
+  int64_t mm = 0, nn = 0;  // oriented problem: mm >= nn rows of Q1 / Q2
+  int ell = 0, ellp = 0;
+  int prec = 0;
+  int64_t ldm = 0, ldn = 0, ldx = 0;
+  int64_t part_elems = 0;
+  int xsplits = 0;
+  // byte offsets
+  size_t o_wop = 0, o_qop = 0, o_part = 0, o_x0 = 0, o_x1 = 0, o_q1 = 0, o_q2 = 0, o_xp = 0,
+         o_g = 0, o_r = 0, o_rinv = 0, o_core = 0, o_qt = 0, o_rt = 0, o_qw = 0, o_tt = 0,
+         o_piv = 0, o_st = 0, o_res = 0, o_sum = 0;
+  size_t total = 0;
+};
+
+size_t align256(size_t x) { return (x + 255) / 256 * 256; }
+
+bool make_plan(int64_t m, int64_t n, int k, int p, int q, int prec, Plan* pl) {
+  (void)q;
+  if (m < 1 || n < 1 || k < 1 || p < 0) return false;
+  const int64_t ell = (int64_t)k + p;
+  if (ell > std::min(m, n) || ell > 256) return false;
+  if (prec < P_F64 || prec > P_BF16X3) return false;
+  pl->mm = std::max(m, n);
+  pl->nn = std::min(m, n);
+  pl->ell = (int)ell;
+  pl->ellp = pad_ell((int)ell);
+  pl->prec = prec;
+  pl->ldm = round_up(pl->mm, 64);
+  pl->ldn = round_up(pl->nn, 64);
+  pl->ldx = std::max(pl->ldm, pl->ldn);
+  const int es = prec == P_F64 ? 8 : 4;  // path element size
+  // partial tiles: the larger of the two pass orientations (gemm prec for
+  // partial element size: BF16 forms accumulate in FP32 like F32)
+  const int gp = prec == P_F64 ? P_F64 : P_F32;
+  pl->part_elems = std::max(partials_capacity(pl->mm, pl->nn, pl->ellp, gp),
+                            partials_capacity(pl->nn, pl->mm, pl->ellp, gp));
+  pl->xsplits = std::max(xty_splits(pl->mm, pl->ell), xty_splits(pl->nn, pl->ell));
+  const size_t l2 = (size_t)ell * ell * 8;
+  size_t off = 0;
+  auto take = [&](size_t bytes) {
+    const size_t o = off;
+    off += align256(bytes);
+    return o;
+  };
+  pl->o_wop = take((size_t)pl->ellp * pl->ldn * es);
+  pl->o_qop = take((size_t)pl->ellp * pl->ldm * es);
+  pl->o_part = take((size_t)pl->part_elems * (prec == P_F64 ? 8 : 4));
+  pl->o_x0 = take((size_t)pl->ellp * pl->ldx * 8);
+  pl->o_x1 = take((size_t)pl->ellp * pl->ldx * 8);
+  pl->o_q1 = take((size_t)pl->ellp * pl->ldm * 8);
+  pl->o_q2 = take((size_t)pl->ellp * pl->ldn * 8);
+  pl->o_xp = take((size_t)pl->xsplits * l2);
+  pl->o_g = take(l2);
+  pl->o_r = take(2 * l2);
+  pl->o_rinv = take(l2);
+  pl->o_core = take(l2);
+  pl->o_qt = take(l2);
+  pl->o_rt = take(l2);
+  pl->o_qw = take(2 * l2);
+  pl->o_tt = take(l2);
+  pl->o_piv = take((size_t)ell * 4);
+  pl->o_st = take(kMaxQr * 4);
+  pl->o_res = take((size_t)residual_blocks(pl->mm) * 2 * 8);
+  pl->o_sum = take(2 * 8);
+  pl->total = off;
+  return true;
+}
+
+}  // namespace
+
+// ---------------------------------------------------------------------------
+// context
+struct Job;
+
+struct corutv_ctx {
+  int device = 0;
+  int num_cu = 256;
+  std::vector<hipStream_t> streams;
+  char* ws = nullptr;
+  size_t ws_bytes = 0;
+  std::atomic<bool> poisoned{false};
+  std::mutex run_mu;  // serializes blocking calls on streams[0]
+  // serving
+  int max_queue = 4096;
+  std::mutex mu;
+  std::condition_variable cv;
+  std::deque<Job*> queue;
+  std::map<uint64_t, Job*> jobs;
+  uint64_t next_ticket = 1;
+  bool stop = false;
+  std::thread sched;
+  bool sched_started = false;
+  std::vector<int> slot_busy;
+  std::vector<std::pair<size_t, size_t>> arena;  // allocated [off, off+size)
+  int* host_status = nullptr;                    // pinned, kMaxQr per slot
+};
+
+namespace {
+
+#define HIPOK(expr)                                  \
+  do {                                               \
+    hipError_t e_ = (expr);                          \
+    if (e_ != hipSuccess) return CORUTV_E_DEVICE;    \
+  } while (0)
+
+bool mat_ok(const corutv_mat* a) {
+  if (!a || !a->ptr || a->rows < 1 || a->cols < 1) return false;
+  if (a->dtype != CORUTV_F64 && a->dtype != CORUTV_F32) return false;
+  if (a->layout == CORUTV_COL_MAJOR) return a->ld >= a->rows;
+  if (a->layout == CORUTV_ROW_MAJOR) return a->ld >= a->cols;
+  return false;
+}
+
+MatOut out_of(const corutv_mat* a) {
+  MatOut o;
+  o.ptr = a->ptr;
+  o.ld = a->ld;
+  o.dtype = a->dtype;
+  o.layout = a->layout;
+  return o;
+}
+
+// Arguments of one decomposition, validated.
+struct DecArgs {
+  corutv_mat A, U, V;
+  double* T = nullptr;
+  int64_t ldt = 0;
+  int32_t* piv = nullptr;
+  int k = 0, p = 0, q = 0;
+  uint64_t seed = 0;
+  uint32_t sub = 0;
+  corutv_opts opts{};
+};
+
+int validate(const DecArgs& d) {
+  if (!mat_ok(&d.A) || !mat_ok(&d.U) || !mat_ok(&d.V) || !d.T) return CORUTV_E_INVAL;
+  const int64_t m = d.A.rows, n = d.A.cols;
+  const int64_t ell = (int64_t)d.k + d.p;
+  if (d.k < 1 || d.p < 0 || d.q < 0 || d.q > 30) return CORUTV_E_INVAL;
+  if (ell > std::min(m, n) || ell > 256) return CORUTV_E_INVAL;
+  if (d.U.rows != m || d.U.cols != ell || d.V.rows != n || d.V.cols != ell) return CORUTV_E_INVAL;
+  if (d.ldt < ell) return CORUTV_E_INVAL;
+  const int prec = d.opts.prec;
+  if (prec < P_F64 || prec > P_BF16X3) return CORUTV_E_INVAL;
+  if (prec == P_F64 && d.A.dtype != CORUTV_F64) return CORUTV_E_INVAL;
+  if (prec != P_F64 && d.A.dtype != CORUTV_F32) return CORUTV_E_INVAL;
+  if (d.opts.tri < CORUTV_TRI_AUTO || d.opts.tri > CORUTV_TRI_LOWER) return CORUTV_E_INVAL;
+  return CORUTV_OK;
+}
+
+struct Enqueued {
+  int nqr = 0;
+  int* dev_status = nullptr;
+  double* dev_sum = nullptr;
+  int transposed = 0;
+  int tri = CORUTV_TRI_UPPER;
+  int passes = 0;
+};
+
+// Thin QR of the sketch held in the stream-K partials `pp` (rows x ell):
+// CholeskyQR2 with FP64 Gram and Cholesky, Householder after a breakdown.
+// Outputs: q64 (FP64, may be scratch) and, for the F32 path, q32.
+hipError_t qr_from_partials(const Plan& pl, char* ws, const Partials& pp, int64_t rows, int64_t ld,
+                            double* q64, float* q32, int* st, hipStream_t s) {
+  const int ell = pl.ell;
+  double* x0 = (double*)(ws + pl.o_x0);
+  double* x1 = (double*)(ws + pl.o_x1);
+  double* xp = (double*)(ws + pl.o_xp);
+  double* G = (double*)(ws + pl.o_g);
+  double* R = (double*)(ws + pl.o_r);
+  double* Ri = (double*)(ws + pl.o_rinv);
+  const int64_t l2 = (int64_t)ell * ell;
+  const int splits = xty_splits(rows, ell);
+  hipError_t e;
+  if ((e = launch_sum_partials(pp, ell, pl.ellp, x0, nullptr, ld, s)) != hipSuccess) return e;
+  if ((e = launch_xty(x0, ld, x0, ld, rows, ell, xp, splits, nullptr, s)) != hipSuccess) return e;
+  if ((e = launch_reduce(xp, splits, l2, G, nullptr, s)) != hipSuccess) return e;
+  if ((e = launch_chol(G, ell, R, Ri, st, nullptr, s)) != hipSuccess) return e;
+  MatOut ox1;
+  ox1.ptr = x1;
+  ox1.ld = ld;
+  if ((e = launch_rowmat(x0, ld, rows, ell, Ri, ell, nullptr, ox1, 1, MatOut(), 0, st, s)) != hipSuccess)
+    return e;
+  if ((e = launch_xty(x1, ld, x1, ld, rows, ell, xp, splits, st, s)) != hipSuccess) return e;
+  if ((e = launch_reduce(xp, splits, l2, G, st, s)) != hipSuccess) return e;
+  if ((e = launch_chol(G, ell, R, Ri, st, st, s)) != hipSuccess) return e;
+  MatOut o1, o2;
+  o1.ptr = q64;
+  o1.ld = ld;
+  if (q32) {
+    o2.ptr = q32;
+    o2.ld = ld;
+    o2.dtype = CORUTV_F32;
+  }
+  if ((e = launch_rowmat(x1, ld, rows, ell, Ri, ell, nullptr, o1, 1, o2, 1, st, s)) != hipSuccess)
+    return e;
+  return launch_householder_qr(x0, ld, rows, ell, x1, ld, q64, ld, q32, ld, nullptr, st, s);
+}
+
+// Enqueue a whole decomposition on stream s using the workspace at ws.
+int enqueue_decompose(corutv_ctx* ctx, const Plan& pl, char* ws, const DecArgs& d, hipStream_t s,
+                      Enqueued* out) {
+  const int64_t m = d.A.rows, n = d.A.cols;
+  const int ell = pl.ell, ellp = pl.ellp;
+  const int prec = d.opts.prec;
+  const bool f64 = prec == P_F64;
+  if (prec == P_BF16 || prec == P_BF16X3) return CORUTV_E_INVAL;  // not in this build yet
+  const bool transposed = m < n;
+  const int64_t mm = pl.mm, nn = pl.nn;
+  // big row-major view of A
+  const bool a_col = d.A.layout == CORUTV_COL_MAJOR;
+  const int64_t Rb = a_col ? n : m, Cb = a_col ? m : n;
+  // problem matrix P = A (or A^T when transposed); P X is trans tA on the big view
+  const int tA = (a_col ? 1 : 0) ^ (transposed ? 1 : 0);
+  const int tAt = 1 - tA;
+  int tri = d.opts.tri;
+  if (tri == CORUTV_TRI_AUTO) tri = transposed ? CORUTV_TRI_LOWER : CORUTV_TRI_UPPER;
+  // the oriented problem factors P with its own triangle; transposing back flips it
+  const bool lower_inner = transposed ? (tri == CORUTV_TRI_UPPER) : (tri == CORUTV_TRI_LOWER);
+
+  void* wop = ws + pl.o_wop;  // nn x ellp, path dtype
+  void* qop = ws + pl.o_qop;  // mm x ellp, path dtype
+  void* part = ws + pl.o_part;
+  double* q1 = (double*)(ws + pl.o_q1);
+  double* q2 = (double*)(ws + pl.o_q2);
+  double* x0 = (double*)(ws + pl.o_x0);
+  double* x1 = (double*)(ws + pl.o_x1);
+  double* xp = (double*)(ws + pl.o_xp);
+  double* core = (double*)(ws + pl.o_core);
+  double* qt = (double*)(ws + pl.o_qt);
+  double* rt = (double*)(ws + pl.o_rt);
+  double* qw = (double*)(ws + pl.o_qw);
+  double* tt = (double*)(ws + pl.o_tt);
+  int32_t* piv = (int32_t*)(ws + pl.o_piv);
+  int* st = (int*)(ws + pl.o_st);
+  const int64_t ldm = pl.ldm, ldn = pl.ldn;
+  const int es = f64 ? 8 : 4;
+
+  HIPOK(launch_fill_int(st, kMaxQr, 0, s));
+  // padding columns of the pass operands must read as zero
+  HIPOK(hipMemsetAsync(wop, 0, (size_t)ellp * ldn * es, s));
+  if (!f64) HIPOK(hipMemsetAsync(qop, 0, (size_t)ellp * ldm * es, s));
+  HIPOK(hipMemsetAsync(q1, 0, (size_t)ellp * ldm * 8, s));
+  HIPOK(hipMemsetAsync(q2, 0, (size_t)ellp * ldn * 8, s));
+  // F64 path: the FP64 bases are the pass operands themselves
+  const void* qsrc = f64 ? (const void*)q1 : qop;
+  const void* wsrc = f64 ? (const void*)q2 : wop;
+
+  int nqr = 0;
+  Partials pp;
+  auto passA = [&](const void* opnd) {  // P X, X nn x ell -> mm x ell
+    return launch_sketch(prec, tA, d.A.ptr, d.A.ld, Rb, Cb, opnd, ldn, ellp, part, pl.part_elems, &pp,
+                         ctx->num_cu, s);
+  };
+  auto passAt = [&](const void* opnd) {  // P^T Y, Y mm x ell -> nn x ell
+    return launch_sketch(prec, tAt, d.A.ptr, d.A.ld, Rb, Cb, opnd, ldm, ellp, part, pl.part_elems, &pp,
+                         ctx->num_cu, s);
+  };
+  // Omega (nn x ell), then Q1 = qf(P Omega)
+  HIPOK(launch_omega(nn, ell, ellp, d.seed, d.sub, f64 ? (double*)wop : nullptr,
+                     f64 ? nullptr : (float*)wop, ldn, s));
+  HIPOK(passA(wop));
+  HIPOK(qr_from_partials(pl, ws, pp, mm, ldm, q1, f64 ? nullptr : (float*)qop, st + nqr++, s));
+  for (int it = 0; it < d.q; ++it) {
+    // W = qf(P^T Q1); Q1 = qf(P W)
+    HIPOK(passAt(qsrc));
+    HIPOK(qr_from_partials(pl, ws, pp, nn, ldn, q2, f64 ? nullptr : (float*)wop, st + nqr++, s));
+    HIPOK(passA(wsrc));
+    HIPOK(qr_from_partials(pl, ws, pp, mm, ldm, q1, f64 ? nullptr : (float*)qop, st + nqr++, s));
+  }
+  // Z = P^T Q1; Q2 = qf(Z)
+  HIPOK(passAt(qsrc));
+  HIPOK(qr_from_partials(pl, ws, pp, nn, ldn, q2, f64 ? nullptr : (float*)wop, st + nqr++, s));
+  // core D = Q1^T (P Q2)
+  HIPOK(passA(wsrc));
+  HIPOK(launch_sum_partials(pp, ell, ellp, x0, nullptr, ldm, s));
+  const int sp = xty_splits(mm, ell);
+  HIPOK(launch_xty(q1, ldm, x0, ldm, mm, ell, xp, sp, nullptr, s));
+  HIPOK(launch_reduce(xp, sp, (int64_t)ell * ell, core, nullptr, s));
+  // QRCP of D (upper) or of D^T (lower)
+  HIPOK(launch_qrcp(core, ell, lower_inner ? 1 : 0, ell, qt, rt, piv, qw, s));
+  // lifts in the oriented problem: Uo (mm x ell), Vo (nn x ell), To
+  //   upper: Uo = Q1 Qt, To = R, Vo = Q2[:, piv]
+  //   lower: Uo = Q1[:, piv], To = R^T, Vo = Q2 Qt
+  const corutv_mat* Udst = transposed ? &d.V : &d.U;
+  const corutv_mat* Vdst = transposed ? &d.U : &d.V;
+  MatOut ou = out_of(Udst), ov = out_of(Vdst);
+  MatOut u64, v64;
+  const bool want_err = d.opts.want_err != 0;
+  if (want_err) {  // FP64 copies for the residual
+    u64.ptr = x0;
+    u64.ld = ldm;
+    v64.ptr = x1;
+    v64.ld = ldn;
+  }
+  if (!lower_inner) {
+    HIPOK(launch_rowmat(q1, ldm, mm, ell, qt, ell, nullptr, ou, 0, u64, 0, nullptr, s));
+    HIPOK(launch_rowmat(q2, ldn, nn, ell, nullptr, 0, piv, ov, 0, v64, 0, nullptr, s));
+  } else {
+    HIPOK(launch_rowmat(q1, ldm, mm, ell, nullptr, 0, piv, ou, 0, u64, 0, nullptr, s));
+    HIPOK(launch_rowmat(q2, ldn, nn, ell, qt, ell, nullptr, ov, 0, v64, 0, nullptr, s));
+  }
+  // To (oriented) into tt; user T = To (not transposed) or To^T (transposed)
+  HIPOK(launch_copy_tri(rt, ell, lower_inner ? 1 : 0, lower_inner ? 0 : 1, tt, ell, s));
+  const bool t_lower_user = transposed ? !lower_inner : lower_inner;
+  HIPOK(launch_copy_tri(tt, ell, transposed ? 1 : 0, t_lower_user ? 0 : 1, d.T, d.ldt, s));
+  if (d.piv) HIPOK(hipMemcpyAsync(d.piv, piv, (size_t)ell * 4, hipMemcpyDeviceToDevice, s));
+  int passes = 2 * d.q + 3;
+  double* sum = (double*)(ws + pl.o_sum);
+  if (want_err) {
+    // residual of P ~ Uo To Vo^T on the big row-major view of A:
+    //   tA == 0: big = P, rows mm:  B = Uo To,   V = Vo
+    //   tA == 1: big = P^T, rows nn: B = Vo To^T, V = Uo
+    double* res = (double*)(ws + pl.o_res);
+    double* bm = (double*)(ws + pl.o_q1);  // Q1 no longer needed
+    double* tmat = (double*)(ws + pl.o_g);
+    MatOut ob;
+    ob.ptr = bm;
+    if (tA == 0) {
+      ob.ld = ldm;
+      HIPOK(launch_rowmat(x0, ldm, mm, ell, tt, ell, nullptr, ob, 0, MatOut(), 0, nullptr, s));
+      HIPOK(launch_residual(d.A.ptr, d.A.dtype, d.A.ld, Rb, Cb, bm, ldm, x1, ldn, ell, res, s));
+    } else {
+      ob.ld = ldn;
+      HIPOK(launch_copy_tri(tt, ell, 1, lower_inner ? 1 : 0, tmat, ell, s));  // To^T
+      HIPOK(launch_rowmat(x1, ldn, nn, ell, tmat, ell, nullptr, ob, 0, MatOut(), 0, nullptr, s));
+      HIPOK(launch_residual(d.A.ptr, d.A.dtype, d.A.ld, Rb, Cb, bm, ldn, x0, ldm, ell, res, s));
+    }
+    HIPOK(launch_reduce(res, residual_blocks(mm), 2, sum, nullptr, s));
+    passes += 1;
+  }
+  out->nqr = nqr;
+  out->dev_status = st;
+  out->dev_sum = want_err ? sum : nullptr;
+  out->transposed = transposed;
+  out->tri = t_lower_user ? CORUTV_TRI_LOWER : CORUTV_TRI_UPPER;
+  out->passes = passes;
+  return CORUTV_OK;
+}
+
+int finish_info(const Enqueued& eq, const int* hst, const double* hsum, corutv_info* info) {
+  int fallbacks = 0, numeric = 0;
+  for (int i = 0; i < eq.nqr; ++i) {
+    if (hst[i] & 2) numeric = 1;
+    if ((hst[i] & 3) == 1) ++fallbacks;
+  }
+  if (info) {
+    info->ell = 0;
+    info->transposed = eq.transposed;
+    info->tri = eq.tri;
+    info->qr_fallbacks = fallbacks;
+    info->passes = eq.passes;
+    info->rel_err = -1.0;
+    info->a_fro = -1.0;
+    if (hsum) {
+      info->a_fro = std::sqrt(hsum[1]);
+      info->rel_err = hsum[1] > 0 ? std::sqrt(hsum[0] / hsum[1]) : 0.0;
+    }
+  }
+  if (numeric) return CORUTV_E_NUMERIC;
+  if (hsum && !(std::isfinite(hsum[0]) && std::isfinite(hsum[1]))) return CORUTV_E_NUMERIC;
+  return CORUTV_OK;
+}
+
+int guard(corutv_ctx* ctx) {
+  if (!ctx) return CORUTV_E_INVAL;
+  if (ctx->poisoned.load()) return CORUTV_E_DEVICE;
+  if (hipSetDevice(ctx->device) != hipSuccess) return CORUTV_E_DEVICE;
+  return CORUTV_OK;
+}
+
+int poison(corutv_ctx* ctx) {
+  ctx->poisoned.store(true);
+  return CORUTV_E_DEVICE;
+}
+
+}  // namespace
+
+// ---------------------------------------------------------------------------
+extern "C" {
+
+const char* corutv_strerror(int code) {
+  switch (code) {
+    case CORUTV_OK: return "ok";
+    case CORUTV_PENDING: return "pending";
+    case CORUTV_E_INVAL: return "invalid argument";
+    case CORUTV_E_NOMEM: return "workspace too small";
+    case CORUTV_E_BUSY: return "queue full";
+    case CORUTV_E_NUMERIC: return "non-finite input or unrecoverable factorization";
+    case CORUTV_E_DEVICE: return "device error (context poisoned)";
+    case CORUTV_E_NOTFOUND: return "unknown ticket";
+    default: return "unknown status";
+  }
+}
+
+uint64_t corutv_workspace_bytes(int64_t m, int64_t n, int32_t k, int32_t p, int32_t q, int32_t prec) {
+  Plan pl;
+  if (!make_plan(m, n, k, p, q, prec, &pl)) return 0;
+  return pl.total;
+}
+
+int corutv_create(corutv_ctx** out, const corutv_config* cfg) {
+  if (!out || !cfg) return CORUTV_E_INVAL;
+  *out = nullptr;
+  if (cfg->n_streams < 1 || !cfg->streams || !cfg->workspace) return CORUTV_E_INVAL;
+  if (((uintptr_t)cfg->workspace) % 256 != 0) return CORUTV_E_INVAL;
+  corutv_ctx* c = new (std::nothrow) corutv_ctx();
+  if (!c) return CORUTV_E_NOMEM;
+  c->device = cfg->device;
+  if (hipSetDevice(c->device) != hipSuccess) {
+    delete c;
+    return CORUTV_E_DEVICE;
+  }
+  int cus = 0;
+  if (hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, c->device) == hipSuccess &&
+      cus > 0)
+    c->num_cu = cus;
+  for (int i = 0; i < cfg->n_streams; ++i) c->streams.push_back((hipStream_t)cfg->streams[i]);
+  c->ws = (char*)cfg->workspace;
+  c->ws_bytes = cfg->workspace_bytes;
+  c->max_queue = cfg->max_queue > 0 ? cfg->max_queue : 4096;
+  const int slots = std::max(1, cfg->n_streams - 1);
+  c->slot_busy.assign(slots, 0);
+  if (hipHostMalloc((void**)&c->host_status, sizeof(int) * (kMaxQr + 8) * (slots + 1)) != hipSuccess) {
+    delete c;
+    return CORUTV_E_DEVICE;
+  }
+  *out = c;
+  return CORUTV_OK;
+}
+
+int corutv_decompose(corutv_ctx* ctx, const corutv_mat* A, int32_t k, int32_t p, int32_t q,
+                     uint64_t seed, const corutv_opts* opts, corutv_mat* U, double* T, int64_t ldt,
+                     corutv_mat* V, int32_t* piv, corutv_info* info) {
+  int rc = guard(ctx);
+  if (rc) return rc;
+  if (!A || !U || !V || !opts) return CORUTV_E_INVAL;
+  DecArgs d;
+  d.A = *A;
+  d.U = *U;
+  d.V = *V;
+  d.T = T;
+  d.ldt = ldt;
+  d.piv = piv;
+  d.k = k;
+  d.p = p;
+  d.q = q;
+  d.seed = seed;
+  d.opts = *opts;
+  if ((rc = validate(d)) != CORUTV_OK) return rc;
+  Plan pl;
+  if (!make_plan(A->rows, A->cols, k, p, q, opts->prec, &pl)) return CORUTV_E_INVAL;
+  if (pl.total > ctx->ws_bytes) return CORUTV_E_NOMEM;
+  std::lock_guard<std::mutex> lk(ctx->run_mu);
+  hipStream_t s = ctx->streams[0];
+  hipEvent_t e0, e1;
+  if (hipEventCreate(&e0) != hipSuccess || hipEventCreate(&e1) != hipSuccess) return poison(ctx);
+  hipEventRecord(e0, s);
+  Enqueued eq;
+  rc = enqueue_decompose(ctx, pl, ctx->ws, d, s, &eq);
+  if (rc == CORUTV_E_DEVICE) {
+    hipEventDestroy(e0);
+    hipEventDestroy(e1);
+    return poison(ctx);
+  }
+  if (rc != CORUTV_OK) {
+    hipEventDestroy(e0);
+    hipEventDestroy(e1);
+    return rc;
+  }
+  hipEventRecord(e1, s);
+  int* hst = ctx->host_status;
+  double hsum[2] = {0, 0};
+  if (hipMemcpyAsync(hst, eq.dev_status, sizeof(int) * eq.nqr, hipMemcpyDeviceToHost, s) != hipSuccess)
+    return poison(ctx);
+  if (eq.dev_sum && hipMemcpyAsync(hsum, eq.dev_sum, 16, hipMemcpyDeviceToHost, s) != hipSuccess)
+    return poison(ctx);
+  if (hipStreamSynchronize(s) != hipSuccess) return poison(ctx);
+  float ms = 0.f;
+  hipEventElapsedTime(&ms, e0, e1);
+  hipEventDestroy(e0);
+  hipEventDestroy(e1);
+  rc = finish_info(eq, hst, eq.dev_sum ? hsum : nullptr, info);
+  if (info) {
+    info->gpu_ms = ms;
+    info->ell = pl.ell;
+  }
+  return rc;
+}
+
+int corutv_omega(corutv_ctx* ctx, int64_t n, int32_t ell, uint64_t seed, uint32_t sub, int32_t dtype,
+                 void* out, int64_t ld) {
+  int rc = guard(ctx);
+  if (rc) return rc;
+  if (n < 1 || ell < 1 || !out || ld < n || (dtype != CORUTV_F64 && dtype != CORUTV_F32))
+    return CORUTV_E_INVAL;
+  std::lock_guard<std::mutex> lk(ctx->run_mu);
+  hipStream_t s = ctx->streams[0];
+  HIPOK(launch_omega(n, ell, ell, seed, sub, dtype == CORUTV_F64 ? (double*)out : nullptr,
+                     dtype == CORUTV_F32 ? (float*)out : nullptr, ld, s));
+  if (hipStreamSynchronize(s) != hipSuccess) return poison(ctx);
+  return CORUTV_OK;
+}
+
+int corutv_sketch(corutv_ctx* ctx, const corutv_mat* A, int32_t trans, int32_t prec, const void* X,
+                  int64_t ldx, int32_t ell, void* Y, int64_t ldy) {
+  int rc = guard(ctx);
+  if (rc) return rc;
+  if (!mat_ok(A) || !X || !Y || ell < 1 || ell > 256 || (trans != 0 && trans != 1))
+    return CORUTV_E_INVAL;
+  if (prec != P_F64 && prec != P_F32) return CORUTV_E_INVAL;
+  if ((prec == P_F64) != (A->dtype == CORUTV_F64)) return CORUTV_E_INVAL;
+  const int64_t m = A->rows, n = A->cols;
+  const int64_t klen = trans ? m : n, nout = trans ? n : m;
+  if (ldx < klen || ldy < nout) return CORUTV_E_INVAL;
+  const int ellp = pad_ell(ell);
+  const int es = prec == P_F64 ? 8 : 4;
+  const int64_t ldk = round_up(klen, 64);
+  const bool a_col = A->layout == CORUTV_COL_MAJOR;
+  const int64_t Rb = a_col ? n : m, Cb = a_col ? m : n;
+  const int t = (a_col ? 1 : 0) ^ trans;
+  const int64_t cap = partials_capacity(nout, klen, ellp, prec);
+  const size_t need = align256((size_t)ellp * ldk * es) + align256((size_t)cap * es);
+  if (need > ctx->ws_bytes) return CORUTV_E_NOMEM;
+  std::lock_guard<std::mutex> lk(ctx->run_mu);
+  hipStream_t s = ctx->streams[0];
+  char* xs = ctx->ws;
+  char* part = ctx->ws + align256((size_t)ellp * ldk * es);
+  HIPOK(hipMemsetAsync(xs, 0, (size_t)ellp * ldk * es, s));
+  HIPOK(hipMemcpy2DAsync(xs, ldk * es, X, ldx * es, klen * es, ell, hipMemcpyDeviceToDevice, s));
+  Partials pp;
+  HIPOK(launch_sketch(prec, t, A->ptr, A->ld, Rb, Cb, xs, ldk, ellp, part, cap, &pp, ctx->num_cu, s));
+  HIPOK(launch_sum_partials(pp, ell, ell, prec == P_F64 ? (double*)Y : nullptr,
+                            prec == P_F64 ? nullptr : (float*)Y, ldy, s));
+  if (hipStreamSynchronize(s) != hipSuccess) return poison(ctx);
+  return CORUTV_OK;
+}
+
+int corutv_tsqr(corutv_ctx* ctx, const double* X, int64_t rows, int32_t ell, int64_t ldx, double* Q,
+                int64_t ldq, double* R, int64_t ldr, int32_t* fallback) {
+  int rc = guard(ctx);
+  if (rc) return rc;
+  if (!X || !Q || rows < 1 || ell < 1 || ell > 256 || rows < ell || ldx < rows || ldq < rows)
+    return CORUTV_E_INVAL;
+  if (R && ldr < ell) return CORUTV_E_INVAL;
+  const int64_t ld = round_up(rows, 64);
+  const int ellp = pad_ell(ell);
+  const size_t l2 = (size_t)ell * ell * 8;
+  const int splits = xty_splits(rows, ell);
+  size_t off = 0;
+  auto take = [&](size_t b) {
+    const size_t o = off;
+    off += align256(b);
+    return o;
+  };
+  const size_t o_x0 = take((size_t)ellp * ld * 8), o_x1 = take((size_t)ellp * ld * 8),
+               o_q = take((size_t)ellp * ld * 8), o_xp = take(splits * l2), o_g = take(l2),
+               o_r1 = take(2 * l2), o_r2 = take(2 * l2), o_ri = take(l2), o_rh = take(l2),
+               o_st = take(64);
+  if (off > ctx->ws_bytes) return CORUTV_E_NOMEM;
+  std::lock_guard<std::mutex> lk(ctx->run_mu);
+  hipStream_t s = ctx->streams[0];
+  char* w = ctx->ws;
+  double *x0 = (double*)(w + o_x0), *x1 = (double*)(w + o_x1), *qq = (double*)(w + o_q),
+         *xp = (double*)(w + o_xp), *G = (double*)(w + o_g), *R1 = (double*)(w + o_r1),
+         *R2 = (double*)(w + o_r2), *Ri = (double*)(w + o_ri), *Rh = (double*)(w + o_rh);
+  int* st = (int*)(w + o_st);
+  HIPOK(launch_fill_int(st, 1, 0, s));
+  HIPOK(hipMemcpy2DAsync(x0, ld * 8, X, ldx * 8, rows * 8, ell, hipMemcpyDeviceToDevice, s));
+  const int64_t l2e = (int64_t)ell * ell;
+  HIPOK(launch_xty(x0, ld, x0, ld, rows, ell, xp, splits, nullptr, s));
+  HIPOK(launch_reduce(xp, splits, l2e, G, nullptr, s));
+  HIPOK(launch_chol(G, ell, R1, Ri, st, nullptr, s));
+  MatOut ox1;
+  ox1.ptr = x1;
+  ox1.ld = ld;
+  HIPOK(launch_rowmat(x0, ld, rows, ell, Ri, ell, nullptr, ox1, 1, MatOut(), 0, st, s));
+  HIPOK(launch_xty(x1, ld, x1, ld, rows, ell, xp, splits, st, s));
+  HIPOK(launch_reduce(xp, splits, l2e, G, st, s));
+  HIPOK(launch_chol(G, ell, R2, Ri, st, st, s));
+  MatOut oq;
+  oq.ptr = qq;
+  oq.ld = ld;
+  HIPOK(launch_rowmat(x1, ld, rows, ell, Ri, ell, nullptr, oq, 1, MatOut(), 0, st, s));
+  HIPOK(launch_householder_qr(x0, ld, rows, ell, x1, ld, qq, ld, nullptr, 0, Rh, st, s));
+  int hst = 0;
+  HIPOK(hipMemcpyAsync(&hst, st, 4, hipMemcpyDeviceToHost, s));
+  if (hipStreamSynchronize(s) != hipSuccess) return poison(ctx);
+  if (hst & 2) return CORUTV_E_NUMERIC;
+  const bool fb = (hst & 3) == 1;
+  if (fallback) *fallback = fb ? 1 : 0;
+  HIPOK(hipMemcpy2DAsync(Q, ldq * 8, qq, ld * 8, rows * 8, ell, hipMemcpyDeviceToDevice, s));
+  if (R) {
+    if (fb) {
+      HIPOK(launch_copy_tri(Rh, ell, 0, 1, R, ldr, s));
+    } else {
+      MatOut orr;  // R = R2 R1
+      orr.ptr = R;
+      orr.ld = ldr;
+      HIPOK(launch_rowmat(R2, ell, ell, ell, R1, ell, nullptr, orr, 0, MatOut(), 0, nullptr, s));
+    }
+  }
+  if (hipStreamSynchronize(s) != hipSuccess) return poison(ctx);
+  return CORUTV_OK;
+}
+
+int corutv_qrcp(corutv_ctx* ctx, int32_t ell, const double* D, int64_t ldd, double* Qt, double* R,
+                int32_t* piv) {
+  int rc = guard(ctx);
+  if (rc) return rc;
+  if (ell < 1 || ell > 256 || !D || !Qt || !R || !piv || ldd < ell) return CORUTV_E_INVAL;
+  if ((size_t)2 * ell * ell * 8 > ctx->ws_bytes) return CORUTV_E_NOMEM;
+  std::lock_guard<std::mutex> lk(ctx->run_mu);
+  hipStream_t s = ctx->streams[0];
+  HIPOK(launch_qrcp(D, ldd, 0, ell, Qt, R, piv, (double*)ctx->ws, s));
+  if (hipStreamSynchronize(s) != hipSuccess) return poison(ctx);
+  return CORUTV_OK;
+}
+
+}  // extern "C"
+
+// ---------------------------------------------------------------------------
+// serving: host queue + scheduler thread, slots = streams[1..] (or streams[0])
+struct Job {
+  uint64_t ticket = 0;
+  DecArgs d;
+  Plan pl;
+  enum { QUEUED, RUNNING, DONE } state = QUEUED;
+  int rc = CORUTV_PENDING;
+  corutv_info info{};
+  int slot = -1;
+  size_t off = 0;
+  hipEvent_t e0 = nullptr, e1 = nullptr;
+  Enqueued eq;
+};
+
+namespace {
+
+int* slot_status(corutv_ctx* c, int slot) { return c->host_status + (size_t)(slot + 1) * (kMaxQr + 8); }
+double* slot_sum(corutv_ctx* c, int slot) { return (double*)(slot_status(c, slot) + kMaxQr); }
+
+// first-fit allocation in the workspace; arena kept sorted by offset
+bool arena_alloc(corutv_ctx* c, size_t bytes, size_t* off) {
+  size_t cur = 0;
+  for (size_t i = 0; i <= c->arena.size(); ++i) {
+    const size_t end = i < c->arena.size() ? c->arena[i].first : c->ws_bytes;
+    if (end >= cur && end - cur >= bytes) {
+      c->arena.insert(c->arena.begin() + i, {cur, cur + bytes});
+      *off = cur;
+      return true;
+    }
+    if (i < c->arena.size()) cur = align256(c->arena[i].second);
+  }
+  return false;
+}
+
+void arena_free(corutv_ctx* c, size_t off) {
+  for (size_t i = 0; i < c->arena.size(); ++i)
+    if (c->arena[i].first == off) {
+      c->arena.erase(c->arena.begin() + i);
+      return;
+    }
+}
+
+hipStream_t slot_stream(corutv_ctx* c, int slot) {
+  return c->streams.size() > 1 ? c->streams[1 + slot] : c->streams[0];
+}
+
+// Start the job on a free slot if memory allows (called with c->mu held).
+bool try_start(corutv_ctx* c, Job* j) {
+  int slot = -1;
+  for (size_t i = 0; i < c->slot_busy.size(); ++i)
+    if (!c->slot_busy[i]) {
+      slot = (int)i;
+      break;
+    }
+  if (slot < 0) return false;
+  size_t off = 0;
+  if (!arena_alloc(c, j->pl.total, &off)) return false;
+  hipStream_t s = slot_stream(c, slot);
+  j->slot = slot;
+  j->off = off;
+  c->slot_busy[slot] = 1;
+  j->state = Job::RUNNING;
+  int rc = CORUTV_OK;
+  if (hipEventCreate(&j->e0) != hipSuccess || hipEventCreate(&j->e1) != hipSuccess) rc = CORUTV_E_DEVICE;
+  if (rc == CORUTV_OK) hipEventRecord(j->e0, s);
+  if (rc == CORUTV_OK) rc = enqueue_decompose(c, j->pl, c->ws + off, j->d, s, &j->eq);
+  if (rc == CORUTV_OK) {
+    hipEventRecord(j->e1, s);
+    if (hipMemcpyAsync(slot_status(c, slot), j->eq.dev_status, sizeof(int) * j->eq.nqr,
+                       hipMemcpyDeviceToHost, s) != hipSuccess)
+      rc = CORUTV_E_DEVICE;
+    if (rc == CORUTV_OK && j->eq.dev_sum &&
+        hipMemcpyAsync(slot_sum(c, slot), j->eq.dev_sum, 16, hipMemcpyDeviceToHost, s) != hipSuccess)
+      rc = CORUTV_E_DEVICE;
+    if (rc == CORUTV_OK && hipEventRecord(j->e1, s) != hipSuccess) rc = CORUTV_E_DEVICE;
+  }
+  if (rc != CORUTV_OK) {
+    if (rc == CORUTV_E_DEVICE) c->poisoned.store(true);
+    j->rc = rc;
+    j->state = Job::DONE;
+    c->slot_busy[slot] = 0;
+    arena_free(c, off);
+  }
+  return true;
+}
+
+void finish_job(corutv_ctx* c, Job* j) {
+  float ms = 0.f;
+  hipEventElapsedTime(&ms, j->e0, j->e1);
+  j->rc = finish_info(j->eq, slot_status(c, j->slot), j->eq.dev_sum ? slot_sum(c, j->slot) : nullptr,
+                      &j->info);
+  j->info.gpu_ms = ms;
+  j->info.ell = j->pl.ell;
+  hipEventDestroy(j->e0);
+  hipEventDestroy(j->e1);
+  c->slot_busy[j->slot] = 0;
+  arena_free(c, j->off);
+  j->state = Job::DONE;
+}
+
+void scheduler(corutv_ctx* c) {
+  hipSetDevice(c->device);
+  std::unique_lock<std::mutex> lk(c->mu);
+  for (;;) {
+    bool progress = false;
+    // completions
+    for (auto& kv : c->jobs) {
+      Job* j = kv.second;
+      if (j->state != Job::RUNNING) continue;
+      const hipError_t q = hipEventQuery(j->e1);
+      if (q == hipSuccess) {
+        finish_job(c, j);
+        progress = true;
+      } else if (q != hipErrorNotReady) {
+        c->poisoned.store(true);
+        j->rc = CORUTV_E_DEVICE;
+        j->state = Job::DONE;
+        c->slot_busy[j->slot] = 0;
+        arena_free(c, j->off);
+        progress = true;
+      }
+    }
+    // admissions, in arrival order (the head blocks later requests so that
+    // large requests are not starved)
+    while (!c->queue.empty()) {
+      Job* j = c->queue.front();
+      if (c->poisoned.load()) {
+        j->rc = CORUTV_E_DEVICE;
+        j->state = Job::DONE;
+        c->queue.pop_front();
+        progress = true;
+        continue;
+      }
+      if (!try_start(c, j)) break;
+      c->queue.pop_front();
+      progress = true;
+    }
+    if (progress) c->cv.notify_all();
+    bool running = false;
+    for (auto& kv : c->jobs)
+      if (kv.second->state == Job::RUNNING) running = true;
+    if (c->stop && c->queue.empty() && !running) break;
+    if (running)
+      c->cv.wait_for(lk, std::chrono::microseconds(20));
+    else
+      c->cv.wait(lk, [&] { return c->stop || !c->queue.empty(); });
+  }
+}
+
+}  // namespace
+
+extern "C" {
+
+int corutv_submit(corutv_ctx* ctx, const corutv_request* req, uint64_t* ticket) {
+  int rc = guard(ctx);
+  if (rc) return rc;
+  if (!req || !ticket) return CORUTV_E_INVAL;
+  Job* j = new (std::nothrow) Job();
+  if (!j) return CORUTV_E_NOMEM;
+  j->d.A = req->A;
+  j->d.U = req->U;
+  j->d.V = req->V;
+  j->d.T = req->T;
+  j->d.ldt = req->ldt;
+  j->d.piv = req->piv;
+  j->d.k = req->k;
+  j->d.p = req->p;
+  j->d.q = req->q;
+  j->d.seed = req->seed;
+  j->d.opts = req->opts;
+  if ((rc = validate(j->d)) != CORUTV_OK ||
+      !make_plan(req->A.rows, req->A.cols, req->k, req->p, req->q, req->opts.prec, &j->pl)) {
+    delete j;
+    return rc ? rc : CORUTV_E_INVAL;
+  }
+  if (j->pl.total > ctx->ws_bytes) {
+    delete j;
+    return CORUTV_E_NOMEM;
+  }
+  std::lock_guard<std::mutex> lk(ctx->mu);
+  if ((int)ctx->queue.size() >= ctx->max_queue) {
+    delete j;
+    return CORUTV_E_BUSY;
+  }
+  if (!ctx->sched_started) {
+    ctx->sched = std::thread(scheduler, ctx);
+    ctx->sched_started = true;
+  }
+  j->ticket = ctx->next_ticket++;
+  ctx->jobs[j->ticket] = j;
+  ctx->queue.push_back(j);
+  *ticket = j->ticket;
+  ctx->cv.notify_all();
+  return CORUTV_OK;
+}
+
+int corutv_poll(corutv_ctx* ctx, uint64_t ticket, corutv_info* info) {
+  if (!ctx) return CORUTV_E_INVAL;
+  std::lock_guard<std::mutex> lk(ctx->mu);
+  auto it = ctx->jobs.find(ticket);
+  if (it == ctx->jobs.end()) return CORUTV_E_NOTFOUND;
+  Job* j = it->second;
+  if (j->state != Job::DONE) return CORUTV_PENDING;
+  const int rc = j->rc;
+  if (info) *info = j->info;
+  ctx->jobs.erase(it);
+  delete j;
+  return rc;
+}
+
+int corutv_wait(corutv_ctx* ctx, uint64_t ticket, corutv_info* info) {
+  if (!ctx) return CORUTV_E_INVAL;
+  {
+    std::unique_lock<std::mutex> lk(ctx->mu);
+    auto it = ctx->jobs.find(ticket);
+    if (it == ctx->jobs.end()) return CORUTV_E_NOTFOUND;
+    Job* j = it->second;
+    ctx->cv.wait(lk, [&] { return j->state == Job::DONE; });
+  }
+  return corutv_poll(ctx, ticket, info);
+}
+
+int corutv_cancel(corutv_ctx* ctx, uint64_t ticket) {
+  if (!ctx) return CORUTV_E_INVAL;
+  std::lock_guard<std::mutex> lk(ctx->mu);
+  auto it = ctx->jobs.find(ticket);
+  if (it == ctx->jobs.end()) return CORUTV_E_NOTFOUND;
+  Job* j = it->second;
+  if (j->state != Job::QUEUED) return CORUTV_E_BUSY;
+  for (auto q = ctx->queue.begin(); q != ctx->queue.end(); ++q)
+    if (*q == j) {
+      ctx->queue.erase(q);
+      break;
+    }
+  ctx->jobs.erase(it);
+  delete j;
+  return CORUTV_OK;
+}
+
+int corutv_destroy(corutv_ctx* ctx) {
+  if (!ctx) return CORUTV_E_INVAL;
+  {
+    std::lock_guard<std::mutex> lk(ctx->mu);
+    ctx->stop = true;
+    ctx->cv.notify_all();
+  }
+  if (ctx->sched_started) ctx->sched.join();
+  for (auto& kv : ctx->jobs) delete kv.second;
+  ctx->jobs.clear();
+  if (ctx->host_status) hipHostFree(ctx->host_status);
+  delete ctx;
+  return CORUTV_OK;
+}
+
+}  // extern "C"
+
+extern "C" int corutv_rpca(corutv_ctx* ctx, const corutv_mat* M, double lambda, int32_t k, int32_t p,
+                           int32_t q, int32_t max_iter, double tol, uint64_t seed,
+                           const corutv_opts* opts, corutv_mat* L, corutv_mat* S,
+                           corutv_rpca_info* info) {
+  (void)ctx; (void)M; (void)lambda; (void)k; (void)p; (void)q; (void)max_iter; (void)tol;
+  (void)seed; (void)opts; (void)L; (void)S; (void)info;
+  return CORUTV_E_INVAL;
+}

@@ -1,0 +1,145 @@
+// Internal declarations of libcorutv (not part of the C ABI).
+#pragma once
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+#include <cstddef>
+
+#include "../../include/corutv.h"
+
+namespace corutv {
+
+// Skinny matrices (m x l, n x l) live column-major as [ellp][ld] with the
+// column count padded to a multiple of 16 (MFMA tile) and zero padding.
+constexpr int kPadL = 16;
+__host__ __device__ inline int pad_ell(int ell) { return (ell + kPadL - 1) / kPadL * kPadL; }
+inline int64_t round_up(int64_t x, int64_t m) { return (x + m - 1) / m * m; }
+
+// Arithmetic of one pass over A.
+enum Prec { P_F64 = 0, P_F32 = 1, P_BF16 = 2, P_BF16X3 = 3 };
+
+// Geometry of the partial tiles a stream-K sketch pass writes.  The pass
+// splits the reduction into 8 chunks (one per XCD); inside a chunk the
+// (tile, k-block) units are divided evenly over gx workgroups.  Partial tile
+// (x, j, slot) holds workgroup j of chunk x's contribution to output tile
+// (first tile of j) + slot, laid out [ellp][tw].
+struct Partials {
+  void* ptr = nullptr;    // float (F32/BF16 forms) or double (F64)
+  int elem = 4;           // bytes per element
+  int ellp = 0;
+  int tw = 0;             // output rows per tile
+  int tiles = 0;
+  int nkx = 0;            // k-blocks per chunk
+  int gx = 0;             // workgroups per chunk
+  int maxslot = 0;
+  int64_t n = 0;          // output length
+};
+
+
+// ---- launchers (return hipError_t) ----------------------------------------
+hipError_t launch_omega(int64_t n, int ell, int ellp, uint64_t seed, uint32_t sub, double* out64,
+                        float* out32, int64_t ld, hipStream_t st);
+
+// One pass over a row-major R x C matrix: trans = 0 -> out (R x l) = A S^T-operand,
+// i.e. Y = A W with W (C x l) stored as S[c*lds + j]; trans = 1 -> Z (C x l) = A^T Q
+// with Q (R x l) stored as S[c*lds + i].  Writes partial tiles into `part`
+// (whose geometry is filled in here).
+// part_elems: capacity of part_buf in elements; the grid shrinks to fit.
+hipError_t launch_sketch(int prec, int trans, const void* A, int64_t lda, int64_t R, int64_t C,
+                         const void* S, int64_t lds, int ellp, void* part_buf, int64_t part_elems,
+                         Partials* part, int num_cu, hipStream_t st);
+// Capacity (elements) that covers every grid launch_sketch may pick on a
+// 256-CU device.
+int64_t partials_capacity(int64_t n_out, int64_t k_len, int ellp, int prec);
+
+// out64[c*ld + i] = sum of the partial tiles for row i (i < n, c < ell); zero for
+// ell <= c < ncols.  Optionally also out32 (float copy).
+hipError_t launch_sum_partials(const Partials& p, int ell, int ncols, double* out64, float* out32,
+                               int64_t ld, hipStream_t st);
+
+// Row-block products.  xty: part[b] = sum over the rows of split b of
+// Xa[i,:]^T Xb[i,:] (ell x ell, column-major); the splits are summed in order
+// by launch_reduce.  Xa, Xb column-major FP64 with leading dims.
+int xty_splits(int64_t rows, int ell);
+hipError_t launch_xty(const double* Xa, int64_t lda, const double* Xb, int64_t ldb, int64_t rows,
+                      int ell, double* part, int splits, const int* skip, hipStream_t st);
+hipError_t launch_reduce(const double* part, int splits, int64_t elems, double* out,
+                         const int* skip, hipStream_t st);
+
+// Dense output descriptor used by the row-matrix kernel.
+struct MatOut {
+  void* ptr = nullptr;
+  int64_t ld = 0;
+  int dtype = CORUTV_F64;
+  int layout = CORUTV_COL_MAJOR;
+};
+// Y[i, :] = X[i, :] B (rows x ell times ell x ell, B column-major FP64 with
+// ldb; X column-major FP64).  When `perm` is given, Y[:, j] = X[:, perm[j]]
+// instead (B unused).  Outputs: up to two destinations (may be null).  Rows
+// >= rows are not written; columns ell..ellp-1 of FP64 skinny destinations
+// (dtype F64/F32 column-major with pad = 1) are zero-filled.
+hipError_t launch_rowmat(const double* X, int64_t ldx, int64_t rows, int ell, const double* B,
+                         int64_t ldb, const int32_t* perm, MatOut o1, int pad1, MatOut o2, int pad2,
+                         const int* skip, hipStream_t st);
+
+// Cholesky G = R^T R of an SPD ell x ell FP64 matrix (column-major, ld ell)
+// and the inverse of R, both written column-major (ld ell).  R must have room
+// for 2*ell*ell doubles (the second half is scratch for ell > 128).  status gets
+// bit 1 on breakdown (non-positive or non-finite pivot) and bit 2 when the
+// input holds NaN/Inf.  Runs only when *skip == 0 (skip may be null).
+hipError_t launch_chol(const double* G, int ell, double* R, double* Rinv, int* status,
+                       const int* skip, hipStream_t st);
+
+// Householder thin QR of X (rows x ell, column-major FP64) -> Q (diag R >= 0,
+// FP64 and optionally a float copy), R (nullable); runs only when
+// (*status & 3) == 1 (a Cholesky breakdown on finite data).  work: rows x ell.
+hipError_t launch_householder_qr(const double* X, int64_t ldx, int64_t rows, int ell, double* work,
+                                 int64_t ldw, double* Q, int64_t ldq, float* Q32, int64_t ldq32,
+                                 double* R, const int* status, hipStream_t st);
+hipError_t launch_fill_int(int* p, int n, int v, hipStream_t st);
+
+// Column-pivoted QR of an ell x ell FP64 matrix (column-major, ldd; trans
+// reads D^T).  Qt, R column-major ld ell; piv int32.  work: 2*ell*ell doubles.
+hipError_t launch_qrcp(const double* D, int64_t ldd, int trans, int ell, double* Qt, double* R,
+                       int32_t* piv, double* work, hipStream_t st);
+
+// Copy an ell x ell FP64 column-major matrix (optionally transposed, with
+// zeroed strict lower (upper=1) or strict upper (upper=0) part) to dst.
+hipError_t launch_copy_tri(const double* src, int ell, int trans, int upper, double* dst, int64_t ldd,
+                           hipStream_t st);
+
+// Residual: part[b] = { sum (A - B V^T)^2, sum A^2 } over row block b, with
+// A row-major R x C (dtype F64/F32), B (R x ell) and V (C x ell) column-major
+// FP64 skinny matrices.  Then summed in order.
+int residual_blocks(int64_t R);
+hipError_t launch_residual(const void* A, int dtype, int64_t lda, int64_t R, int64_t C,
+                           const double* B, int64_t ldb, const double* V, int64_t ldv, int ell,
+                           double* part, hipStream_t st);
+
+// Flag NaN/Inf in a dense matrix (any layout): sets bit 2 of *status.
+hipError_t launch_check_finite(const void* A, int dtype, int64_t rows, int64_t cols, int64_t ld,
+                               int* status, hipStream_t st);
+
+// RPCA elementwise step (see rpca.hip).
+struct RpcaStep {
+  const float* M;
+  float* S;
+  float* Y;
+  float* B;        // next CoR-UTV input (M - S + Y/mu_next)
+  float* Lout;     // nullable dense L
+  int64_t ld;      // column-major leading dimension of M, S, Y, B, L (all same)
+  int64_t m, n;
+  const double* Ub;  // m x ell, column-major, FP64 (U)
+  int64_t ldu;
+  const double* Wt;  // n x ell, column-major FP64: W = V T^T, so L = U(:,1:r) W(:,1:r)^T
+  int64_t ldw;
+  const double* T;   // ell x ell FP64 (for the rank decision)
+  int ell;
+  const double* mu;  // device scalars: mu[0] = mu_j, mu[1] = mu_{j+1}
+  double lambda;
+  double* part;      // per-block residual partials
+};
+int rpca_blocks(int64_t m, int64_t n);
+hipError_t launch_rpca_step(const RpcaStep& a, hipStream_t st);
+
+}  // namespace corutv

@@ -1,0 +1,389 @@
+// Passes over the dense matrix A (Sec. 3.1 eqs. 4, 5, 7; Algorithm 1 power
+// loop): Y = A W (m x n times n x l) and Z = A^T Q (n x m times m x l), the
+// O(mnl) part of CoR-UTV.  The paper counts 2mnl flops per product and 2q+3
+// passes over A (Sec. 3.2); each pass here streams A from HBM exactly once.
+//
+// Design (MI355X / gfx950):
+//  * A is row-major R x C with leading dimension lda (a column-major matrix is
+//    the row-major view of its transpose, so both orientations reduce to the
+//    two kernels below: trans = 0 contracts over C, trans = 1 over R).
+//  * MFMA 16x16x4 (FP32 or FP64).  The matrix-core A operand is the skinny
+//    matrix (l rows, staged in LDS, shared by the four waves of a workgroup);
+//    the B operand is A itself, loaded straight from HBM into registers with
+//    16-byte vector loads (each element of A is used by exactly one lane).
+//    The k index of each MFMA step is permuted so that a lane's four
+//    consecutive k values come from one contiguous vector load.
+//  * Output tile: all l (padded to 16) sketch columns x TW output rows, so A
+//    is read once per pass.
+//  * Work split: stream-K.  The reduction range is cut into 8 chunks, one per
+//    XCD (workgroup w runs on XCD w mod 8), so each XCD's L2 holds only its
+//    1/8 of the skinny operand; inside a chunk the (tile, k-block) units are
+//    divided evenly over a persistent grid, so every CU gets the same work.
+//    Each workgroup writes one partial tile per output tile it touches; the
+//    consumer kernel sums them in a fixed order, so results are
+//    deterministic (no atomics).
+#include "internal.hpp"
+
+namespace corutv {
+namespace {
+
+typedef float f4 __attribute__((ext_vector_type(4)));
+typedef float f2 __attribute__((ext_vector_type(2)));
+typedef double d4 __attribute__((ext_vector_type(4)));
+typedef double d2 __attribute__((ext_vector_type(2)));
+
+template <typename T>
+struct Mma;
+template <>
+struct Mma<float> {
+  using acc = f4;
+  using v16 = f4;  // 16-byte vector
+  static __device__ __forceinline__ acc op(float a, float b, acc c) {
+    return __builtin_amdgcn_mfma_f32_16x16x4f32(a, b, c, 0, 0, 0);
+  }
+};
+template <>
+struct Mma<double> {
+  using acc = d4;
+  using v16 = d2;
+  static __device__ __forceinline__ acc op(double a, double b, acc c) {
+    return __builtin_amdgcn_mfma_f64_16x16x4f64(a, b, c, 0, 0, 0);
+  }
+};
+
+struct SketchArgs {
+  const void* A;
+  int64_t lda;
+  int64_t N;  // output length (rows of Y / Z)
+  int64_t K;  // reduction length
+  const void* S;
+  int64_t lds;
+  void* P;
+  int tiles, nk, nkx, gx, maxslot;
+  int vec;  // A rows 16-byte aligned: vector loads allowed
+};
+
+template <typename T, int MB, bool TRANS, int NB>
+__global__ void __launch_bounds__(256) sketch_kernel(SketchArgs a) {
+  using M = Mma<T>;
+  using acc_t = typename M::acc;
+  using v16 = typename M::v16;
+  constexpr int E16 = 16 / sizeof(T);   // elements per 16-byte vector
+  constexpr int KC = 128 / sizeof(T);   // k values per LDS stage
+  constexpr int KG = KC / 16;           // 16-k MFMA groups per stage
+  constexpr int ELLP = MB * 16;
+  constexpr int LDK = KC + E16;         // LDS row stride (one vector of pad)
+  constexpr int TW = 64 * NB;           // output rows per workgroup tile
+  constexpr int VPR = KC / E16;         // vectors per skinny row per stage
+  constexpr int SPASS = (ELLP * VPR + 255) / 256;
+  __shared__ __attribute__((aligned(16))) T lds_s[2][ELLP * LDK];
+
+  const int tid = threadIdx.x;
+  const int lane = tid & 63, wave = tid >> 6;
+  const int g = lane >> 4, qd = lane & 15;
+  const int x = blockIdx.x & 7;
+  const int jw = blockIdx.x >> 3;
+  const T* __restrict__ A = (const T*)a.A;
+  const T* __restrict__ S = (const T*)a.S;
+  T* __restrict__ P = (T*)a.P;
+  const int64_t U = (int64_t)a.tiles * a.nkx;
+  int64_t u = (int64_t)jw * U / a.gx;
+  const int64_t uend = (int64_t)(jw + 1) * U / a.gx;
+  const int tfirst = (int)(u / a.nkx);
+  int iter = 0;  // LDS buffer parity, continuous across tiles
+
+  while (u < uend) {
+    const int t = (int)(u / a.nkx);
+    const int kb0 = (int)(u % a.nkx);
+    const int kb1 = (int)min((int64_t)a.nkx, kb0 + (uend - u));
+    const int gk0 = x * a.nkx + kb0;
+    const int gk1 = min(x * a.nkx + kb1, a.nk);
+    const int64_t nbase = (int64_t)t * TW + wave * 16 * NB;
+
+    acc_t acc[MB][NB];
+#pragma unroll
+    for (int mb = 0; mb < MB; ++mb)
+#pragma unroll
+      for (int nb = 0; nb < NB; ++nb) acc[mb][nb] = acc_t{0, 0, 0, 0};
+
+    if (gk0 < gk1) {
+      v16 sreg[SPASS];
+      // B operand registers: N-pass [nb][h][4], T-pass [h][tt][nb]
+      T bcur[NB * KG * 4], bnext[NB * KG * 4];
+
+      auto load_skinny = [&](int kb) {
+#pragma unroll
+        for (int p = 0; p < SPASS; ++p) {
+          const int v = tid + 256 * p;
+          const int c = v / VPR, kv = v % VPR;
+          const int64_t k = (int64_t)kb * KC + kv * E16;
+          v16 r;
+#pragma unroll
+          for (int e = 0; e < E16; ++e) r[e] = T(0);
+          if (c < ELLP) {
+            const T* src = S + (int64_t)c * a.lds + k;
+            if (k + E16 <= a.K) {
+              r = *(const v16*)src;
+            } else {
+#pragma unroll
+              for (int e = 0; e < E16; ++e)
+                if (k + e < a.K) r[e] = src[e];
+            }
+          }
+          sreg[p] = r;
+        }
+      };
+      auto store_skinny = [&](int buf) {
+#pragma unroll
+        for (int p = 0; p < SPASS; ++p) {
+          const int v = tid + 256 * p;
+          const int c = v / VPR, kv = v % VPR;
+          if (c < ELLP) *(v16*)&lds_s[buf][c * LDK + kv * E16] = sreg[p];
+        }
+      };
+      auto load_b = [&](int kb, T* b) {
+        if constexpr (!TRANS) {
+#pragma unroll
+          for (int nb = 0; nb < NB; ++nb) {
+            const int64_t n = nbase + nb * 16 + qd;
+#pragma unroll
+            for (int h = 0; h < KG; ++h) {
+              const int64_t k = (int64_t)kb * KC + 16 * h + 4 * g;
+              T* d = b + (nb * KG + h) * 4;
+#pragma unroll
+              for (int e = 0; e < 4; ++e) d[e] = T(0);
+              if (n < a.N) {
+                const T* src = A + n * a.lda + k;
+                if (a.vec && k + 4 <= a.K) {
+                  if constexpr (sizeof(T) == 4) {
+                    const f4 vv = *(const f4*)src;
+                    d[0] = vv[0]; d[1] = vv[1]; d[2] = vv[2]; d[3] = vv[3];
+                  } else {
+                    const d2 v0 = *(const d2*)src;
+                    const d2 v1 = *(const d2*)(src + 2);
+                    d[0] = v0[0]; d[1] = v0[1]; d[2] = v1[0]; d[3] = v1[1];
+                  }
+                } else {
+#pragma unroll
+                  for (int e = 0; e < 4; ++e)
+                    if (k + e < a.K) d[e] = src[e];
+                }
+              }
+            }
+          }
+        } else {
+#pragma unroll
+          for (int h = 0; h < KG; ++h)
+#pragma unroll
+            for (int tt = 0; tt < 4; ++tt) {
+              const int64_t k = (int64_t)kb * KC + 16 * h + 4 * g + tt;
+              const int64_t n0 = nbase + NB * qd;
+              T* d = b + (h * 4 + tt) * NB;
+#pragma unroll
+              for (int e = 0; e < NB; ++e) d[e] = T(0);
+              if (k < a.K) {
+                const T* src = A + k * a.lda + n0;
+                if (NB == 2 && a.vec && n0 + 2 <= a.N) {
+                  if constexpr (sizeof(T) == 4) {
+                    const f2 vv = *(const f2*)src;
+                    d[0] = vv[0]; d[NB - 1] = vv[1];
+                  } else {
+                    const d2 vv = *(const d2*)src;
+                    d[0] = vv[0]; d[NB - 1] = vv[1];
+                  }
+                } else {
+#pragma unroll
+                  for (int e = 0; e < NB; ++e)
+                    if (n0 + e < a.N) d[e] = src[e];
+                }
+              }
+            }
+        }
+      };
+
+      load_skinny(gk0);
+      load_b(gk0, bcur);
+      for (int kb = gk0; kb < gk1; ++kb, ++iter) {
+        const int buf = iter & 1;
+        store_skinny(buf);
+        __syncthreads();
+        if (kb + 1 < gk1) {
+          load_skinny(kb + 1);
+          load_b(kb + 1, bnext);
+        }
+        const T* ls = &lds_s[buf][0];
+#pragma unroll
+        for (int h = 0; h < KG; ++h) {
+          T sf[MB][4];
+#pragma unroll
+          for (int mb = 0; mb < MB; ++mb) {
+            const T* src = ls + (mb * 16 + qd) * LDK + 16 * h + 4 * g;
+            if constexpr (sizeof(T) == 4) {
+              const f4 vv = *(const f4*)src;
+              sf[mb][0] = vv[0]; sf[mb][1] = vv[1]; sf[mb][2] = vv[2]; sf[mb][3] = vv[3];
+            } else {
+              const d2 v0 = *(const d2*)src;
+              const d2 v1 = *(const d2*)(src + 2);
+              sf[mb][0] = v0[0]; sf[mb][1] = v0[1]; sf[mb][2] = v1[0]; sf[mb][3] = v1[1];
+            }
+          }
+#pragma unroll
+          for (int tt = 0; tt < 4; ++tt)
+#pragma unroll
+            for (int mb = 0; mb < MB; ++mb)
+#pragma unroll
+              for (int nb = 0; nb < NB; ++nb) {
+                const T bv = TRANS ? bcur[(h * 4 + tt) * NB + nb] : bcur[(nb * KG + h) * 4 + tt];
+                acc[mb][nb] = M::op(sf[mb][tt], bv, acc[mb][nb]);
+              }
+        }
+        if (kb + 1 < gk1) {
+#pragma unroll
+          for (int e = 0; e < NB * KG * 4; ++e) bcur[e] = bnext[e];
+        }
+      }
+    }
+
+    // partial tile (x, jw, t - tfirst): [ELLP][TW]
+    const int64_t slot = ((int64_t)x * a.gx + jw) * a.maxslot + (t - tfirst);
+    T* dst = P + slot * (int64_t)ELLP * TW;
+#pragma unroll
+    for (int mb = 0; mb < MB; ++mb)
+#pragma unroll
+      for (int i = 0; i < 4; ++i) {
+        // accumulator slot i of lane (g, qd) holds row 4g + i of the 16 x 16
+        // block for the FP32 instruction and row g + 4i for the FP64 one
+        const int c = mb * 16 + (sizeof(T) == 4 ? 4 * g + i : g + 4 * i);
+        if constexpr (!TRANS) {
+#pragma unroll
+          for (int nb = 0; nb < NB; ++nb) dst[(int64_t)c * TW + wave * 16 * NB + nb * 16 + qd] = acc[mb][nb][i];
+        } else {
+#pragma unroll
+          for (int nb = 0; nb < NB; ++nb) dst[(int64_t)c * TW + wave * 16 * NB + NB * qd + nb] = acc[mb][nb][i];
+        }
+      }
+    u += kb1 - kb0;
+  }
+}
+
+template <typename T, int MB, bool TRANS>
+void* kernel_ptr() {
+  constexpr int NB = MB <= 8 ? 2 : 1;
+  return (void*)&sketch_kernel<T, MB, TRANS, NB>;
+}
+
+template <typename T, bool TRANS>
+void* pick(int mb) {
+  switch (mb) {
+    case 1: return kernel_ptr<T, 1, TRANS>();
+    case 2: return kernel_ptr<T, 2, TRANS>();
+    case 3: return kernel_ptr<T, 3, TRANS>();
+    case 4: return kernel_ptr<T, 4, TRANS>();
+    case 5: return kernel_ptr<T, 5, TRANS>();
+    case 6: return kernel_ptr<T, 6, TRANS>();
+    case 7: return kernel_ptr<T, 7, TRANS>();
+    case 8: return kernel_ptr<T, 8, TRANS>();
+    case 9: return kernel_ptr<T, 9, TRANS>();
+    case 10: return kernel_ptr<T, 10, TRANS>();
+    case 11: return kernel_ptr<T, 11, TRANS>();
+    case 12: return kernel_ptr<T, 12, TRANS>();
+    case 13: return kernel_ptr<T, 13, TRANS>();
+    case 14: return kernel_ptr<T, 14, TRANS>();
+    case 15: return kernel_ptr<T, 15, TRANS>();
+    case 16: return kernel_ptr<T, 16, TRANS>();
+    default: return nullptr;
+  }
+}
+
+// Workgroups per CU to use (occupancy reported by the runtime, capped).
+constexpr int kOccCap = 4;
+
+int occupancy_of(void* fn) {
+  int occ = 0;
+  if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&occ, (const void*)fn, 256, 0) != hipSuccess)
+    occ = 1;
+  if (occ < 1) occ = 1;
+  return occ < kOccCap ? occ : kOccCap;
+}
+
+void geometry(int64_t N, int64_t K, int ellp, int elem, int gx, Partials* p) {
+  const int mb = ellp / 16;
+  const int nb = mb <= 8 ? 2 : 1;
+  const int tw = 64 * nb;
+  const int kc = 128 / elem;
+  p->ellp = ellp;
+  p->tw = tw;
+  p->elem = elem;
+  p->n = N;
+  p->tiles = (int)((N + tw - 1) / tw);
+  const int64_t nk = (K + kc - 1) / kc;
+  p->nkx = (int)((nk + 7) / 8);
+  if (p->nkx < 1) p->nkx = 1;
+  p->gx = gx;
+  const int64_t U = (int64_t)p->tiles * p->nkx;
+  int ms = 1;
+  for (int j = 0; j < gx; ++j) {
+    const int64_t u0 = (int64_t)j * U / gx, u1 = (int64_t)(j + 1) * U / gx;
+    if (u1 <= u0) continue;
+    const int s = (int)((u1 - 1) / p->nkx - u0 / p->nkx) + 1;
+    if (s > ms) ms = s;
+  }
+  p->maxslot = ms;
+}
+
+}  // namespace
+
+static int64_t need_elems(const Partials& p) {
+  return 8ll * p.gx * p.maxslot * (int64_t)p.ellp * p.tw;
+}
+
+int64_t partials_capacity(int64_t n_out, int64_t k_len, int ellp, int prec) {
+  int64_t best = 0;
+  for (int occ = 1; occ <= kOccCap; ++occ) {
+    Partials p;
+    geometry(n_out, k_len, ellp, prec == P_F64 ? 8 : 4, 32 * occ, &p);
+    const int64_t e = need_elems(p);
+    if (e > best) best = e;
+  }
+  return best;
+}
+
+hipError_t launch_sketch(int prec, int trans, const void* A, int64_t lda, int64_t R, int64_t C,
+                         const void* S, int64_t lds, int ellp, void* part_buf, int64_t part_elems,
+                         Partials* part, int num_cu, hipStream_t st) {
+  const bool f64 = prec == P_F64;
+  const int mb = ellp / 16;
+  void* fn = f64 ? (trans ? pick<double, true>(mb) : pick<double, false>(mb))
+                 : (trans ? pick<float, true>(mb) : pick<float, false>(mb));
+  if (!fn || (prec != P_F64 && prec != P_F32)) return hipErrorInvalidValue;
+  const int elem = f64 ? 8 : 4;
+  const int64_t N = trans ? C : R;
+  const int64_t K = trans ? R : C;
+  int gx = (num_cu / 8) * occupancy_of(fn);
+  if (gx < 1) gx = 1;
+  geometry(N, K, ellp, elem, gx, part);
+  while (need_elems(*part) > part_elems && gx > 1) {
+    gx = gx > 8 ? gx - 8 : gx - 1;
+    geometry(N, K, ellp, elem, gx, part);
+  }
+  if (need_elems(*part) > part_elems) return hipErrorInvalidValue;
+  part->ptr = part_buf;
+  SketchArgs a;
+  a.A = A;
+  a.lda = lda;
+  a.N = N;
+  a.K = K;
+  a.S = S;
+  a.lds = lds;
+  a.P = part_buf;
+  a.tiles = part->tiles;
+  a.nk = (int)((K + (128 / elem) - 1) / (128 / elem));
+  a.nkx = part->nkx;
+  a.gx = part->gx;
+  a.maxslot = part->maxslot;
+  a.vec = (((uintptr_t)A) % 16 == 0) && ((lda * elem) % 16 == 0);
+  void* args[] = {&a};
+  return hipLaunchKernel((const void*)fn, dim3(8 * gx), dim3(256), args, 0, st);
+}
+
+}  // namespace corutv

@@ -1,0 +1,164 @@
+"""End-to-end GPU parity of corutv_decompose against the float64 oracle.
+
+Bars (the decomposition is randomized but both sides draw the identical test
+matrix, so they compute the same thing up to rounding):
+* F64 path: |e_gpu - e_oracle| <= 1e-10 and ||A_gpu - A_oracle||_F / ||A||_F
+  <= 1e-10 (A_x = U T V^T), U, V orthonormal to 1e-13, T exactly triangular
+  with a non-negative non-increasing diagonal, and the pivots of the steps
+  decided by a margin (the leading k) identical.
+* F32 path: |e_gpu - e_oracle| <= 1e-5 (e = relative Frobenius error) with
+  the oracle run in float64 on the same float32 data.
+Cases cover the small plain configuration (2000 x 1500, rank 20 + 1e-6 noise,
+l = 30, q = 1, lower T), orientations, layouts, ragged sizes, q in {0, 1, 2},
+exact low rank (Householder fallback), NaN input and bad arguments.
+"""
+import numpy as np
+import pytest
+import torch
+
+from oracle.corutv import corutv, rel_err
+from workloads import decaying, noisy_low_rank
+
+pytestmark = pytest.mark.gpu
+
+
+@pytest.fixture(scope="module")
+def ctx():
+    import paper_1906_04572_amd as cu
+
+    c = cu.Context(workspace_bytes=1 << 31)
+    yield c
+    c.close()
+
+
+def _say(*a):
+    print("[case]", *a, flush=True)
+
+
+def _dev(A, layout):
+    if layout == "row":
+        return torch.from_numpy(np.ascontiguousarray(A)).cuda()
+    return torch.from_numpy(np.ascontiguousarray(A.T)).cuda().t()
+
+
+def _run(ctx, A, k, p, q, seed, prec, tri, layout="row"):
+    U, T, V, piv, info = ctx.decompose(_dev(A, layout), k, p, q, seed, prec=prec, tri=tri, want_err=True)
+    return U.cpu().numpy().astype(np.float64), T.cpu().numpy(), V.cpu().numpy().astype(np.float64), \
+        piv.cpu().numpy(), info
+
+
+def _check_f64(A, k, p, q, seed, tri, got, ref):
+    U, T, V, piv, info = got
+    ell = k + p
+    e_ref = rel_err(A, ref["U"], ref["T"], ref["V"])
+    assert abs(info["rel_err"] - e_ref) <= 1e-10, (info["rel_err"], e_ref)
+    Ah = U @ T @ V.T
+    Ar = ref["U"] @ ref["T"] @ ref["V"].T
+    d = np.linalg.norm(Ah - Ar) / np.linalg.norm(A)
+    assert d <= 1e-10, d
+    assert np.max(np.abs(U.T @ U - np.eye(ell))) <= 1e-13
+    assert np.max(np.abs(V.T @ V - np.eye(ell))) <= 1e-13
+    lower = info["tri"] == "lower"
+    assert np.all((np.triu(T, 1) if lower else np.tril(T, -1)) == 0)
+    dg = np.diag(T)
+    assert np.all(dg >= 0) and np.all(dg[:-1] >= dg[1:] * (1 - 1e-12))
+    np.testing.assert_array_equal(piv[:k], ref["piv"][:k])
+    # leading-k factors (signs are fixed by diag(T) >= 0)
+    np.testing.assert_allclose(dg[:k], np.diag(ref["T"])[:k], rtol=1e-10, atol=0)
+    return info
+
+
+def test_plain_config_2000x1500_rank20_lower(ctx):
+    _say("C1 2000x1500 rank20 1e-6 noise, l=30, q=1, lower, f64")
+    A = noisy_low_rank(2000, 1500, 20, 1e-6, seed=1)
+    got = _run(ctx, A, 20, 10, 1, 2024, "f64", "lower")
+    ref = corutv(A, 20, 10, 1, seed=2024, tri="lower")
+    info = _check_f64(A, 20, 10, 1, 2024, "lower", got, ref)
+    assert info["tri"] == "lower" and info["passes"] == 6
+    print("C1 rel_err gpu %.12e fallbacks %d" % (info["rel_err"], info["qr_fallbacks"]))
+
+
+@pytest.mark.parametrize("m,n,k,p,q,tri,layout", [
+    (1200, 900, 20, 10, 1, "upper", "row"),
+    (1200, 900, 20, 10, 0, "auto", "col"),
+    (900, 1200, 20, 10, 1, "auto", "row"),
+    (900, 1200, 20, 10, 2, "upper", "col"),
+    (1037, 613, 17, 6, 1, "lower", "col"),
+    (3000, 250, 5, 5, 1, "auto", "row"),
+    (700, 700, 100, 28, 1, "auto", "row"),
+    (2100, 1900, 150, 50, 0, "upper", "row"),
+])
+def test_f64_cases(ctx, m, n, k, p, q, tri, layout):
+    _say("f64", m, n, k, p, q, tri, layout)
+    A = decaying(m, n, min(m, n) // 2, 1e-4, seed=m + n, kind="exp", tau=max(k / 2, 3))
+    got = _run(ctx, A, k, p, q, 77, "f64", tri, layout)
+    ref = corutv(A, k, p, q, seed=77, tri=tri)
+    _check_f64(A, k, p, q, 77, tri, got, ref)
+
+
+@pytest.mark.parametrize("m,n,k,p,q,layout", [
+    (3000, 2000, 50, 10, 1, "row"), (2000, 3000, 50, 10, 1, "col"), (4000, 3000, 100, 10, 2, "row"),
+    (2500, 1800, 30, 20, 0, "col"),
+])
+def test_f32_cases(ctx, m, n, k, p, q, layout):
+    _say("f32", m, n, k, p, q, layout)
+    A = decaying(m, n, 300, 1e-4, seed=m * 3 + n, kind="exp", tau=25.0).astype(np.float32)
+    U, T, V, piv, info = _run(ctx, A, k, p, q, 5, "f32", "auto", layout)
+    A64 = A.astype(np.float64)
+    ref = corutv(A64, k, p, q, seed=5)
+    e_ref = rel_err(A64, ref["U"], ref["T"], ref["V"])
+    assert abs(info["rel_err"] - e_ref) <= 1e-5, (info["rel_err"], e_ref)
+    e_gpu = rel_err(A64, U, T, V)  # the returned factors themselves
+    assert abs(e_gpu - e_ref) <= 1e-5
+    ell = k + p
+    assert np.max(np.abs(U.T @ U - np.eye(ell))) <= 1e-5
+    assert np.max(np.abs(V.T @ V - np.eye(ell))) <= 1e-5
+
+
+@pytest.mark.parametrize("prec", ["f64", "f32"])
+def test_exact_low_rank_is_recovered(ctx, prec):
+    _say("exact rank", prec)
+    A = noisy_low_rank(1500, 1100, 12, 0.0, seed=3)
+    if prec == "f32":
+        A = A.astype(np.float32)
+    U, T, V, piv, info = _run(ctx, A, 12, 8, 1, 9, prec, "auto")
+    assert info["qr_fallbacks"] >= 1
+    bound = 1e-12 if prec == "f64" else 1e-5
+    assert info["rel_err"] <= bound
+    assert rel_err(A.astype(np.float64), U, T, V) <= bound
+
+
+def test_nan_input_is_reported(ctx):
+    import paper_1906_04572_amd as cu
+
+    _say("nan")
+    A = decaying(600, 500, 50, 1e-3, seed=1)
+    A[123, 45] = np.nan
+    rc = ctx.decompose_rc(_dev(A, "row"), 10, 5, 1, 3)
+    assert rc == cu.E_NUMERIC
+
+
+def test_bad_arguments_leave_outputs_untouched(ctx):
+    import paper_1906_04572_amd as cu
+
+    _say("bad args")
+    A = torch.from_numpy(decaying(300, 200, 20, 1e-3, seed=1)).cuda()
+    out = ctx.alloc_outputs(A, 10, 5)
+    for t in out:
+        t.fill_(7)
+    assert ctx.decompose_rc(A, 150, 100, 1, 3, out=out) == cu.E_INVAL  # l > min(m, n)
+    assert ctx.decompose_rc(A, 0, 5, 1, 3, out=out) == cu.E_INVAL
+    assert ctx.decompose_rc(A, 10, 5, -1, 3, out=out) == cu.E_INVAL
+    assert ctx.decompose_rc(A, 10, 5, 1, 3, prec="f32", out=out) == cu.E_INVAL  # f64 data
+    torch.cuda.synchronize()
+    for t in out:
+        assert torch.all(t == 7)
+
+
+def test_deterministic_bitwise(ctx):
+    _say("determinism")
+    A = _dev(decaying(5000, 3000, 200, 1e-4, seed=2), "row").float()
+    a = ctx.decompose(A, 50, 10, 1, 4, prec="f32")
+    b = ctx.decompose(A, 50, 10, 1, 4, prec="f32")
+    for x, y in zip(a[:4], b[:4]):
+        assert torch.equal(x, y)

@@ -1,0 +1,128 @@
+"""GPU parity of the single steps, through the C ABI, against the oracle.
+
+* Gaussian test matrix: bit-identical to the oracle's stream (F64), F32 is its
+  round-to-nearest-even.
+* Passes over A (Y = A X, Z = A^T X): F64 within 1e-13 relative, F32 within
+  the FP32 accumulation bound, both layouts, ragged and misaligned sizes.
+* Thin QR (CholeskyQR2 / Householder fallback): equal to the oracle's
+  Householder Q (unique with diag R > 0) within 1e-12; orthonormal to 1e-13.
+* QRCP of the core: identical pivots when fed the oracle's input bits.
+"""
+import numpy as np
+import pytest
+import torch
+
+from oracle.corutv import corutv
+from oracle.dense import householder_qr, qrcp
+from oracle.philox import omega
+from workloads import decaying, noisy_low_rank
+
+pytestmark = pytest.mark.gpu
+
+
+@pytest.fixture(scope="module")
+def ctx():
+    import paper_1906_04572_amd as cu
+
+    c = cu.Context(workspace_bytes=1 << 31)
+    yield c
+    c.close()
+
+
+def _say(*a):
+    print("[case]", *a, flush=True)
+
+
+@pytest.mark.parametrize("n,ell,seed,sub", [(1000, 37, 1, 0), (4097, 16, 2**63 + 5, 3), (3, 1, 0, 0xFFFF),
+                                            (200003, 64, 12345, 0)])
+def test_omega_bit_exact(ctx, n, ell, seed, sub):
+    _say("omega", n, ell, seed, sub)
+    g = ctx.omega(n, ell, seed, sub).cpu().numpy()
+    o = omega(n, ell, seed, sub)
+    assert np.array_equal(g.view(np.uint64), o.view(np.uint64)), np.argwhere(g != o)[:5]
+    g32 = ctx.omega(n, ell, seed, sub, torch.float32).cpu().numpy()
+    assert np.array_equal(g32.view(np.uint32), o.astype(np.float32).view(np.uint32))
+
+
+CASES = [
+    # m, n, ell, layout, prec
+    (1000, 777, 37, "row", "f64"), (1000, 777, 37, "col", "f64"), (1000, 777, 37, "row", "f32"),
+    (1000, 777, 37, "col", "f32"), (513, 2050, 16, "row", "f32"), (4096, 1024, 112, "row", "f32"),
+    (4096, 1024, 112, "col", "f64"), (3000, 700, 256, "row", "f32"), (1537, 1201, 1, "row", "f64"),
+    (64, 64, 64, "col", "f32"), (300, 20000, 10, "row", "f32"), (2048, 1000, 200, "row", "f64"),
+]
+
+
+@pytest.mark.parametrize("m,n,ell,layout,prec", CASES)
+@pytest.mark.parametrize("trans", [False, True])
+def test_sketch_pass(ctx, m, n, ell, layout, prec, trans):
+    _say("sketch", m, n, ell, layout, prec, trans)
+    dt = np.float64 if prec == "f64" else np.float32
+    rng = np.random.default_rng(m * 7 + n + ell)
+    A = rng.standard_normal((m, n)).astype(dt)
+    X = rng.standard_normal((m if trans else n, ell)).astype(dt)
+    At = torch.from_numpy(A).cuda()
+    if layout == "col":
+        At = torch.from_numpy(np.ascontiguousarray(A.T)).cuda().t()
+    Y = ctx.sketch(At, torch.from_numpy(X).cuda(), trans=trans, prec=prec).cpu().numpy()
+    ref = (A.astype(np.float64).T if trans else A.astype(np.float64)) @ X.astype(np.float64)
+    K = m if trans else n
+    scale = np.sqrt(K) * np.abs(X).max() * np.abs(A).max()
+    tol = 1e-14 * np.sqrt(K) if prec == "f64" else 2e-6 * np.sqrt(K)
+    err = np.max(np.abs(Y - ref)) / scale
+    assert err <= tol, err
+
+
+@pytest.mark.parametrize("rows,ell", [(5000, 40), (20000, 112), (777, 1), (3001, 130), (4000, 220)])
+def test_tsqr_matches_householder(ctx, rows, ell):
+    _say("tsqr", rows, ell)
+    rng = np.random.default_rng(rows + ell)
+    X = rng.standard_normal((rows, ell)) @ np.diag(np.logspace(0, -3, ell))
+    Q, R, fb = ctx.tsqr(torch.from_numpy(X).cuda())
+    Q, R = Q.cpu().numpy(), R.cpu().numpy()
+    Qo, Ro = householder_qr(X)
+    assert not fb
+    assert np.max(np.abs(Q.T @ Q - np.eye(ell))) <= 1e-13 * max(1, ell / 32)
+    assert np.max(np.abs(Q - Qo)) <= 1e-10
+    assert np.max(np.abs(R - Ro)) <= 1e-12 * np.abs(Ro).max()
+    assert np.all(np.tril(R, -1) == 0) and np.all(np.diag(R) > 0)
+
+
+@pytest.mark.parametrize("rows,ell,rank", [(3000, 30, 12), (2000, 64, 1), (500, 17, 16)])
+def test_tsqr_rank_deficient_falls_back(ctx, rows, ell, rank):
+    _say("tsqr-deficient", rows, ell, rank)
+    rng = np.random.default_rng(rows)
+    X = rng.standard_normal((rows, rank)) @ rng.standard_normal((rank, ell))
+    Q, R, fb = ctx.tsqr(torch.from_numpy(X).cuda())
+    Q, R = Q.cpu().numpy(), R.cpu().numpy()
+    assert fb
+    assert np.max(np.abs(Q.T @ Q - np.eye(ell))) <= 1e-13
+    assert np.max(np.abs(Q @ R - X)) <= 1e-13 * np.abs(X).max() * np.sqrt(rows)
+    assert np.all(np.diag(R) >= 0)
+
+
+def _cores():
+    out = []
+    A = noisy_low_rank(400, 300, 20, 1e-6, seed=1)
+    out.append(("c1-like", corutv(A, 20, 10, 1, seed=1)["D"]))
+    rng = np.random.default_rng(5)
+    for ell in (10, 30, 110, 128, 129, 200, 256):
+        out.append(("gauss%d" % ell, rng.standard_normal((ell, ell)) * np.logspace(0, -8, ell)))
+    D = rng.standard_normal((40, 6)) @ rng.standard_normal((6, 40))
+    out.append(("rank6", D))
+    Z = np.zeros((12, 12))
+    Z[:, 3] = 1.0
+    Z[:, 7] = 1.0
+    out.append(("ties", Z))
+    return out
+
+
+@pytest.mark.parametrize("name,D", _cores(), ids=[c[0] for c in _cores()])
+def test_qrcp_pivots_bit_exact(ctx, name, D):
+    _say("qrcp", name, D.shape)
+    Qt, R, piv = ctx.qrcp(torch.from_numpy(np.ascontiguousarray(D)).cuda())
+    Qto, Ro, pivo = qrcp(D)
+    np.testing.assert_array_equal(piv.cpu().numpy(), pivo)
+    # same arithmetic order: R and Qt agree to the last bits
+    np.testing.assert_allclose(R.cpu().numpy(), Ro, rtol=0, atol=1e-13 * max(1.0, np.abs(D).max()))
+    np.testing.assert_allclose(Qt.cpu().numpy(), Qto, rtol=0, atol=1e-12)
