@@ -195,6 +195,21 @@ int corutv_wait(corutv_ctx* ctx, uint64_t ticket, corutv_info* info);
 
 const char* corutv_strerror(int code);
 
+/* ---- measurement ---------------------------------------------------------
+ * When enabled, corutv_decompose records HIP events on its stream around
+ * every pass over A (the sketch kernels of eqs. 4, 5 and 7 and the power
+ * products of Algorithm 1) and accumulates their device time; the residual
+ * pass of want_err is not included.  Disabled by default; enabling or
+ * reading clears nothing else. */
+typedef struct corutv_pass_stats {
+  int64_t passes;      /* passes timed since the last reset               */
+  double total_ms;     /* summed device time of those passes              */
+  double min_ms;       /* fastest single pass                             */
+  double max_ms;       /* slowest single pass                             */
+} corutv_pass_stats;
+int corutv_pass_timing(corutv_ctx* ctx, int32_t enable, int32_t reset);
+int corutv_get_pass_stats(corutv_ctx* ctx, corutv_pass_stats* out);
+
 /* ---- single steps (parity checks and diagnostics) -----------------------
  * Each runs one stage of the pipeline on caller buffers, blocking. */
 

@@ -56,6 +56,11 @@ class RpcaInfo(ctypes.Structure):
         return {f: getattr(self, f) for f, _ in self._fields_}
 
 
+class PassStats(ctypes.Structure):
+    _fields_ = [("passes", ctypes.c_int64), ("total_ms", ctypes.c_double), ("min_ms", ctypes.c_double),
+                ("max_ms", ctypes.c_double)]
+
+
 class Config(ctypes.Structure):
     _fields_ = [("device", ctypes.c_int32), ("n_streams", ctypes.c_int32),
                 ("streams", ctypes.POINTER(ctypes.c_void_p)), ("workspace", ctypes.c_void_p),
@@ -93,6 +98,8 @@ def _load():
         "corutv_sketch": (ctypes.c_int, [P, MP, I32, I32, P, I64, I32, P, I64]),
         "corutv_tsqr": (ctypes.c_int, [P, P, I64, I32, I64, P, I64, P, I64, ctypes.POINTER(I32)]),
         "corutv_qrcp": (ctypes.c_int, [P, I32, P, I64, P, P, P]),
+        "corutv_pass_timing": (ctypes.c_int, [P, I32, I32]),
+        "corutv_get_pass_stats": (ctypes.c_int, [P, ctypes.POINTER(PassStats)]),
     }
     for name, (res, args) in sig.items():
         f = getattr(lib, name)
@@ -244,6 +251,15 @@ class Context:
         _check(lib.corutv_qrcp(self.h, ell, Dc.data_ptr(), ell, Qt.data_ptr(), R.data_ptr(),
                                piv.data_ptr()), "qrcp")
         return Qt.t(), R.t(), piv
+
+    # -- measurement ----------------------------------------------------------
+    def pass_timing(self, enable=True, reset=True):
+        _check(lib.corutv_pass_timing(self.h, 1 if enable else 0, 1 if reset else 0), "pass_timing")
+
+    def pass_stats(self):
+        st = PassStats()
+        _check(lib.corutv_get_pass_stats(self.h, ctypes.byref(st)), "pass_stats")
+        return {f: getattr(st, f) for f, _ in st._fields_}
 
     # -- robust PCA -----------------------------------------------------------
     def rpca(self, M, k, p, q, seed, lam=-1.0, max_iter=50, tol=0.0, want_L=True):

@@ -122,6 +122,11 @@ struct corutv_ctx {
   std::vector<int> slot_busy;
   std::vector<std::pair<size_t, size_t>> arena;  // allocated [off, off+size)
   int* host_status = nullptr;                    // pinned, kMaxQr per slot
+  // pass timing (blocking decompositions only)
+  bool timing = false;
+  std::vector<hipEvent_t> ev_pool;
+  int64_t t_passes = 0;
+  double t_total = 0, t_min = 1e300, t_max = 0;
 };
 
 namespace {
@@ -228,7 +233,7 @@ hipError_t qr_from_partials(const Plan& pl, char* ws, const Partials& pp, int64_
 
 // Enqueue a whole decomposition on stream s using the workspace at ws.
 int enqueue_decompose(corutv_ctx* ctx, const Plan& pl, char* ws, const DecArgs& d, hipStream_t s,
-                      Enqueued* out) {
+                      Enqueued* out, std::vector<hipEvent_t>* pass_ev = nullptr) {
   const int64_t m = d.A.rows, n = d.A.cols;
   const int ell = pl.ell, ellp = pl.ellp;
   const int prec = d.opts.prec;
@@ -277,13 +282,23 @@ int enqueue_decompose(corutv_ctx* ctx, const Plan& pl, char* ws, const DecArgs& 
 
   int nqr = 0;
   Partials pp;
+  size_t evi = 0;
+  auto mark = [&]() {
+    if (pass_ev && evi < pass_ev->size()) hipEventRecord((*pass_ev)[evi++], s);
+  };
   auto passA = [&](const void* opnd) {  // P X, X nn x ell -> mm x ell
-    return launch_sketch(prec, tA, d.A.ptr, d.A.ld, Rb, Cb, opnd, ldn, ellp, part, pl.part_elems, &pp,
-                         ctx->num_cu, s);
+    mark();
+    hipError_t e = launch_sketch(prec, tA, d.A.ptr, d.A.ld, Rb, Cb, opnd, ldn, ellp, part,
+                                 pl.part_elems, &pp, ctx->num_cu, s);
+    mark();
+    return e;
   };
   auto passAt = [&](const void* opnd) {  // P^T Y, Y mm x ell -> nn x ell
-    return launch_sketch(prec, tAt, d.A.ptr, d.A.ld, Rb, Cb, opnd, ldm, ellp, part, pl.part_elems, &pp,
-                         ctx->num_cu, s);
+    mark();
+    hipError_t e = launch_sketch(prec, tAt, d.A.ptr, d.A.ld, Rb, Cb, opnd, ldm, ellp, part,
+                                 pl.part_elems, &pp, ctx->num_cu, s);
+    mark();
+    return e;
   };
   // Omega (nn x ell), then Q1 = qf(P Omega)
   HIPOK(launch_omega(nn, ell, ellp, d.seed, d.sub, f64 ? (double*)wop : nullptr,
@@ -486,7 +501,17 @@ int corutv_decompose(corutv_ctx* ctx, const corutv_mat* A, int32_t k, int32_t p,
   if (hipEventCreate(&e0) != hipSuccess || hipEventCreate(&e1) != hipSuccess) return poison(ctx);
   hipEventRecord(e0, s);
   Enqueued eq;
-  rc = enqueue_decompose(ctx, pl, ctx->ws, d, s, &eq);
+  const int npass = 2 * q + 3;
+  if (ctx->timing) {
+    while ((int)ctx->ev_pool.size() < 2 * npass) {
+      hipEvent_t e;
+      if (hipEventCreate(&e) != hipSuccess) return poison(ctx);
+      ctx->ev_pool.push_back(e);
+    }
+  }
+  std::vector<hipEvent_t> pev;
+  if (ctx->timing) pev.assign(ctx->ev_pool.begin(), ctx->ev_pool.begin() + 2 * npass);
+  rc = enqueue_decompose(ctx, pl, ctx->ws, d, s, &eq, ctx->timing ? &pev : nullptr);
   if (rc == CORUTV_E_DEVICE) {
     hipEventDestroy(e0);
     hipEventDestroy(e1);
@@ -509,6 +534,16 @@ int corutv_decompose(corutv_ctx* ctx, const corutv_mat* A, int32_t k, int32_t p,
   hipEventElapsedTime(&ms, e0, e1);
   hipEventDestroy(e0);
   hipEventDestroy(e1);
+  if (ctx->timing) {
+    for (int i = 0; i < npass; ++i) {
+      float pm = 0.f;
+      if (hipEventElapsedTime(&pm, pev[2 * i], pev[2 * i + 1]) != hipSuccess) continue;
+      ctx->t_passes++;
+      ctx->t_total += pm;
+      ctx->t_min = std::min(ctx->t_min, (double)pm);
+      ctx->t_max = std::max(ctx->t_max, (double)pm);
+    }
+  }
   rc = finish_info(eq, hst, eq.dev_sum ? hsum : nullptr, info);
   if (info) {
     info->gpu_ms = ms;
@@ -888,6 +923,29 @@ int corutv_cancel(corutv_ctx* ctx, uint64_t ticket) {
   return CORUTV_OK;
 }
 
+int corutv_pass_timing(corutv_ctx* ctx, int32_t enable, int32_t reset) {
+  if (!ctx) return CORUTV_E_INVAL;
+  std::lock_guard<std::mutex> lk(ctx->run_mu);
+  ctx->timing = enable != 0;
+  if (reset) {
+    ctx->t_passes = 0;
+    ctx->t_total = 0;
+    ctx->t_min = 1e300;
+    ctx->t_max = 0;
+  }
+  return CORUTV_OK;
+}
+
+int corutv_get_pass_stats(corutv_ctx* ctx, corutv_pass_stats* out) {
+  if (!ctx || !out) return CORUTV_E_INVAL;
+  std::lock_guard<std::mutex> lk(ctx->run_mu);
+  out->passes = ctx->t_passes;
+  out->total_ms = ctx->t_total;
+  out->min_ms = ctx->t_passes ? ctx->t_min : 0.0;
+  out->max_ms = ctx->t_max;
+  return CORUTV_OK;
+}
+
 int corutv_destroy(corutv_ctx* ctx) {
   if (!ctx) return CORUTV_E_INVAL;
   {
@@ -899,6 +957,7 @@ int corutv_destroy(corutv_ctx* ctx) {
   for (auto& kv : ctx->jobs) delete kv.second;
   ctx->jobs.clear();
   if (ctx->host_status) hipHostFree(ctx->host_status);
+  for (hipEvent_t e : ctx->ev_pool) hipEventDestroy(e);
   delete ctx;
   return CORUTV_OK;
 }

@@ -22,6 +22,9 @@
 //    Each workgroup writes one partial tile per output tile it touches; the
 //    consumer kernel sums them in a fixed order, so results are
 //    deterministic (no atomics).
+#include <map>
+#include <mutex>
+
 #include "internal.hpp"
 
 namespace corutv {
@@ -298,12 +301,24 @@ void* pick(int mb) {
 // Workgroups per CU to use (occupancy reported by the runtime, capped).
 constexpr int kOccCap = 4;
 
+// cached per kernel: the runtime query costs host time on every launch
+std::mutex g_occ_mu;
+std::map<void*, int> g_occ;
+
 int occupancy_of(void* fn) {
+  {
+    std::lock_guard<std::mutex> lk(g_occ_mu);
+    auto it = g_occ.find(fn);
+    if (it != g_occ.end()) return it->second;
+  }
   int occ = 0;
   if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&occ, (const void*)fn, 256, 0) != hipSuccess)
     occ = 1;
   if (occ < 1) occ = 1;
-  return occ < kOccCap ? occ : kOccCap;
+  occ = occ < kOccCap ? occ : kOccCap;
+  std::lock_guard<std::mutex> lk(g_occ_mu);
+  g_occ[fn] = occ;
+  return occ;
 }
 
 void geometry(int64_t N, int64_t K, int ellp, int elem, int gx, Partials* p) {
