@@ -85,7 +85,7 @@ bool make_plan(int64_t m, int64_t n, int k, int p, int q, int prec, Plan* pl) {
   pl->o_core = take(l2);
   pl->o_qt = take(l2);
   pl->o_rt = take(l2);
-  pl->o_qw = take(2 * l2);
+  pl->o_qw = take(2 * l2 + 2 * (size_t)ell * 8);
   pl->o_tt = take(l2);
   pl->o_piv = take((size_t)ell * 4);
   pl->o_st = take(kMaxQr * 4);
@@ -673,7 +673,7 @@ int corutv_qrcp(corutv_ctx* ctx, int32_t ell, const double* D, int64_t ldd, doub
   int rc = guard(ctx);
   if (rc) return rc;
   if (ell < 1 || ell > 256 || !D || !Qt || !R || !piv || ldd < ell) return CORUTV_E_INVAL;
-  if ((size_t)2 * ell * ell * 8 > ctx->ws_bytes) return CORUTV_E_NOMEM;
+  if (((size_t)2 * ell * ell + 2 * ell) * 8 > ctx->ws_bytes) return CORUTV_E_NOMEM;
   std::lock_guard<std::mutex> lk(ctx->run_mu);
   hipStream_t s = ctx->streams[0];
   HIPOK(launch_qrcp(D, ldd, 0, ell, Qt, R, piv, (double*)ctx->ws, s));

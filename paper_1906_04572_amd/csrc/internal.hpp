@@ -83,8 +83,7 @@ hipError_t launch_rowmat(const double* X, int64_t ldx, int64_t rows, int ell, co
                          const int* skip, hipStream_t st);
 
 // Cholesky G = R^T R of an SPD ell x ell FP64 matrix (column-major, ld ell)
-// and the inverse of R, both written column-major (ld ell).  R must have room
-// for 2*ell*ell doubles (the second half is scratch for ell > 128).  status gets
+// and the inverse of R, both written column-major (ld ell).  status gets
 // bit 1 on breakdown (non-positive or non-finite pivot) and bit 2 when the
 // input holds NaN/Inf.  Runs only when *skip == 0 (skip may be null).
 hipError_t launch_chol(const double* G, int ell, double* R, double* Rinv, int* status,
@@ -99,7 +98,7 @@ hipError_t launch_householder_qr(const double* X, int64_t ldx, int64_t rows, int
 hipError_t launch_fill_int(int* p, int n, int v, hipStream_t st);
 
 // Column-pivoted QR of an ell x ell FP64 matrix (column-major, ldd; trans
-// reads D^T).  Qt, R column-major ld ell; piv int32.  work: 2*ell*ell doubles.
+// reads D^T).  Qt, R column-major ld ell; piv int32.  work: 2*ell*ell + 2*ell doubles.
 hipError_t launch_qrcp(const double* D, int64_t ldd, int trans, int ell, double* Qt, double* R,
                        int32_t* piv, double* work, hipStream_t st);
 

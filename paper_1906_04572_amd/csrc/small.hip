@@ -14,41 +14,53 @@ namespace corutv {
 namespace {
 
 // ---------------------------------------------------------------------------
-// sum of stream-K partial tiles
-template <typename T>
-__device__ double sum_tile_partials(const T* __restrict__ P, const Partials& p, int c, int64_t n) {
-  const int t = (int)(n / p.tw);
-  const int nl = (int)(n % p.tw);
-  const int64_t U = (int64_t)p.tiles * p.nkx;
-  const int64_t lo = (int64_t)t * p.nkx, hi = lo + p.nkx;
-  const int64_t tile_elems = (int64_t)p.ellp * p.tw;
-  double s = 0.0;
-  for (int x = 0; x < 8; ++x) {
-    for (int j = (int)(lo * p.gx / U); j < p.gx; ++j) {
-      const int64_t u0 = (int64_t)j * U / p.gx;
-      if (u0 >= hi) break;
-      const int64_t u1 = (int64_t)(j + 1) * U / p.gx;
-      if ((u0 > lo ? u0 : lo) >= (u1 < hi ? u1 : hi)) continue;
-      const int64_t slot = ((int64_t)x * p.gx + j) * p.maxslot + (t - u0 / p.nkx);
-      s += (double)P[slot * tile_elems + (int64_t)c * p.tw + nl];
-    }
-  }
-  return s;
-}
+// Sum of the stream-K partial tiles.  One block per (output tile, column
+// group): the tile's contributing partial slots are listed once in LDS in the
+// fixed order (chunk x ascending, workgroup ascending), then every thread sums
+// its (column, row) entries over that list.
+constexpr int kSegMax = 2048;
+constexpr int kSumCols = 16;  // columns per block
 
-__global__ void sum_partials_kernel(Partials p, int ell, int ncols, double* __restrict__ out64,
-                                    float* __restrict__ out32, int64_t ld) {
-  const int64_t idx = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-  if (idx >= p.n * ncols) return;
-  const int64_t n = idx % p.n;
-  const int c = (int)(idx / p.n);
-  double v = 0.0;
-  if (c < ell) {
-    v = p.elem == 8 ? sum_tile_partials((const double*)p.ptr, p, c, n)
-                    : sum_tile_partials((const float*)p.ptr, p, c, n);
+template <typename T>
+__global__ void __launch_bounds__(256) sum_partials_kernel(Partials p, const T* __restrict__ P, int ell,
+                                                           int ncols, double* __restrict__ out64,
+                                                           float* __restrict__ out32, int64_t ld) {
+  __shared__ int seg[kSegMax];
+  __shared__ int nseg;
+  const int t = blockIdx.x;
+  const int c0 = blockIdx.y * kSumCols;
+  if (threadIdx.x == 0) {
+    const int64_t U = (int64_t)p.tiles * p.nkx;
+    const int64_t lo = (int64_t)t * p.nkx, hi = lo + p.nkx;
+    int n = 0;
+    for (int x = 0; x < 8; ++x) {
+      for (int j = (int)(lo * p.gx / U); j < p.gx; ++j) {
+        const int64_t u0 = (int64_t)j * U / p.gx;
+        if (u0 >= hi) break;
+        const int64_t u1 = (int64_t)(j + 1) * U / p.gx;
+        if ((u0 > lo ? u0 : lo) >= (u1 < hi ? u1 : hi)) continue;
+        if (n < kSegMax) seg[n] = (x * p.gx + j) * p.maxslot + (t - (int)(u0 / p.nkx));
+        ++n;
+      }
+    }
+    nseg = n;
   }
-  if (out64) out64[(int64_t)c * ld + n] = v;
-  if (out32) out32[(int64_t)c * ld + n] = (float)v;
+  __syncthreads();
+  const int ns = nseg < kSegMax ? nseg : kSegMax;
+  const int64_t tile_elems = (int64_t)p.ellp * p.tw;
+  for (int e = threadIdx.x; e < kSumCols * p.tw; e += blockDim.x) {
+    const int nl = e % p.tw;
+    const int c = c0 + e / p.tw;
+    const int64_t n = (int64_t)t * p.tw + nl;
+    if (c >= ncols || n >= p.n) continue;
+    double v = 0.0;
+    if (c < ell) {
+      const T* src = P + (int64_t)c * p.tw + nl;
+      for (int k = 0; k < ns; ++k) v += (double)src[(int64_t)seg[k] * tile_elems];
+    }
+    if (out64) out64[(int64_t)c * ld + n] = v;
+    if (out32) out32[(int64_t)c * ld + n] = (float)v;
+  }
 }
 
 // ---------------------------------------------------------------------------
@@ -109,14 +121,21 @@ __global__ void __launch_bounds__(256) xty_kernel(const double* __restrict__ Xa,
     }
 }
 
-__global__ void reduce_kernel(const double* __restrict__ part, int splits, int64_t elems,
-                              double* __restrict__ out, const int* skip) {
+// out[e] = sum over k of part[k * elems + e], in a fixed order: thread group
+// g (0..3) sums splits g, g+4, ...; the four group sums are added in order.
+__global__ void __launch_bounds__(256) reduce_kernel(const double* __restrict__ part, int splits,
+                                                     int64_t elems, double* __restrict__ out,
+                                                     const int* skip) {
   if (skip && *skip) return;
-  const int64_t e = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-  if (e >= elems) return;
+  __shared__ double red[4][64];
+  const int el = threadIdx.x & 63, grp = threadIdx.x >> 6;
+  const int64_t e = (int64_t)blockIdx.x * 64 + el;
   double s = 0.0;
-  for (int k = 0; k < splits; ++k) s += part[(int64_t)k * elems + e];
-  out[e] = s;
+  if (e < elems)
+    for (int k = grp; k < splits; k += 4) s += part[(int64_t)k * elems + e];
+  red[grp][el] = s;
+  __syncthreads();
+  if (grp == 0 && e < elems) out[e] = ((red[0][el] + red[1][el]) + red[2][el]) + red[3][el];
 }
 
 // ---------------------------------------------------------------------------
@@ -201,21 +220,32 @@ __global__ void __launch_bounds__(256) rowmat_kernel(const double* __restrict__ 
 }
 
 // ---------------------------------------------------------------------------
-// Cholesky G = R^T R fused with the inverse of R.  W (ell x ell, column-major)
-// holds the matrix being factored in its upper triangle and the strict lower
-// part of Z = L^{-1} (L = R^T) below; rd / zd hold the diagonals.
-// Step s: rd[s] = sqrt(W[s,s]); row s of R = W[s, s+1:] / rd[s]; Z[s, :s] /= rd[s],
-// zd[s] = 1/rd[s]; then rank-1 updates W[i,l] -= R[s,i] R[s,l] (s < i <= l)
-// and Z[i,j] -= R[s,i] Z[s,j] (i > s, j <= s).  Rinv = Z^T.
-__device__ void chol_body(double* W, double* rd, double* zd, int* flag, const double* __restrict__ G,
-                          int ell, double* __restrict__ R, double* __restrict__ Rinv,
-                          int* status) {
-  const int tid = threadIdx.x, nt = blockDim.x;
-  const int64_t n2 = (int64_t)ell * ell;
-  for (int64_t e = tid; e < n2; e += nt) {
-    const int i = (int)(e % ell), l = (int)(e / ell);
-    W[e] = i <= l ? G[e] : 0.0;
-  }
+// Cholesky G = R^T R fused with the inverse of R, one workgroup of 1024
+// threads.  Element (r, c) of the working matrix lives in a register of
+// thread (r mod 32, c mod 32) (block-cyclic).  The upper triangle holds the
+// matrix being factored, the strict lower triangle the rows of Z = R^{-T}
+// (L = R^T, Z = L^{-1}); rows are kept unscaled and scaled at the end.
+// Step s: the owners of row s publish it (double-buffered LDS vector), every
+// thread reads the pivot d = W[s,s] and computes iv = 1/sqrt(d), then
+//   W[r,c] -= (W[s,r] iv^2) W[s,c]   for r > s and (c >= r or c < s)
+//   W[r,s] -= W[s,r] iv^2            for r > s (the Z diagonal iv enters)
+// which is the rank-1 update of the trailing matrix and the forward
+// substitution step of L Z = I.  One barrier per step.
+template <int NPT>
+__device__ __forceinline__ void chol_reg_body(const double* __restrict__ G, int ell,
+                                              double* __restrict__ R, double* __restrict__ Rinv,
+                                              int* status, double* rowbuf, double* inv,
+                                              double* sh) {
+  const int tid = threadIdx.x;
+  const int tr = tid & 31, tc = tid >> 5;
+  double w[NPT][NPT];
+#pragma unroll
+  for (int a = 0; a < NPT; ++a)
+#pragma unroll
+    for (int b = 0; b < NPT; ++b) {
+      const int r = tr + 32 * a, c = tc + 32 * b;
+      w[a][b] = (r < ell && c < ell && r <= c) ? G[(int64_t)c * ell + r] : 0.0;
+    }
   if (tid == 0) {
     double dmax = 0.0;
     int bad = 0;
@@ -224,83 +254,95 @@ __device__ void chol_body(double* W, double* rd, double* zd, int* flag, const do
       if (!isfinite(d)) bad = 1;
       if (d > dmax) dmax = d;
     }
-    flag[0] = bad ? 2 : 0;
-    rd[ell] = dmax;  // scratch: largest diagonal entry
+    // a pivot below 4 l u max_i G_ii means the sketch's condition number is
+    // beyond ~ (4 l u)^(-1/2): CholeskyQR is not reliable, fall back
+    sh[0] = bad ? -1.0 : 4.0 * ell * 2.220446049250313e-16 * dmax;
   }
   __syncthreads();
-  // breakdown when a pivot is not clearly positive relative to the largest
-  // diagonal entry (the Gram of a sketch with condition number above
-  // ~ (4 l u)^(-1/2) cannot be factored reliably)
-  const double thr = 4.0 * ell * 2.220446049250313e-16 * rd[ell];
-  for (int s = 0; s < ell && flag[0] == 0; ++s) {
-    if (tid == 0) {
-      const double d = W[(int64_t)s * ell + s];
-      if (!(d > thr) || !isfinite(d)) {
-        flag[0] = 1;
-      } else {
-        const double r = sqrt(d);
-        rd[s] = r;
-        zd[s] = 1.0 / r;
-      }
-    }
-    __syncthreads();
-    if (flag[0]) break;
-    const double inv = zd[s];
-    // row s of R (columns > s) and row s of Z (columns < s)
-    for (int l = s + 1 + tid; l < ell; l += nt) W[(int64_t)l * ell + s] *= inv;
-    for (int j = tid; j < s; j += nt) W[(int64_t)j * ell + s] *= inv;
-    __syncthreads();
-    const int w = ell - s - 1;
-    const int64_t tot = (int64_t)w * ell;
-    for (int64_t e = tid; e < tot; e += nt) {
-      const int i = s + 1 + (int)(e % w);
-      const int col = (int)(e / w);
-      if (col > s) {  // trailing update, upper part only (i <= col)
-        if (i <= col) {
-          const double rsi = W[(int64_t)i * ell + s], rsl = W[(int64_t)col * ell + s];
-          W[(int64_t)col * ell + i] -= rsi * rsl;
-        }
-      } else {  // Z[i, col] -= R[s, i] Z[s, col], col <= s
-        const double rsi = W[(int64_t)i * ell + s];
-        const double zs = col == s ? zd[s] : W[(int64_t)col * ell + s];
-        W[(int64_t)col * ell + i] -= rsi * zs;
-      }
-    }
-    __syncthreads();
-  }
-  __syncthreads();
-  if (flag[0]) {
-    if (tid == 0) atomicOr(status, flag[0]);
+  const double thr = sh[0];
+  if (thr < 0.0) {
+    if (tid == 0) atomicOr(status, 2);
     return;
   }
-  for (int64_t e = tid; e < n2; e += nt) {
-    const int i = (int)(e % ell), j = (int)(e / ell);
-    // R[i, j] (upper) = W[i, j] for i < j, rd on the diagonal
-    R[e] = i < j ? W[e] : (i == j ? rd[i] : 0.0);
-    // Rinv[i, j] = Z[j, i] for i < j (Z strict lower at W[i*ell + j])
-    Rinv[e] = i < j ? W[(int64_t)i * ell + j] : (i == j ? zd[i] : 0.0);
+  for (int s = 0; s < ell; ++s) {
+    double* row = rowbuf + (s & 1) * 256;
+#pragma unroll
+    for (int a = 0; a < NPT; ++a) {
+      if (tr + 32 * a != s) continue;
+#pragma unroll
+      for (int b = 0; b < NPT; ++b) {
+        const int c = tc + 32 * b;
+        if (c < ell) row[c] = w[a][b];
+      }
+    }
+    __syncthreads();
+    const double d = row[s];
+    if (!(d > thr) || !isfinite(d)) {
+      if (tid == 0) atomicOr(status, 1);
+      return;  // uniform: every thread read the same d
+    }
+    // 1/sqrt(d): hardware estimate refined by two Newton steps
+    double iv = __builtin_amdgcn_rsq(d);
+    iv = iv * (1.5 - 0.5 * d * iv * iv);
+    iv = iv * (1.5 - 0.5 * d * iv * iv);
+    const double iv2 = iv * iv;
+    if (tid == 0) inv[s] = iv;
+    double rc[NPT];
+#pragma unroll
+    for (int b = 0; b < NPT; ++b) {
+      const int c = tc + 32 * b;
+      rc[b] = c < ell ? row[c] : 0.0;
+    }
+#pragma unroll
+    for (int a = 0; a < NPT; ++a) {
+      if (32 * a + 31 <= s) continue;  // whole row block finished: uniform skip
+      const int r = tr + 32 * a;
+      if (r <= s || r >= ell) continue;
+      const double t = row[r] * iv2;
+#pragma unroll
+      for (int b = 0; b < NPT; ++b) {
+        const int c = tc + 32 * b;
+        if (c >= ell) continue;
+        if (c >= r || c < s)
+          w[a][b] -= t * rc[b];
+        else if (c == s)
+          w[a][b] -= t;
+      }
+    }
   }
+  __syncthreads();
+  // outputs: element (r, c) of W gives
+  //   r < c : R[r,c] = W[r,c] iv_r
+  //   r = c : R[r,r] = sqrt(W[r,r]), Rinv[r,r] = iv_r
+  //   r > c : Rinv[c,r] = Z[r,c] = W[r,c] iv_r  (and zeros in the lower parts)
+#pragma unroll
+  for (int a = 0; a < NPT; ++a)
+#pragma unroll
+    for (int b = 0; b < NPT; ++b) {
+      const int r = tr + 32 * a, c = tc + 32 * b;
+      if (r >= ell || c >= ell) continue;
+      const int64_t rc_ = (int64_t)c * ell + r, cr = (int64_t)r * ell + c;
+      if (r < c) {
+        R[rc_] = w[a][b] * inv[r];
+      } else if (r == c) {
+        R[rc_] = sqrt(w[a][b]);
+        Rinv[rc_] = inv[r];
+      } else {
+        R[rc_] = 0.0;
+        Rinv[rc_] = 0.0;
+        Rinv[cr] = w[a][b] * inv[r];
+      }
+    }
 }
 
-constexpr int kCholLdsMax = 128;
-
-__global__ void __launch_bounds__(1024) chol_lds_kernel(const double* G, int ell, double* R,
-                                                        double* Rinv, int* status,
-                                                        const int* skip) {
+template <int NPT>
+__global__ void __launch_bounds__(1024) chol_kernel(const double* G, int ell, double* R, double* Rinv,
+                                                    int* status, const int* skip) {
   if (skip && *skip) return;
-  __shared__ double W[kCholLdsMax * kCholLdsMax];
-  __shared__ double rd[kCholLdsMax + 1], zd[kCholLdsMax];
-  __shared__ int flag[1];
-  chol_body(W, rd, zd, flag, G, ell, R, Rinv, status);
-}
-
-__global__ void __launch_bounds__(1024) chol_global_kernel(const double* G, int ell, double* R,
-                                                           double* Rinv, double* W, int* status,
-                                                           const int* skip) {
-  if (skip && *skip) return;
-  __shared__ double rd[257], zd[256];
-  __shared__ int flag[1];
-  chol_body(W, rd, zd, flag, G, ell, R, Rinv, status);
+  __shared__ double rowbuf[512];
+  __shared__ double inv[256];
+  __shared__ double sh[2];
+  chol_reg_body<NPT>(G, ell, R, Rinv, status, rowbuf, inv, sh);
 }
 
 // ---------------------------------------------------------------------------
@@ -518,10 +560,16 @@ __global__ void fill_int_kernel(int* p, int n, int v) {
 // ---------------------------------------------------------------------------
 hipError_t launch_sum_partials(const Partials& p, int ell, int ncols, double* out64, float* out32,
                                int64_t ld, hipStream_t st) {
-  const int64_t total = p.n * ncols;
-  if (total == 0) return hipSuccess;
-  sum_partials_kernel<<<dim3((unsigned)((total + 255) / 256)), dim3(256), 0, st>>>(p, ell, ncols, out64,
-                                                                                    out32, ld);
+  if (p.n == 0 || ncols == 0) return hipSuccess;
+  // every segment list must fit: at most 8 * (gx + 1) entries per tile
+  if (8 * (p.gx + 1) > kSegMax) return hipErrorInvalidValue;
+  dim3 grid((unsigned)p.tiles, (unsigned)((ncols + kSumCols - 1) / kSumCols));
+  if (p.elem == 8)
+    sum_partials_kernel<double><<<grid, dim3(256), 0, st>>>(p, (const double*)p.ptr, ell, ncols, out64,
+                                                            out32, ld);
+  else
+    sum_partials_kernel<float><<<grid, dim3(256), 0, st>>>(p, (const float*)p.ptr, ell, ncols, out64,
+                                                           out32, ld);
   return hipGetLastError();
 }
 
@@ -543,8 +591,7 @@ hipError_t launch_xty(const double* Xa, int64_t lda, const double* Xb, int64_t l
 
 hipError_t launch_reduce(const double* part, int splits, int64_t elems, double* out, const int* skip,
                          hipStream_t st) {
-  reduce_kernel<<<dim3((unsigned)((elems + 255) / 256)), dim3(256), 0, st>>>(part, splits, elems, out,
-                                                                             skip);
+  reduce_kernel<<<dim3((unsigned)((elems + 63) / 64)), dim3(256), 0, st>>>(part, splits, elems, out, skip);
   return hipGetLastError();
 }
 
@@ -560,13 +607,17 @@ hipError_t launch_rowmat(const double* X, int64_t ldx, int64_t rows, int ell, co
 
 hipError_t launch_chol(const double* G, int ell, double* R, double* Rinv, int* status,
                        const int* skip, hipStream_t st) {
-  // ell > 128: the working matrix lives in the second half of R's storage.
-  if (ell <= kCholLdsMax) {
-    chol_lds_kernel<<<dim3(1), dim3(1024), 0, st>>>(G, ell, R, Rinv, status, skip);
-  } else {
-    chol_global_kernel<<<dim3(1), dim3(1024), 0, st>>>(G, ell, R, Rinv, R + (int64_t)ell * ell,
-                                                       status, skip);
-  }
+  const int npt = (ell + 31) / 32;
+  if (npt <= 4)
+    chol_kernel<4><<<dim3(1), dim3(1024), 0, st>>>(G, ell, R, Rinv, status, skip);
+  else if (npt == 5)
+    chol_kernel<5><<<dim3(1), dim3(1024), 0, st>>>(G, ell, R, Rinv, status, skip);
+  else if (npt == 6)
+    chol_kernel<6><<<dim3(1), dim3(1024), 0, st>>>(G, ell, R, Rinv, status, skip);
+  else if (npt == 7)
+    chol_kernel<7><<<dim3(1), dim3(1024), 0, st>>>(G, ell, R, Rinv, status, skip);
+  else
+    chol_kernel<8><<<dim3(1), dim3(1024), 0, st>>>(G, ell, R, Rinv, status, skip);
   return hipGetLastError();
 }
 
