@@ -140,6 +140,9 @@ int corutv_decompose(corutv_ctx* ctx, const corutv_mat* A, int32_t k, int32_t p,
 
 /* ALM-CoRUTV robust PCA (Sec. 4, Algorithm 2; operators of eq. 12).
  *   M      m x n F32 input (read only).  S: m x n F32 output (the sparse part).
+ *          The iteration state (multiplier, next CoR-UTV input) and every
+ *          CoR-UTV of the loop are FP64 (opts->prec is ignored): the shrink
+ *          threshold lambda/mu falls below FP32 resolution late in the run.
  *   L      nullable m x n F32 output (the low-rank part, formed densely).
  *   lambda <= 0 selects 1/sqrt(max(m, n)).
  *   k, p, q: the CoR-UTV of every iteration (l = k + p <= 256).
@@ -159,6 +162,8 @@ typedef struct corutv_rpca_info {
 int corutv_rpca(corutv_ctx* ctx, const corutv_mat* M, double lambda, int32_t k, int32_t p,
                 int32_t q, int32_t max_iter, double tol, uint64_t seed, const corutv_opts* opts,
                 corutv_mat* L, corutv_mat* S, corutv_rpca_info* info);
+/* Workspace bytes corutv_rpca needs for an m x n input (0 for invalid sizes). */
+uint64_t corutv_rpca_workspace_bytes(int64_t m, int64_t n, int32_t k, int32_t p, int32_t q);
 
 /* ---- serving ------------------------------------------------------------
  * Non-blocking decompositions with continuous batching: requests queue on the

@@ -98,6 +98,7 @@ def _load():
         "corutv_sketch": (ctypes.c_int, [P, MP, I32, I32, P, I64, I32, P, I64]),
         "corutv_tsqr": (ctypes.c_int, [P, P, I64, I32, I64, P, I64, P, I64, ctypes.POINTER(I32)]),
         "corutv_qrcp": (ctypes.c_int, [P, I32, P, I64, P, P, P]),
+        "corutv_rpca_workspace_bytes": (U64, [I64, I64, I32, I32, I32]),
         "corutv_pass_timing": (ctypes.c_int, [P, I32, I32]),
         "corutv_get_pass_stats": (ctypes.c_int, [P, ctypes.POINTER(PassStats)]),
     }
@@ -140,6 +141,10 @@ def mat(t):
 
 def workspace_bytes(m, n, k, p, q, prec="f64"):
     return int(lib.corutv_workspace_bytes(m, n, k, p, q, PREC[prec]))
+
+
+def rpca_workspace_bytes(m, n, k, p, q):
+    return int(lib.corutv_rpca_workspace_bytes(m, n, k, p, q))
 
 
 class Context:

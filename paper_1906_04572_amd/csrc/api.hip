@@ -964,11 +964,181 @@ int corutv_destroy(corutv_ctx* ctx) {
 
 }  // extern "C"
 
+// ---------------------------------------------------------------------------
+// ALM-CoRUTV (Sec. 4, Algorithm 2)
+namespace {
+
+struct RpcaPlan {
+  Plan dec;
+  int ell = 0;
+  size_t o_y = 0, o_b = 0, o_u = 0, o_v = 0, o_t = 0, o_tt = 0, o_p = 0, o_q = 0, o_part = 0,
+         o_sum = 0;
+  size_t total = 0;
+};
+
+bool make_rpca_plan(int64_t m, int64_t n, int k, int p, int q, RpcaPlan* rp) {
+  if (!make_plan(m, n, k, p, q, P_F64, &rp->dec)) return false;
+  const int ell = k + p;
+  rp->ell = ell;
+  size_t off = rp->dec.total;
+  auto take = [&](size_t bytes) {
+    const size_t o = off;
+    off += align256(bytes);
+    return o;
+  };
+  rp->o_y = take((size_t)m * n * 8);
+  rp->o_b = take((size_t)m * n * 8);
+  rp->o_u = take((size_t)m * ell * 8);
+  rp->o_v = take((size_t)n * ell * 8);
+  rp->o_t = take((size_t)ell * ell * 8);
+  rp->o_tt = take((size_t)ell * ell * 8);
+  rp->o_p = take((size_t)m * ell * 8);
+  rp->o_q = take((size_t)n * ell * 8);
+  rp->o_part = take((size_t)rpca_partial_blocks() * 8);
+  rp->o_sum = take(4 * 8);
+  rp->total = off;
+  return true;
+}
+
+}  // namespace
+
+extern "C" uint64_t corutv_rpca_workspace_bytes(int64_t m, int64_t n, int32_t k, int32_t p, int32_t q) {
+  RpcaPlan rp;
+  if (!make_rpca_plan(m, n, k, p, q, &rp)) return 0;
+  return rp.total;
+}
+
 extern "C" int corutv_rpca(corutv_ctx* ctx, const corutv_mat* M, double lambda, int32_t k, int32_t p,
                            int32_t q, int32_t max_iter, double tol, uint64_t seed,
                            const corutv_opts* opts, corutv_mat* L, corutv_mat* S,
                            corutv_rpca_info* info) {
-  (void)ctx; (void)M; (void)lambda; (void)k; (void)p; (void)q; (void)max_iter; (void)tol;
-  (void)seed; (void)opts; (void)L; (void)S; (void)info;
-  return CORUTV_E_INVAL;
+  int rc = guard(ctx);
+  if (rc) return rc;
+  (void)opts;
+  if (!mat_ok(M) || !mat_ok(S) || M->dtype != CORUTV_F32 || S->dtype != CORUTV_F32) return CORUTV_E_INVAL;
+  const int64_t m = M->rows, n = M->cols;
+  if (S->rows != m || S->cols != n) return CORUTV_E_INVAL;
+  if (L && (!mat_ok(L) || L->dtype != CORUTV_F32 || L->rows != m || L->cols != n)) return CORUTV_E_INVAL;
+  if (k < 1 || p < 0 || q < 0 || q > 30 || max_iter < 1 || (int64_t)k + p > std::min(m, n) || k + p > 256)
+    return CORUTV_E_INVAL;
+  RpcaPlan rp;
+  if (!make_rpca_plan(m, n, k, p, q, &rp)) return CORUTV_E_INVAL;
+  if (rp.total > ctx->ws_bytes) return CORUTV_E_NOMEM;
+  if (!(lambda > 0)) lambda = 1.0 / std::sqrt((double)std::max(m, n));
+  const int ell = rp.ell;
+  std::lock_guard<std::mutex> lk(ctx->run_mu);
+  hipStream_t s = ctx->streams[0];
+  char* ws = ctx->ws;
+  double* Y = (double*)(ws + rp.o_y);
+  double* B = (double*)(ws + rp.o_b);
+  double* U = (double*)(ws + rp.o_u);
+  double* V = (double*)(ws + rp.o_v);
+  double* T = (double*)(ws + rp.o_t);
+  double* Tt = (double*)(ws + rp.o_tt);
+  double* Pm = (double*)(ws + rp.o_p);
+  double* Qm = (double*)(ws + rp.o_q);
+  double* part = (double*)(ws + rp.o_part);
+  double* sum = (double*)(ws + rp.o_sum);
+  const int nb = rpca_partial_blocks();
+  // Y and B share M's layout, packed
+  const int lay = M->layout;
+  const int64_t ldi = lay == CORUTV_COL_MAJOR ? m : n;
+  hipEvent_t e0, e1;
+  if (hipEventCreate(&e0) != hipSuccess || hipEventCreate(&e1) != hipSuccess) return poison(ctx);
+  hipEventRecord(e0, s);
+  HIPOK(hipMemsetAsync(Y, 0, (size_t)m * n * 8, s));
+  HIPOK(launch_widen((const float*)M->ptr, lay, M->ld, m, n, B, ldi, s));
+  // ||M||_F
+  HIPOK(launch_sumsq((const float*)M->ptr, lay, M->ld, m, n, part, s));
+  HIPOK(launch_reduce(part, nb, 1, sum, nullptr, s));
+  // decomposition arguments shared by every CoR-UTV of the loop
+  DecArgs d;
+  d.U = corutv_mat{U, m, ell, m, CORUTV_F64, CORUTV_COL_MAJOR};
+  d.V = corutv_mat{V, n, ell, n, CORUTV_F64, CORUTV_COL_MAJOR};
+  d.T = T;
+  d.ldt = ell;
+  d.k = k;
+  d.p = p;
+  d.q = q;
+  d.seed = seed;
+  d.opts.prec = P_F64;
+  d.opts.tri = CORUTV_TRI_AUTO;
+  Enqueued eq;
+  corutv_mat Bm{B, m, n, ldi, CORUTV_F64, lay};
+  // mu_0 = 1.25 / ||M||_2, with ||M||_2 estimated by T[0,0] of a CoR-UTV of M
+  d.A = Bm;
+  d.sub = 0xFFFF;
+  rc = enqueue_decompose(ctx, rp.dec, ws, d, s, &eq);
+  if (rc != CORUTV_OK) return rc == CORUTV_E_DEVICE ? poison(ctx) : rc;
+  double h[2] = {0, 0};
+  int hst[kMaxQr];
+  HIPOK(hipMemcpyAsync(h, T, 8, hipMemcpyDeviceToHost, s));
+  HIPOK(hipMemcpyAsync(h + 1, sum, 8, hipMemcpyDeviceToHost, s));
+  HIPOK(hipMemcpyAsync(hst, eq.dev_status, sizeof(int) * eq.nqr, hipMemcpyDeviceToHost, s));
+  if (hipStreamSynchronize(s) != hipSuccess) return poison(ctx);
+  if (finish_info(eq, hst, nullptr, nullptr) != CORUTV_OK || !(h[0] > 0) || !std::isfinite(h[1]))
+    return CORUTV_E_NUMERIC;
+  const double normM = std::sqrt(h[1]);
+  const double mu0 = 1.25 / h[0];
+  const double mu_bar = 1e7 * mu0;
+  const double rho = 1.5;
+  double mu = mu0;
+  const bool lower = m < n;  // AUTO orientation: lower T for the wide problem
+  int iters = 0;
+  double zeta = -1.0, mu_last = mu;
+  for (int j = 0; j < max_iter; ++j) {
+    d.A = Bm;
+    d.sub = (uint32_t)j;
+    rc = enqueue_decompose(ctx, rp.dec, ws, d, s, &eq);
+    if (rc != CORUTV_OK) return rc == CORUTV_E_DEVICE ? poison(ctx) : rc;
+    // rank-r factors: upper T -> P = U, Q = V T^T; lower T -> P = U T, Q = V
+    MatOut o;
+    o.ptr = lower ? Pm : Qm;
+    o.ld = lower ? m : n;
+    HIPOK(launch_copy_tri(T, ell, 1, lower ? 1 : 0, Tt, ell, s));
+    if (lower)
+      HIPOK(launch_rowmat(U, m, m, ell, T, ell, nullptr, o, 0, MatOut(), 0, nullptr, s));
+    else
+      HIPOK(launch_rowmat(V, n, n, ell, Tt, ell, nullptr, o, 0, MatOut(), 0, nullptr, s));
+    const double* P = lower ? Pm : U;
+    const double* Q = lower ? V : Qm;
+    const double mu_next = std::min(rho * mu, mu_bar);
+    const bool last = j + 1 == max_iter;
+    HIPOK(launch_rpca_elementwise((const float*)M->ptr, lay, M->ld, (float*)S->ptr, S->layout, S->ld, Y,
+                                  ldi, last ? nullptr : B, ldi, L ? (float*)L->ptr : nullptr,
+                                  L ? L->layout : CORUTV_COL_MAJOR, L ? L->ld : 1, m, n, P, m, Q, n, T,
+                                  ell, ell, mu, mu_next, lambda, part, s));
+    HIPOK(launch_reduce(part, nb, 1, sum, nullptr, s));
+    iters = j + 1;
+    mu_last = mu;
+    mu = mu_next;
+    if (tol > 0 || last) {
+      double zs = 0;
+      HIPOK(hipMemcpyAsync(&zs, sum, 8, hipMemcpyDeviceToHost, s));
+      if (hipStreamSynchronize(s) != hipSuccess) return poison(ctx);
+      zeta = std::sqrt(zs) / normM;
+      if (!std::isfinite(zeta)) return CORUTV_E_NUMERIC;
+      if (tol > 0 && zeta < tol) break;
+    }
+  }
+  // final rank: diagonal entries of the last T above 1/mu_last
+  std::vector<double> Th((size_t)ell * ell);
+  HIPOK(hipMemcpyAsync(Th.data(), T, Th.size() * 8, hipMemcpyDeviceToHost, s));
+  hipEventRecord(e1, s);
+  if (hipStreamSynchronize(s) != hipSuccess) return poison(ctx);
+  float ms = 0;
+  hipEventElapsedTime(&ms, e0, e1);
+  hipEventDestroy(e0);
+  hipEventDestroy(e1);
+  int r = 0;
+  while (r < ell && Th[(size_t)r * ell + r] > 1.0 / mu_last) ++r;
+  if (info) {
+    info->iters = iters;
+    info->final_rank = r;
+    info->zeta = zeta;
+    info->mu0 = mu0;
+    info->mu = mu;
+    info->gpu_ms = ms;
+  }
+  return CORUTV_OK;
 }

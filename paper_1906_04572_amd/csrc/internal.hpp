@@ -115,30 +115,20 @@ hipError_t launch_residual(const void* A, int dtype, int64_t lda, int64_t R, int
                            const double* B, int64_t ldb, const double* V, int64_t ldv, int ell,
                            double* part, hipStream_t st);
 
-// Flag NaN/Inf in a dense matrix (any layout): sets bit 2 of *status.
-hipError_t launch_check_finite(const void* A, int dtype, int64_t rows, int64_t cols, int64_t ld,
-                               int* status, hipStream_t st);
-
-// RPCA elementwise step (see rpca.hip).
-struct RpcaStep {
-  const float* M;
-  float* S;
-  float* Y;
-  float* B;        // next CoR-UTV input (M - S + Y/mu_next)
-  float* Lout;     // nullable dense L
-  int64_t ld;      // column-major leading dimension of M, S, Y, B, L (all same)
-  int64_t m, n;
-  const double* Ub;  // m x ell, column-major, FP64 (U)
-  int64_t ldu;
-  const double* Wt;  // n x ell, column-major FP64: W = V T^T, so L = U(:,1:r) W(:,1:r)^T
-  int64_t ldw;
-  const double* T;   // ell x ell FP64 (for the rank decision)
-  int ell;
-  const double* mu;  // device scalars: mu[0] = mu_j, mu[1] = mu_{j+1}
-  double lambda;
-  double* part;      // per-block residual partials
-};
-int rpca_blocks(int64_t m, int64_t n);
-hipError_t launch_rpca_step(const RpcaStep& a, hipStream_t st);
+// RPCA elementwise step (rpca.hip): S, Y (and B for the next iteration, L if
+// non-null) from M and the rank-r factors P (m x ell), Q (n x ell) with r the
+// number of diagonal entries of T above 1/mu; per-block sums of the squared
+// residual M - L - S go to part[rpca_partial_blocks()].
+int rpca_partial_blocks();
+hipError_t launch_rpca_elementwise(const float* M, int lay_m, int64_t ldm, float* S, int lay_s,
+                                   int64_t lds, double* Y, int64_t ldy, double* B, int64_t ldb, float* L,
+                                   int lay_l, int64_t ldl, int64_t m, int64_t n, const double* P,
+                                   int64_t ldp, const double* Q, int64_t ldq, const double* T,
+                                   int64_t ldt, int ell, double mu, double mu_next, double lambda,
+                                   double* part, hipStream_t st);
+hipError_t launch_sumsq(const float* X, int lay, int64_t ld, int64_t m, int64_t n, double* part,
+                        hipStream_t st);
+hipError_t launch_widen(const float* X, int lay, int64_t ld, int64_t m, int64_t n, double* B, int64_t ldb,
+                        hipStream_t st);
 
 }  // namespace corutv

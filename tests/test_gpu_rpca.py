@@ -1,0 +1,91 @@
+"""GPU ALM-CoRUTV robust PCA (Sec. 4, Algorithm 2) against the float64 oracle
+and against the planted low-rank + sparse truth.
+
+The float32 inputs are generated with factors and corruption values on a
+2^-6 grid, so that M = L + S holds exactly in float32: exact support recovery
+is then well defined (with generic float32 rounding the input is only
+approximately low-rank + sparse, and the late shrink thresholds lambda/mu ~
+1e-6 fall below its rounding residue).
+
+The rank decisions of the iteration are discrete, so trajectories may differ
+by rounding; the endpoints are compared: the support of S (bit-exact set of
+nonzeros), the recovered rank, ||L - L_true||_F / ||L_true||_F <= 1e-5 and the
+relative residual zeta.
+"""
+import numpy as np
+import pytest
+import torch
+
+from oracle.rpca import alm_corutv
+from workloads import low_rank_plus_sparse
+
+pytestmark = pytest.mark.gpu
+GRID = 2.0 ** -6
+
+
+@pytest.fixture(scope="module")
+def ctx():
+    import paper_1906_04572_amd as cu
+
+    c = cu.Context(workspace_bytes=cu.rpca_workspace_bytes(76800, 300, 5, 5, 1) + (64 << 20))
+    yield c
+    c.close()
+
+
+def _say(*a):
+    print("[case]", *a, flush=True)
+
+
+def _col(X):
+    return torch.from_numpy(np.ascontiguousarray(X.T, dtype=np.float32)).cuda().t()
+
+
+def test_frames_shape_reduced_matches_oracle(ctx):
+    _say("rpca 7680x300")
+    M, L, S = low_rank_plus_sparse(7680, 300, 5, 0.05, 50.0, seed=4, grid=GRID)
+    assert np.array_equal(M.astype(np.float32).astype(np.float64), M)
+    Lg, Sg, info = ctx.rpca(_col(M), 5, 5, 1, seed=4, max_iter=50)
+    Lg, Sg = Lg.cpu().numpy().astype(np.float64), Sg.cpu().numpy().astype(np.float64)
+    Lo, So, oinfo = alm_corutv(M, 5, 5, 1, seed=4, max_iter=50)
+    assert info["final_rank"] == 5 == oinfo["ranks"][-1]
+    assert np.array_equal(Sg != 0, S != 0)
+    assert np.array_equal(Sg != 0, So != 0)
+    assert np.linalg.norm(Lg - L) / np.linalg.norm(L) <= 1e-5
+    assert abs(info["mu0"] - oinfo["mu0"]) <= 1e-5 * oinfo["mu0"]
+    assert info["iters"] == 50
+
+
+def test_table1_n1000_row(ctx):
+    _say("rpca table-1 n=1000")
+    M, L, S = low_rank_plus_sparse(1000, 1000, 50, 0.05, 80.0, seed=1000, values="pm", grid=GRID)
+    assert np.array_equal(M.astype(np.float32).astype(np.float64), M)
+    Lg, Sg, info = ctx.rpca(_col(M), 50, 50, 1, seed=7, max_iter=60, tol=1e-5)
+    Lg, Sg = Lg.cpu().numpy().astype(np.float64), Sg.cpu().numpy().astype(np.float64)
+    assert info["final_rank"] == 50
+    assert np.count_nonzero(Sg) == 50000
+    assert np.array_equal(Sg != 0, S != 0)
+    assert info["zeta"] < 1e-5
+    assert 8 <= info["iters"] <= 16
+
+
+def test_frames_full_76800x300(ctx):
+    _say("rpca 76800x300 50 iterations")
+    M, L, S = low_rank_plus_sparse(76800, 300, 5, 0.05, 50.0, seed=4, grid=GRID)
+    assert np.array_equal(M.astype(np.float32).astype(np.float64), M)
+    Lg, Sg, info = ctx.rpca(_col(M), 5, 5, 1, seed=4, max_iter=50)
+    Lg, Sg = Lg.cpu().numpy().astype(np.float64), Sg.cpu().numpy().astype(np.float64)
+    assert info["final_rank"] == 5
+    assert np.array_equal(Sg != 0, S != 0)
+    assert np.linalg.norm(Lg - L) / np.linalg.norm(L) <= 1e-5
+    print("rpca 76800x300: %.2f ms, zeta %.3e" % (info["gpu_ms"], info["zeta"]))
+
+
+def test_rpca_bad_arguments(ctx):
+    import paper_1906_04572_amd as cu
+
+    _say("rpca bad args")
+    M = torch.zeros((100, 50), dtype=torch.float64, device="cuda")
+    with pytest.raises(cu.CorutvError):
+        ctx.rpca(M, 5, 5, 1, seed=1)  # float64 input
+    with pytest.raises(cu.CorutvError):
+        ctx.rpca(M.float(), 40, 20, 1, seed=1)  # l > min(m, n)

@@ -73,11 +73,19 @@ def sec51_matrix(n, k, seed):
     return (U * sig) @ V.T + 0.1 * sig[-1] * E, sig
 
 
-def low_rank_plus_sparse(m, n, r, frac, amp, seed, values="uniform", dtype=np.float64):
-    """Returns (M, L, S)."""
+def low_rank_plus_sparse(m, n, r, frac, amp, seed, values="uniform", dtype=np.float64, grid=None):
+    """Returns (M, L, S).
+
+    grid: if given (e.g. 2**-6), the Gaussian factors and the corruption values
+    are rounded to multiples of it, so that M = L + S holds exactly in float32
+    (products and sums stay within 24 significant bits for the sizes used):
+    float32 data is then exactly low-rank plus sparse."""
     rng = _rng(seed)
     X = rng.standard_normal((m, r))
     Y = rng.standard_normal((n, r))
+    if grid:
+        X = np.round(X / grid) * grid
+        Y = np.round(Y / grid) * grid
     L = X @ Y.T
     count = int(round(frac * m * n))
     pos = rng.choice(m * n, size=count, replace=False)
@@ -85,6 +93,9 @@ def low_rank_plus_sparse(m, n, r, frac, amp, seed, values="uniform", dtype=np.fl
         vals = rng.uniform(-amp, amp, size=count)
     else:
         vals = amp * rng.choice(np.array([-1.0, 1.0]), size=count)
+    if grid:
+        vals = np.round(vals / grid) * grid
+        vals[vals == 0] = grid
     S = np.zeros(m * n)
     S[pos] = vals
     S = S.reshape(m, n)
