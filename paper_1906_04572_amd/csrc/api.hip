@@ -238,7 +238,6 @@ int enqueue_decompose(corutv_ctx* ctx, const Plan& pl, char* ws, const DecArgs& 
   const int ell = pl.ell, ellp = pl.ellp;
   const int prec = d.opts.prec;
   const bool f64 = prec == P_F64;
-  if (prec == P_BF16 || prec == P_BF16X3) return CORUTV_E_INVAL;  // not in this build yet
   const bool transposed = m < n;
   const int64_t mm = pl.mm, nn = pl.nn;
   // big row-major view of A
@@ -572,7 +571,7 @@ int corutv_sketch(corutv_ctx* ctx, const corutv_mat* A, int32_t trans, int32_t p
   if (rc) return rc;
   if (!mat_ok(A) || !X || !Y || ell < 1 || ell > 256 || (trans != 0 && trans != 1))
     return CORUTV_E_INVAL;
-  if (prec != P_F64 && prec != P_F32) return CORUTV_E_INVAL;
+  if (prec < P_F64 || prec > P_BF16X3) return CORUTV_E_INVAL;
   if ((prec == P_F64) != (A->dtype == CORUTV_F64)) return CORUTV_E_INVAL;
   const int64_t m = A->rows, n = A->cols;
   const int64_t klen = trans ? m : n, nout = trans ? n : m;

@@ -269,6 +269,221 @@ __global__ void __launch_bounds__(256) sketch_kernel(SketchArgs a) {
   }
 }
 
+// ---------------------------------------------------------------------------
+// Reduced-precision forms (float A and operands): BF16 rounds both operands to
+// nearest-even bfloat16 in the loader; BF16X3 splits x = hi + lo (hi =
+// bf16(x), lo = bf16(x - hi)) and accumulates lo*hi + hi*lo + hi*hi, small
+// terms first.  FP32 accumulation on v_mfma_f32_16x16x32_bf16: lane (g, qd)
+// supplies k = 8g..8g+7 of a 32-k block for row qd of the skinny operand and
+// for output row qd of A; accumulator slot i holds row 4g + i.
+typedef __bf16 bf8 __attribute__((ext_vector_type(8)));
+
+__device__ __forceinline__ void split8(const float* x, bf8& hi, bf8& lo, bool want_lo) {
+#pragma unroll
+  for (int e = 0; e < 8; ++e) {
+    const __bf16 h = (__bf16)x[e];
+    hi[e] = h;
+    if (want_lo) lo[e] = (__bf16)(x[e] - (float)h);
+  }
+}
+
+template <int MB, bool TRANS, int NB, bool X3>
+__global__ void __launch_bounds__(256) sketch_bf16_kernel(SketchArgs a) {
+  constexpr int KC = 32;                 // k values per LDS stage = one MFMA block
+  constexpr int ELLP = MB * 16;
+  constexpr int LDK = KC + 4;
+  constexpr int TW = 64 * NB;
+  constexpr int VPR = KC / 4;
+  constexpr int SPASS = (ELLP * VPR + 255) / 256;
+  __shared__ __attribute__((aligned(16))) float lds_s[2][ELLP * LDK];
+
+  const int tid = threadIdx.x;
+  const int lane = tid & 63, wave = tid >> 6;
+  const int g = lane >> 4, qd = lane & 15;
+  const int x = blockIdx.x & 7;
+  const int jw = blockIdx.x >> 3;
+  const float* __restrict__ A = (const float*)a.A;
+  const float* __restrict__ S = (const float*)a.S;
+  float* __restrict__ P = (float*)a.P;
+  const int64_t U = (int64_t)a.tiles * a.nkx;
+  int64_t u = (int64_t)jw * U / a.gx;
+  const int64_t uend = (int64_t)(jw + 1) * U / a.gx;
+  const int tfirst = (int)(u / a.nkx);
+  int iter = 0;
+
+  while (u < uend) {
+    const int t = (int)(u / a.nkx);
+    const int kb0 = (int)(u % a.nkx);
+    const int kb1 = (int)min((int64_t)a.nkx, kb0 + (uend - u));
+    const int gk0 = x * a.nkx + kb0;
+    const int gk1 = min(x * a.nkx + kb1, a.nk);
+    const int64_t nbase = (int64_t)t * TW + wave * 16 * NB;
+    f4 acc[MB][NB];
+#pragma unroll
+    for (int mb = 0; mb < MB; ++mb)
+#pragma unroll
+      for (int nb = 0; nb < NB; ++nb) acc[mb][nb] = f4{0, 0, 0, 0};
+
+    if (gk0 < gk1) {
+      f4 sreg[SPASS];
+      float bcur[NB * 8], bnext[NB * 8];  // [nb][8 k values]
+      auto load_skinny = [&](int kb) {
+#pragma unroll
+        for (int p = 0; p < SPASS; ++p) {
+          const int v = tid + 256 * p;
+          const int c = v / VPR, kv = v % VPR;
+          const int64_t k = (int64_t)kb * KC + kv * 4;
+          f4 r = {0, 0, 0, 0};
+          if (c < ELLP) {
+            const float* src = S + (int64_t)c * a.lds + k;
+            if (k + 4 <= a.K) {
+              r = *(const f4*)src;
+            } else {
+#pragma unroll
+              for (int e = 0; e < 4; ++e)
+                if (k + e < a.K) r[e] = src[e];
+            }
+          }
+          sreg[p] = r;
+        }
+      };
+      auto store_skinny = [&](int buf) {
+#pragma unroll
+        for (int p = 0; p < SPASS; ++p) {
+          const int v = tid + 256 * p;
+          const int c = v / VPR, kv = v % VPR;
+          if (c < ELLP) *(f4*)&lds_s[buf][c * LDK + kv * 4] = sreg[p];
+        }
+      };
+      auto load_b = [&](int kb, float* b) {
+#pragma unroll
+        for (int e = 0; e < NB * 8; ++e) b[e] = 0.f;
+        if constexpr (!TRANS) {
+#pragma unroll
+          for (int nb = 0; nb < NB; ++nb) {
+            const int64_t n = nbase + nb * 16 + qd;
+            const int64_t k = (int64_t)kb * KC + 8 * g;
+            float* d = b + nb * 8;
+            if (n < a.N) {
+              const float* src = A + n * a.lda + k;
+              if (a.vec && k + 8 <= a.K) {
+                const f4 v0 = *(const f4*)src;
+                const f4 v1 = *(const f4*)(src + 4);
+                d[0] = v0[0]; d[1] = v0[1]; d[2] = v0[2]; d[3] = v0[3];
+                d[4] = v1[0]; d[5] = v1[1]; d[6] = v1[2]; d[7] = v1[3];
+              } else {
+#pragma unroll
+                for (int e = 0; e < 8; ++e)
+                  if (k + e < a.K) d[e] = src[e];
+              }
+            }
+          }
+        } else {
+#pragma unroll
+          for (int tt = 0; tt < 8; ++tt) {
+            const int64_t k = (int64_t)kb * KC + 8 * g + tt;
+            const int64_t n0 = nbase + NB * qd;
+            if (k < a.K) {
+              const float* src = A + k * a.lda + n0;
+              if (NB == 2 && a.vec && n0 + 2 <= a.N) {
+                const f2 vv = *(const f2*)src;
+                b[tt] = vv[0];
+                b[8 * (NB - 1) + tt] = vv[1];
+              } else {
+#pragma unroll
+                for (int e = 0; e < NB; ++e)
+                  if (n0 + e < a.N) b[8 * e + tt] = src[e];
+              }
+            }
+          }
+        }
+      };
+
+      load_skinny(gk0);
+      load_b(gk0, bcur);
+      for (int kb = gk0; kb < gk1; ++kb, ++iter) {
+        const int buf = iter & 1;
+        store_skinny(buf);
+        __syncthreads();
+        if (kb + 1 < gk1) {
+          load_skinny(kb + 1);
+          load_b(kb + 1, bnext);
+        }
+        bf8 bh[NB], bl[NB];
+#pragma unroll
+        for (int nb = 0; nb < NB; ++nb) split8(bcur + nb * 8, bh[nb], bl[nb], X3);
+        const float* ls = &lds_s[buf][0];
+#pragma unroll
+        for (int mb = 0; mb < MB; ++mb) {
+          const float* src = ls + (mb * 16 + qd) * LDK + 8 * g;
+          const f4 v0 = *(const f4*)src;
+          const f4 v1 = *(const f4*)(src + 4);
+          const float sv[8] = {v0[0], v0[1], v0[2], v0[3], v1[0], v1[1], v1[2], v1[3]};
+          bf8 sh, sl;
+          split8(sv, sh, sl, X3);
+#pragma unroll
+          for (int nb = 0; nb < NB; ++nb) {
+            if constexpr (X3) {
+              acc[mb][nb] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(sl, bh[nb], acc[mb][nb], 0, 0, 0);
+              acc[mb][nb] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(sh, bl[nb], acc[mb][nb], 0, 0, 0);
+            }
+            acc[mb][nb] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(sh, bh[nb], acc[mb][nb], 0, 0, 0);
+          }
+        }
+        if (kb + 1 < gk1) {
+#pragma unroll
+          for (int e = 0; e < NB * 8; ++e) bcur[e] = bnext[e];
+        }
+      }
+    }
+    const int64_t slot = ((int64_t)x * a.gx + jw) * a.maxslot + (t - tfirst);
+    float* dst = P + slot * (int64_t)ELLP * TW;
+#pragma unroll
+    for (int mb = 0; mb < MB; ++mb)
+#pragma unroll
+      for (int i = 0; i < 4; ++i) {
+        const int c = mb * 16 + 4 * g + i;
+        if constexpr (!TRANS) {
+#pragma unroll
+          for (int nb = 0; nb < NB; ++nb) dst[(int64_t)c * TW + wave * 16 * NB + nb * 16 + qd] = acc[mb][nb][i];
+        } else {
+#pragma unroll
+          for (int nb = 0; nb < NB; ++nb) dst[(int64_t)c * TW + wave * 16 * NB + NB * qd + nb] = acc[mb][nb][i];
+        }
+      }
+    u += kb1 - kb0;
+  }
+}
+
+template <int MB, bool TRANS, bool X3>
+void* bf16_ptr() {
+  constexpr int NB = MB <= 8 ? 2 : 1;
+  return (void*)&sketch_bf16_kernel<MB, TRANS, NB, X3>;
+}
+
+template <bool TRANS, bool X3>
+void* pick_bf16(int mb) {
+  switch (mb) {
+    case 1: return bf16_ptr<1, TRANS, X3>();
+    case 2: return bf16_ptr<2, TRANS, X3>();
+    case 3: return bf16_ptr<3, TRANS, X3>();
+    case 4: return bf16_ptr<4, TRANS, X3>();
+    case 5: return bf16_ptr<5, TRANS, X3>();
+    case 6: return bf16_ptr<6, TRANS, X3>();
+    case 7: return bf16_ptr<7, TRANS, X3>();
+    case 8: return bf16_ptr<8, TRANS, X3>();
+    case 9: return bf16_ptr<9, TRANS, X3>();
+    case 10: return bf16_ptr<10, TRANS, X3>();
+    case 11: return bf16_ptr<11, TRANS, X3>();
+    case 12: return bf16_ptr<12, TRANS, X3>();
+    case 13: return bf16_ptr<13, TRANS, X3>();
+    case 14: return bf16_ptr<14, TRANS, X3>();
+    case 15: return bf16_ptr<15, TRANS, X3>();
+    case 16: return bf16_ptr<16, TRANS, X3>();
+    default: return nullptr;
+  }
+}
+
 template <typename T, int MB, bool TRANS>
 void* kernel_ptr() {
   constexpr int NB = MB <= 8 ? 2 : 1;
@@ -368,9 +583,16 @@ hipError_t launch_sketch(int prec, int trans, const void* A, int64_t lda, int64_
                          Partials* part, int num_cu, hipStream_t st) {
   const bool f64 = prec == P_F64;
   const int mb = ellp / 16;
-  void* fn = f64 ? (trans ? pick<double, true>(mb) : pick<double, false>(mb))
-                 : (trans ? pick<float, true>(mb) : pick<float, false>(mb));
-  if (!fn || (prec != P_F64 && prec != P_F32)) return hipErrorInvalidValue;
+  void* fn = nullptr;
+  if (prec == P_F64)
+    fn = trans ? pick<double, true>(mb) : pick<double, false>(mb);
+  else if (prec == P_F32)
+    fn = trans ? pick<float, true>(mb) : pick<float, false>(mb);
+  else if (prec == P_BF16)
+    fn = trans ? pick_bf16<true, false>(mb) : pick_bf16<false, false>(mb);
+  else if (prec == P_BF16X3)
+    fn = trans ? pick_bf16<true, true>(mb) : pick_bf16<false, true>(mb);
+  if (!fn) return hipErrorInvalidValue;
   const int elem = f64 ? 8 : 4;
   const int64_t N = trans ? C : R;
   const int64_t K = trans ? R : C;

@@ -162,3 +162,22 @@ def test_deterministic_bitwise(ctx):
     b = ctx.decompose(A, 50, 10, 1, 4, prec="f32")
     for x, y in zip(a[:4], b[:4]):
         assert torch.equal(x, y)
+
+
+@pytest.mark.parametrize("prec,bound", [("bf16x3", 1e-5), ("f32", 1e-5), ("bf16", 2e-3)])
+def test_precision_forms_polynomial_decay(ctx, prec, bound):
+    """Precision forms on the polynomially decaying workload (sigma_i = i^-1.5,
+    1e-5 noise, l = 220, q = 2) at reduced size: relative Frobenius error
+    against the float64 oracle on the same float32 data.  The split-bf16 form
+    holds the 1e-5 bar; plain bf16 is reported with its measured bound."""
+    _say("precision form", prec)
+    A = decaying(6000, 4000, 1000, 1e-5, seed=3, kind="poly", alpha=1.5, dtype=np.float32)
+    U, T, V, piv, info = _run(ctx, A, 200, 20, 2, 17, prec, "auto")
+    A64 = A.astype(np.float64)
+    ref = corutv(A64, 200, 20, 2, seed=17)
+    e_ref = rel_err(A64, ref["U"], ref["T"], ref["V"])
+    d = abs(info["rel_err"] - e_ref)
+    print("precision %s: e_gpu %.8e e_oracle %.8e |diff| %.3e" % (prec, info["rel_err"], e_ref, d))
+    assert d <= bound
+    assert np.max(np.abs(U.T @ U - np.eye(220))) <= 1e-5
+    assert np.max(np.abs(V.T @ V - np.eye(220))) <= 1e-5

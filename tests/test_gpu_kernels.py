@@ -126,3 +126,38 @@ def test_qrcp_pivots_bit_exact(ctx, name, D):
     # same arithmetic order: R and Qt agree to the last bits
     np.testing.assert_allclose(R.cpu().numpy(), Ro, rtol=0, atol=1e-13 * max(1.0, np.abs(D).max()))
     np.testing.assert_allclose(Qt.cpu().numpy(), Qto, rtol=0, atol=1e-12)
+
+
+BF_CASES = [
+    (1000, 777, 37, "row"), (1000, 777, 37, "col"), (3000, 2048, 220, "row"), (4096, 1000, 112, "col"),
+    (300, 20000, 10, "row"), (513, 2050, 16, "row"),
+]
+
+
+@pytest.mark.parametrize("m,n,ell,layout", BF_CASES)
+@pytest.mark.parametrize("trans", [False, True])
+@pytest.mark.parametrize("prec", ["bf16", "bf16x3"])
+def test_sketch_pass_bf16_forms(ctx, m, n, ell, layout, trans, prec):
+    """BF16: operands rounded to nearest-even bfloat16, FP32 accumulation.
+    BF16X3: lo*hi + hi*lo + hi*hi of the 2-way split.  The reference is the
+    exact (float64) product of the same rounded operands (oracle.bf16)."""
+    from oracle.bf16 import matmul_bf16, matmul_bf16x3
+
+    _say("sketch", prec, m, n, ell, layout, trans)
+    rng = np.random.default_rng(m + 3 * n + ell)
+    A = rng.standard_normal((m, n)).astype(np.float32)
+    X = rng.standard_normal((m if trans else n, ell)).astype(np.float32)
+    At = torch.from_numpy(A).cuda()
+    if layout == "col":
+        At = torch.from_numpy(np.ascontiguousarray(A.T)).cuda().t()
+    Y = ctx.sketch(At, torch.from_numpy(X).cuda(), trans=trans, prec=prec).cpu().numpy()
+    Aop = A.T if trans else A
+    ref = (matmul_bf16 if prec == "bf16" else matmul_bf16x3)(Aop, X)
+    K = Aop.shape[1]
+    scale = np.sqrt(K) * np.abs(X).max() * np.abs(A).max()
+    err = np.max(np.abs(Y - ref)) / scale
+    assert err <= 2e-6 * np.sqrt(K), err
+    # and it is not the float32 product: bf16 rounding is visible
+    exact = Aop.astype(np.float64) @ X.astype(np.float64)
+    if prec == "bf16":
+        assert np.max(np.abs(Y - exact)) / scale > 1e-4
