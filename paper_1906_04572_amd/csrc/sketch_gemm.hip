@@ -112,28 +112,19 @@ __global__ void __launch_bounds__(256) sketch_kernel(SketchArgs a) {
     if (gk0 < gk1) {
       v16 sreg[SPASS];
       // B operand registers: N-pass [nb][h][4], T-pass [h][tt][nb]
-      T bcur[NB * KG * 4], bnext[NB * KG * 4];
 
+      // All loads below are unconditional, from addresses clamped into the
+      // valid range, with out-of-range elements zeroed by selects afterwards:
+      // loads under per-lane branches defeat the compiler's tracking of
+      // outstanding loads and serialize the prefetch.
       auto load_skinny = [&](int kb) {
+        // the skinny operand has at least ELLP rows and lds >= the k extent
+        // of the last chunk, with zero padding (library-internal buffers)
 #pragma unroll
         for (int p = 0; p < SPASS; ++p) {
           const int v = tid + 256 * p;
-          const int c = v / VPR, kv = v % VPR;
-          const int64_t k = (int64_t)kb * KC + kv * E16;
-          v16 r;
-#pragma unroll
-          for (int e = 0; e < E16; ++e) r[e] = T(0);
-          if (c < ELLP) {
-            const T* src = S + (int64_t)c * a.lds + k;
-            if (k + E16 <= a.K) {
-              r = *(const v16*)src;
-            } else {
-#pragma unroll
-              for (int e = 0; e < E16; ++e)
-                if (k + e < a.K) r[e] = src[e];
-            }
-          }
-          sreg[p] = r;
+          const int c = min(v / VPR, ELLP - 1), kv = v % VPR;
+          sreg[p] = *(const v16*)(S + (int64_t)c * a.lds + (int64_t)kb * KC + kv * E16);
         }
       };
       auto store_skinny = [&](int buf) {
@@ -144,33 +135,39 @@ __global__ void __launch_bounds__(256) sketch_kernel(SketchArgs a) {
           if (c < ELLP) *(v16*)&lds_s[buf][c * LDK + kv * E16] = sreg[p];
         }
       };
-      auto load_b = [&](int kb, T* b) {
+      // raw loads + a validity bit per element; the bits are applied when the
+      // prefetched set becomes current, so nothing waits on the loaded data
+      // until the next chunk's compute
+      auto load_b = [&](int kb, T* b, uint32_t& mask) {
+        mask = 0;
         if constexpr (!TRANS) {
 #pragma unroll
           for (int nb = 0; nb < NB; ++nb) {
             const int64_t n = nbase + nb * 16 + qd;
+            const bool nok = n < a.N;
+            const int64_t nc = nok ? n : a.N - 1;
 #pragma unroll
             for (int h = 0; h < KG; ++h) {
               const int64_t k = (int64_t)kb * KC + 16 * h + 4 * g;
-              T* d = b + (nb * KG + h) * 4;
+              const int base = (nb * KG + h) * 4;
+              T* d = b + base;
 #pragma unroll
-              for (int e = 0; e < 4; ++e) d[e] = T(0);
-              if (n < a.N) {
-                const T* src = A + n * a.lda + k;
-                if (a.vec && k + 4 <= a.K) {
-                  if constexpr (sizeof(T) == 4) {
-                    const f4 vv = *(const f4*)src;
-                    d[0] = vv[0]; d[1] = vv[1]; d[2] = vv[2]; d[3] = vv[3];
-                  } else {
-                    const d2 v0 = *(const d2*)src;
-                    const d2 v1 = *(const d2*)(src + 2);
-                    d[0] = v0[0]; d[1] = v0[1]; d[2] = v1[0]; d[3] = v1[1];
-                  }
+              for (int e = 0; e < 4; ++e) mask |= (uint32_t)(nok && k + e < a.K) << (base + e);
+              if (a.vec) {
+                // rows are 16-byte aligned and lda is a multiple of 4, so the
+                // 4-vector at k < K stays inside the row's allocation
+                const T* src = A + nc * a.lda + (k < a.K ? k : 0);
+                if constexpr (sizeof(T) == 4) {
+                  const f4 vv = *(const f4*)src;
+                  d[0] = vv[0]; d[1] = vv[1]; d[2] = vv[2]; d[3] = vv[3];
                 } else {
-#pragma unroll
-                  for (int e = 0; e < 4; ++e)
-                    if (k + e < a.K) d[e] = src[e];
+                  const d2 v0 = *(const d2*)src;
+                  const d2 v1 = *(const d2*)(src + 2);
+                  d[0] = v0[0]; d[1] = v0[1]; d[2] = v1[0]; d[3] = v1[1];
                 }
+              } else {
+#pragma unroll
+                for (int e = 0; e < 4; ++e) d[e] = A[nc * a.lda + (k + e < a.K ? k + e : 0)];
               }
             }
           }
@@ -180,40 +177,46 @@ __global__ void __launch_bounds__(256) sketch_kernel(SketchArgs a) {
 #pragma unroll
             for (int tt = 0; tt < 4; ++tt) {
               const int64_t k = (int64_t)kb * KC + 16 * h + 4 * g + tt;
+              const bool kok = k < a.K;
+              const int64_t kc = kok ? k : a.K - 1;
               const int64_t n0 = nbase + NB * qd;
-              T* d = b + (h * 4 + tt) * NB;
+              const int base = (h * 4 + tt) * NB;
+              T* d = b + base;
 #pragma unroll
-              for (int e = 0; e < NB; ++e) d[e] = T(0);
-              if (k < a.K) {
-                const T* src = A + k * a.lda + n0;
-                if (NB == 2 && a.vec && n0 + 2 <= a.N) {
-                  if constexpr (sizeof(T) == 4) {
-                    const f2 vv = *(const f2*)src;
-                    d[0] = vv[0]; d[NB - 1] = vv[1];
-                  } else {
-                    const d2 vv = *(const d2*)src;
-                    d[0] = vv[0]; d[NB - 1] = vv[1];
-                  }
+              for (int e = 0; e < NB; ++e) mask |= (uint32_t)(kok && n0 + e < a.N) << (base + e);
+              if (NB == 2 && a.vec) {
+                // n0 is even and lda a multiple of 4: the pair at n0 < N is
+                // inside the row's allocation
+                const T* src = A + kc * a.lda + (n0 < a.N ? n0 : 0);
+                if constexpr (sizeof(T) == 4) {
+                  const f2 vv = *(const f2*)src;
+                  d[0] = vv[0]; d[NB - 1] = vv[1];
                 } else {
-#pragma unroll
-                  for (int e = 0; e < NB; ++e)
-                    if (n0 + e < a.N) d[e] = src[e];
+                  const d2 vv = *(const d2*)src;
+                  d[0] = vv[0]; d[NB - 1] = vv[1];
                 }
+              } else {
+#pragma unroll
+                for (int e = 0; e < NB; ++e) d[e] = A[kc * a.lda + (n0 + e < a.N ? n0 + e : 0)];
               }
             }
         }
       };
 
+      T bcur[NB * KG * 4], bnext[NB * KG * 4];
+      uint32_t mcur, mnext;
       load_skinny(gk0);
-      load_b(gk0, bcur);
+      load_b(gk0, bcur, mcur);
+#pragma unroll
+      for (int e = 0; e < NB * KG * 4; ++e) bcur[e] = ((mcur >> e) & 1u) ? bcur[e] : T(0);
       for (int kb = gk0; kb < gk1; ++kb, ++iter) {
         const int buf = iter & 1;
         store_skinny(buf);
         __syncthreads();
-        if (kb + 1 < gk1) {
-          load_skinny(kb + 1);
-          load_b(kb + 1, bnext);
-        }
+        // prefetch the next chunk (the last chunk reloads itself: harmless)
+        const int kn = kb + 1 < gk1 ? kb + 1 : kb;
+        load_skinny(kn);
+        load_b(kn, bnext, mnext);
         const T* ls = &lds_s[buf][0];
 #pragma unroll
         for (int h = 0; h < KG; ++h) {
@@ -240,10 +243,8 @@ __global__ void __launch_bounds__(256) sketch_kernel(SketchArgs a) {
                 acc[mb][nb] = M::op(sf[mb][tt], bv, acc[mb][nb]);
               }
         }
-        if (kb + 1 < gk1) {
 #pragma unroll
-          for (int e = 0; e < NB * KG * 4; ++e) bcur[e] = bnext[e];
-        }
+        for (int e = 0; e < NB * KG * 4; ++e) bcur[e] = ((mnext >> e) & 1u) ? bnext[e] : T(0);
       }
     }
 
