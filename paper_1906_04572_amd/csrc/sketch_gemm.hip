@@ -328,24 +328,14 @@ __global__ void __launch_bounds__(256) sketch_bf16_kernel(SketchArgs a) {
     if (gk0 < gk1) {
       f4 sreg[SPASS];
       float bcur[NB * 8], bnext[NB * 8];  // [nb][8 k values]
+      // unconditional loads from clamped addresses; validity bits applied
+      // when the prefetched chunk becomes current (see the FP32/FP64 kernel)
       auto load_skinny = [&](int kb) {
 #pragma unroll
         for (int p = 0; p < SPASS; ++p) {
           const int v = tid + 256 * p;
-          const int c = v / VPR, kv = v % VPR;
-          const int64_t k = (int64_t)kb * KC + kv * 4;
-          f4 r = {0, 0, 0, 0};
-          if (c < ELLP) {
-            const float* src = S + (int64_t)c * a.lds + k;
-            if (k + 4 <= a.K) {
-              r = *(const f4*)src;
-            } else {
-#pragma unroll
-              for (int e = 0; e < 4; ++e)
-                if (k + e < a.K) r[e] = src[e];
-            }
-          }
-          sreg[p] = r;
+          const int c = min(v / VPR, ELLP - 1), kv = v % VPR;
+          sreg[p] = *(const f4*)(S + (int64_t)c * a.lds + (int64_t)kb * KC + kv * 4);
         }
       };
       auto store_skinny = [&](int buf) {
@@ -356,60 +346,66 @@ __global__ void __launch_bounds__(256) sketch_bf16_kernel(SketchArgs a) {
           if (c < ELLP) *(f4*)&lds_s[buf][c * LDK + kv * 4] = sreg[p];
         }
       };
-      auto load_b = [&](int kb, float* b) {
-#pragma unroll
-        for (int e = 0; e < NB * 8; ++e) b[e] = 0.f;
+      auto load_b = [&](int kb, float* b, uint32_t& mask) {
+        mask = 0;
         if constexpr (!TRANS) {
 #pragma unroll
           for (int nb = 0; nb < NB; ++nb) {
             const int64_t n = nbase + nb * 16 + qd;
+            const bool nok = n < a.N;
+            const int64_t nc = nok ? n : a.N - 1;
             const int64_t k = (int64_t)kb * KC + 8 * g;
             float* d = b + nb * 8;
-            if (n < a.N) {
-              const float* src = A + n * a.lda + k;
-              if (a.vec && k + 8 <= a.K) {
-                const f4 v0 = *(const f4*)src;
-                const f4 v1 = *(const f4*)(src + 4);
-                d[0] = v0[0]; d[1] = v0[1]; d[2] = v0[2]; d[3] = v0[3];
-                d[4] = v1[0]; d[5] = v1[1]; d[6] = v1[2]; d[7] = v1[3];
-              } else {
 #pragma unroll
-                for (int e = 0; e < 8; ++e)
-                  if (k + e < a.K) d[e] = src[e];
-              }
+            for (int e = 0; e < 8; ++e) mask |= (uint32_t)(nok && k + e < a.K) << (nb * 8 + e);
+            if (a.vec) {
+              // lda is a multiple of 4: both 4-vectors at k < K (k a multiple
+              // of 8) stay inside the row's 16-byte padded extent only when
+              // k + 4 < K rounds up within lda; the second vector is clamped
+              const float* src = A + nc * a.lda + (k < a.K ? k : 0);
+              const f4 v0 = *(const f4*)src;
+              const int64_t k2 = k + 4 < a.K ? k + 4 : (k < a.K ? k : 0);
+              const f4 v1 = *(const f4*)(A + nc * a.lda + k2);
+              d[0] = v0[0]; d[1] = v0[1]; d[2] = v0[2]; d[3] = v0[3];
+              d[4] = v1[0]; d[5] = v1[1]; d[6] = v1[2]; d[7] = v1[3];
+            } else {
+#pragma unroll
+              for (int e = 0; e < 8; ++e) d[e] = A[nc * a.lda + (k + e < a.K ? k + e : 0)];
             }
           }
         } else {
 #pragma unroll
           for (int tt = 0; tt < 8; ++tt) {
             const int64_t k = (int64_t)kb * KC + 8 * g + tt;
+            const bool kok = k < a.K;
+            const int64_t kc = kok ? k : a.K - 1;
             const int64_t n0 = nbase + NB * qd;
-            if (k < a.K) {
-              const float* src = A + k * a.lda + n0;
-              if (NB == 2 && a.vec && n0 + 2 <= a.N) {
-                const f2 vv = *(const f2*)src;
-                b[tt] = vv[0];
-                b[8 * (NB - 1) + tt] = vv[1];
-              } else {
 #pragma unroll
-                for (int e = 0; e < NB; ++e)
-                  if (n0 + e < a.N) b[8 * e + tt] = src[e];
-              }
+            for (int e = 0; e < NB; ++e) mask |= (uint32_t)(kok && n0 + e < a.N) << (8 * e + tt);
+            if (NB == 2 && a.vec) {
+              const f2 vv = *(const f2*)(A + kc * a.lda + (n0 < a.N ? n0 : 0));
+              b[tt] = vv[0];
+              b[8 * (NB - 1) + tt] = vv[1];
+            } else {
+#pragma unroll
+              for (int e = 0; e < NB; ++e) b[8 * e + tt] = A[kc * a.lda + (n0 + e < a.N ? n0 + e : 0)];
             }
           }
         }
       };
 
+      uint32_t mcur, mnext;
       load_skinny(gk0);
-      load_b(gk0, bcur);
+      load_b(gk0, bcur, mcur);
+#pragma unroll
+      for (int e = 0; e < NB * 8; ++e) bcur[e] = ((mcur >> e) & 1u) ? bcur[e] : 0.f;
       for (int kb = gk0; kb < gk1; ++kb, ++iter) {
         const int buf = iter & 1;
         store_skinny(buf);
         __syncthreads();
-        if (kb + 1 < gk1) {
-          load_skinny(kb + 1);
-          load_b(kb + 1, bnext);
-        }
+        const int kn = kb + 1 < gk1 ? kb + 1 : kb;
+        load_skinny(kn);
+        load_b(kn, bnext, mnext);
         bf8 bh[NB], bl[NB];
 #pragma unroll
         for (int nb = 0; nb < NB; ++nb) split8(bcur + nb * 8, bh[nb], bl[nb], X3);
@@ -431,10 +427,8 @@ __global__ void __launch_bounds__(256) sketch_bf16_kernel(SketchArgs a) {
             acc[mb][nb] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(sh, bh[nb], acc[mb][nb], 0, 0, 0);
           }
         }
-        if (kb + 1 < gk1) {
 #pragma unroll
-          for (int e = 0; e < NB * 8; ++e) bcur[e] = bnext[e];
-        }
+        for (int e = 0; e < NB * 8; ++e) bcur[e] = ((mnext >> e) & 1u) ? bnext[e] : 0.f;
       }
     }
     const int64_t slot = ((int64_t)x * a.gx + jw) * a.maxslot + (t - tfirst);
