@@ -126,7 +126,12 @@ uint64_t corutv_workspace_bytes(int64_t m, int64_t n, int32_t k, int32_t p, int3
  *         l <= min(m, n), l <= 256.  q >= 0 power iterations.
  *   seed  key of the Philox4x64-10 stream of Omega; entry (i, j) of Omega is
  *         the Box-Muller normal of the block at counter (i, j, 0, 0), key
- *         (seed, 0) (definition in the design notes).
+ *         (seed, 0): words w0, w1 give u1 = ((w0 >> 11) + 1) 2^-53 and
+ *         u2 = (w1 >> 11) 2^-53, z = sqrt(-2 ln u1) cos(2 pi u2), with ln
+ *         and cos fixed as truncated series evaluated without fused
+ *         multiply-add (12-term atanh series for ln, exact quadrant
+ *         reduction and degree-18 Taylor polynomials for cos), so the
+ *         stream is reproducible bit for bit (see corutv_omega).
  *   U     m x l, V  n x l: outputs, F64 or F32, either layout.
  *   T     l x l FP64 output, column-major with leading dimension ldt >= l;
  *         the other triangle is stored as exact zeros.

@@ -11,7 +11,7 @@ low-rank step:
   Y_{j+1} = Y_j + mu_j (M - L_{j+1} - S_{j+1})
   mu_{j+1} = min(rho mu_j, mu_bar)
 
-Readings of points the paper leaves open (each listed in the design notes):
+Readings of points the paper leaves open:
 * the S step uses Y_j (the multiplier of the current iterate);
 * the printed mu update takes a max, which would freeze mu after one step
   while the text says the continuation increases mu; min (capped growth) is
