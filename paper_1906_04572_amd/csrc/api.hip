@@ -37,7 +37,7 @@ struct Plan {
   // byte offsets
   size_t o_wop = 0, o_qop = 0, o_part = 0, o_x0 = 0, o_x1 = 0, o_q1 = 0, o_q2 = 0, o_xp = 0,
          o_g = 0, o_r = 0, o_rinv = 0, o_core = 0, o_qt = 0, o_rt = 0, o_qw = 0, o_tt = 0,
-         o_piv = 0, o_st = 0, o_res = 0, o_sum = 0;
+         o_piv = 0, o_st = 0, o_res = 0, o_sum = 0, o_cw = 0;
   size_t total = 0;
 };
 
@@ -91,6 +91,7 @@ bool make_plan(int64_t m, int64_t n, int k, int p, int q, int prec, Plan* pl) {
   pl->o_st = take(kMaxQr * 4);
   pl->o_res = take((size_t)residual_blocks(pl->mm) * 2 * 8);
   pl->o_sum = take(2 * 8);
+  pl->o_cw = take(chol_work_bytes((int)ell));
   pl->total = off;
   return true;
 }
@@ -203,13 +204,14 @@ hipError_t qr_from_partials(const Plan& pl, char* ws, const Partials& pp, int64_
   double* G = (double*)(ws + pl.o_g);
   double* R = (double*)(ws + pl.o_r);
   double* Ri = (double*)(ws + pl.o_rinv);
+  double* cw = (double*)(ws + pl.o_cw);
   const int64_t l2 = (int64_t)ell * ell;
   const int splits = xty_splits(rows, ell);
   hipError_t e;
   if ((e = launch_sum_partials(pp, ell, pl.ellp, x0, nullptr, ld, s)) != hipSuccess) return e;
   if ((e = launch_xty(x0, ld, x0, ld, rows, ell, xp, splits, nullptr, s)) != hipSuccess) return e;
   if ((e = launch_reduce(xp, splits, l2, G, nullptr, s)) != hipSuccess) return e;
-  if ((e = launch_chol(G, ell, R, Ri, st, nullptr, s)) != hipSuccess) return e;
+  if ((e = launch_chol(G, ell, R, Ri, st, nullptr, cw, s)) != hipSuccess) return e;
   MatOut ox1;
   ox1.ptr = x1;
   ox1.ld = ld;
@@ -217,7 +219,7 @@ hipError_t qr_from_partials(const Plan& pl, char* ws, const Partials& pp, int64_
     return e;
   if ((e = launch_xty(x1, ld, x1, ld, rows, ell, xp, splits, st, s)) != hipSuccess) return e;
   if ((e = launch_reduce(xp, splits, l2, G, st, s)) != hipSuccess) return e;
-  if ((e = launch_chol(G, ell, R, Ri, st, st, s)) != hipSuccess) return e;
+  if ((e = launch_chol(G, ell, R, Ri, st, st, cw, s)) != hipSuccess) return e;
   MatOut o1, o2;
   o1.ptr = q64;
   o1.ld = ld;
@@ -619,7 +621,7 @@ int corutv_tsqr(corutv_ctx* ctx, const double* X, int64_t rows, int32_t ell, int
   const size_t o_x0 = take((size_t)ellp * ld * 8), o_x1 = take((size_t)ellp * ld * 8),
                o_q = take((size_t)ellp * ld * 8), o_xp = take(splits * l2), o_g = take(l2),
                o_r1 = take(2 * l2), o_r2 = take(2 * l2), o_ri = take(l2), o_rh = take(l2),
-               o_st = take(64);
+               o_st = take(64), o_cw = take(chol_work_bytes(ell));
   if (off > ctx->ws_bytes) return CORUTV_E_NOMEM;
   std::lock_guard<std::mutex> lk(ctx->run_mu);
   hipStream_t s = ctx->streams[0];
@@ -628,19 +630,20 @@ int corutv_tsqr(corutv_ctx* ctx, const double* X, int64_t rows, int32_t ell, int
          *xp = (double*)(w + o_xp), *G = (double*)(w + o_g), *R1 = (double*)(w + o_r1),
          *R2 = (double*)(w + o_r2), *Ri = (double*)(w + o_ri), *Rh = (double*)(w + o_rh);
   int* st = (int*)(w + o_st);
+  double* cw = (double*)(w + o_cw);
   HIPOK(launch_fill_int(st, 1, 0, s));
   HIPOK(hipMemcpy2DAsync(x0, ld * 8, X, ldx * 8, rows * 8, ell, hipMemcpyDeviceToDevice, s));
   const int64_t l2e = (int64_t)ell * ell;
   HIPOK(launch_xty(x0, ld, x0, ld, rows, ell, xp, splits, nullptr, s));
   HIPOK(launch_reduce(xp, splits, l2e, G, nullptr, s));
-  HIPOK(launch_chol(G, ell, R1, Ri, st, nullptr, s));
+  HIPOK(launch_chol(G, ell, R1, Ri, st, nullptr, cw, s));
   MatOut ox1;
   ox1.ptr = x1;
   ox1.ld = ld;
   HIPOK(launch_rowmat(x0, ld, rows, ell, Ri, ell, nullptr, ox1, 1, MatOut(), 0, st, s));
   HIPOK(launch_xty(x1, ld, x1, ld, rows, ell, xp, splits, st, s));
   HIPOK(launch_reduce(xp, splits, l2e, G, st, s));
-  HIPOK(launch_chol(G, ell, R2, Ri, st, st, s));
+  HIPOK(launch_chol(G, ell, R2, Ri, st, st, cw, s));
   MatOut oq;
   oq.ptr = qq;
   oq.ld = ld;

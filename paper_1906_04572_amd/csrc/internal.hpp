@@ -86,8 +86,10 @@ hipError_t launch_rowmat(const double* X, int64_t ldx, int64_t rows, int ell, co
 // and the inverse of R, both written column-major (ld ell).  status gets
 // bit 1 on breakdown (non-positive or non-finite pivot) and bit 2 when the
 // input holds NaN/Inf.  Runs only when *skip == 0 (skip may be null).
+// work: chol_work_bytes(ell) bytes of device scratch (0 for ell <= 128).
+size_t chol_work_bytes(int ell);
 hipError_t launch_chol(const double* G, int ell, double* R, double* Rinv, int* status,
-                       const int* skip, hipStream_t st);
+                       const int* skip, double* work, hipStream_t st);
 
 // Householder thin QR of X (rows x ell, column-major FP64) -> Q (diag R >= 0,
 // FP64 and optionally a float copy), R (nullable); runs only when

@@ -64,78 +64,136 @@ __global__ void __launch_bounds__(256) sum_partials_kernel(Partials p, const T* 
 }
 
 // ---------------------------------------------------------------------------
-// Xa^T Xb over row splits.  Block: 64 x 64 output tile, 4 x 4 per thread.
-constexpr int XT = 64, XR = 32;
+// Xa^T Xb over row splits on FP64 matrix cores.  A workgroup (4 waves) owns a
+// 64 x 64 region of the l x l result and the rows of one split; rows are
+// staged through LDS in chunks of 32 (column-major, padded stride), the next
+// chunk prefetched into registers while the current one is multiplied.  Wave
+// w computes the 32 x 32 block (w & 1, w >> 1) of the region as 2 x 2 tiles
+// of v_mfma_f64_16x16x4f64 (lane l: A(l%16, k), B(k, l%16), k = l/16 + 4 kstep;
+// accumulator slot s = element (l/16 + 4s, l%16)).  For a Gram matrix
+// (Xa == Xb) only regions on or above the diagonal are computed and the
+// off-diagonal ones are written twice.  Each split writes its own l x l
+// partial (column-major); reduce_kernel adds them in a fixed order.
+typedef double d4x __attribute__((ext_vector_type(4)));
+constexpr int XT = 64, XR = 32, XSP = XR + 1;
+
+__host__ __device__ inline int xty_regions(int ell, int sym) {
+  const int nr = (ell + XT - 1) / XT;
+  return sym ? nr * (nr + 1) / 2 : nr * nr;
+}
 
 __global__ void __launch_bounds__(256) xty_kernel(const double* __restrict__ Xa, int64_t lda,
                                                   const double* __restrict__ Xb, int64_t ldb,
                                                   int64_t rows, int ell, double* __restrict__ part,
-                                                  int splits, const int* skip) {
+                                                  int splits, int sym, const int* skip) {
   if (skip && *skip) return;
-  __shared__ double sa[XR][XT + 1];
-  __shared__ double sb[XR][XT + 1];
-  const int ntile = (ell + XT - 1) / XT;
-  const int tile = blockIdx.x % (ntile * ntile);
-  const int split = blockIdx.x / (ntile * ntile);
-  const int a0 = (tile % ntile) * XT, b0 = (tile / ntile) * XT;
-  const int tid = threadIdx.x, ta = tid >> 4, tb = tid & 15;
+  __shared__ double sa[XT * XSP];
+  __shared__ double sb[XT * XSP];
+  const int nr = (ell + XT - 1) / XT;
+  const int nreg = xty_regions(ell, sym);
+  int reg = blockIdx.x % nreg;
+  const int split = blockIdx.x / nreg;
+  int ra = 0, rb = 0;
+  if (sym) {
+    int len = nr;
+    while (reg >= len) {
+      reg -= len;
+      ++ra;
+      --len;
+    }
+    rb = ra + reg;
+  } else {
+    ra = reg % nr;
+    rb = reg / nr;
+  }
+  const int a0 = ra * XT, b0 = rb * XT;
+  const int tid = threadIdx.x, lane = tid & 63, w = tid >> 6;
+  const int g = lane >> 4, i = lane & 15;
+  const int wa = (w & 1) * 32, wb = (w >> 1) * 32;
   const int64_t per = (rows + splits - 1) / splits;
   const int64_t r0 = (int64_t)split * per;
   const int64_t r1 = r0 + per < rows ? r0 + per : rows;
-  double acc[4][4];
+  // loader: thread covers column tid / 32 + 8 e, row tid % 32 of a chunk
+  const int lr = tid & (XR - 1), lc = tid >> 5;
+  double va[8], vb[8];
+  auto fetch = [&](int64_t rb0) {
+    const int64_t row = rb0 + lr;
+    const bool ok = row < r1;
+    const int64_t rr = ok ? row : r0;  // clamped: always a valid row
 #pragma unroll
-  for (int i = 0; i < 4; ++i)
+    for (int e = 0; e < 8; ++e) {
+      const int c = lc + 8 * e;
+      const int ca = a0 + c < ell ? a0 + c : ell - 1;
+      const int cb = b0 + c < ell ? b0 + c : ell - 1;
+      const double x = Xa[(int64_t)ca * lda + rr];
+      const double y = Xb[(int64_t)cb * ldb + rr];
+      va[e] = (ok && a0 + c < ell) ? x : 0.0;
+      vb[e] = (ok && b0 + c < ell) ? y : 0.0;
+    }
+  };
+  d4x acc[2][2];
 #pragma unroll
-    for (int j = 0; j < 4; ++j) acc[i][j] = 0.0;
-  for (int64_t rb = r0; rb < r1; rb += XR) {
-    // stage XR rows x 64 columns of each operand (coalesced along rows)
-    for (int e = tid; e < XR * XT; e += 256) {
-      const int r = e % XR, c = e / XR;
-      const int64_t row = rb + r;
-      const bool ok = row < r1;
-      sa[r][c] = (ok && a0 + c < ell) ? Xa[(int64_t)(a0 + c) * lda + row] : 0.0;
-      sb[r][c] = (ok && b0 + c < ell) ? Xb[(int64_t)(b0 + c) * ldb + row] : 0.0;
+  for (int x = 0; x < 2; ++x)
+#pragma unroll
+    for (int y = 0; y < 2; ++y) acc[x][y] = (d4x){0.0, 0.0, 0.0, 0.0};
+  if (r0 < r1) fetch(r0);
+  for (int64_t rb0 = r0; rb0 < r1; rb0 += XR) {
+#pragma unroll
+    for (int e = 0; e < 8; ++e) {
+      sa[(lc + 8 * e) * XSP + lr] = va[e];
+      sb[(lc + 8 * e) * XSP + lr] = vb[e];
     }
     __syncthreads();
-#pragma unroll 4
-    for (int r = 0; r < XR; ++r) {
-      double av[4], bv[4];
+    if (rb0 + XR < r1) fetch(rb0 + XR);
 #pragma unroll
-      for (int i = 0; i < 4; ++i) av[i] = sa[r][ta + 16 * i];
-#pragma unroll
-      for (int j = 0; j < 4; ++j) bv[j] = sb[r][tb + 16 * j];
-#pragma unroll
-      for (int i = 0; i < 4; ++i)
-#pragma unroll
-        for (int j = 0; j < 4; ++j) acc[i][j] = fma(av[i], bv[j], acc[i][j]);
+    for (int ks = 0; ks < XR / 4; ++ks) {
+      const int k = 4 * ks + g;
+      const double a0f = sa[(wa + i) * XSP + k], a1f = sa[(wa + 16 + i) * XSP + k];
+      const double b0f = sb[(wb + i) * XSP + k], b1f = sb[(wb + 16 + i) * XSP + k];
+      acc[0][0] = __builtin_amdgcn_mfma_f64_16x16x4f64(a0f, b0f, acc[0][0], 0, 0, 0);
+      acc[0][1] = __builtin_amdgcn_mfma_f64_16x16x4f64(a0f, b1f, acc[0][1], 0, 0, 0);
+      acc[1][0] = __builtin_amdgcn_mfma_f64_16x16x4f64(a1f, b0f, acc[1][0], 0, 0, 0);
+      acc[1][1] = __builtin_amdgcn_mfma_f64_16x16x4f64(a1f, b1f, acc[1][1], 0, 0, 0);
     }
     __syncthreads();
   }
   double* out = part + (int64_t)split * ell * ell;
+  const bool mirror = sym && ra != rb;
 #pragma unroll
-  for (int i = 0; i < 4; ++i)
+  for (int x = 0; x < 2; ++x)
 #pragma unroll
-    for (int j = 0; j < 4; ++j) {
-      const int a = a0 + ta + 16 * i, b = b0 + tb + 16 * j;
-      if (a < ell && b < ell) out[(int64_t)b * ell + a] = acc[i][j];
-    }
+    for (int y = 0; y < 2; ++y)
+#pragma unroll
+      for (int s = 0; s < 4; ++s) {
+        const int a = a0 + wa + 16 * x + g + 4 * s, b = b0 + wb + 16 * y + i;
+        if (a < ell && b < ell) {
+          out[(int64_t)b * ell + a] = acc[x][y][s];
+          if (mirror) out[(int64_t)a * ell + b] = acc[x][y][s];
+        }
+      }
 }
 
 // out[e] = sum over k of part[k * elems + e], in a fixed order: thread group
-// g (0..3) sums splits g, g+4, ...; the four group sums are added in order.
-__global__ void __launch_bounds__(256) reduce_kernel(const double* __restrict__ part, int splits,
-                                                     int64_t elems, double* __restrict__ out,
-                                                     const int* skip) {
+// q (0..15) sums splits q, q+16, ... in order; the sixteen group sums are
+// added in group order.
+__global__ void __launch_bounds__(1024) reduce_kernel(const double* __restrict__ part, int splits,
+                                                      int64_t elems, double* __restrict__ out,
+                                                      const int* skip) {
   if (skip && *skip) return;
-  __shared__ double red[4][64];
+  __shared__ double red[16][64];
   const int el = threadIdx.x & 63, grp = threadIdx.x >> 6;
   const int64_t e = (int64_t)blockIdx.x * 64 + el;
   double s = 0.0;
   if (e < elems)
-    for (int k = grp; k < splits; k += 4) s += part[(int64_t)k * elems + e];
+    for (int k = grp; k < splits; k += 16) s += part[(int64_t)k * elems + e];
   red[grp][el] = s;
   __syncthreads();
-  if (grp == 0 && e < elems) out[e] = ((red[0][el] + red[1][el]) + red[2][el]) + red[3][el];
+  if (grp == 0 && e < elems) {
+    double t = red[0][el];
+#pragma unroll
+    for (int q = 1; q < 16; ++q) t += red[q][el];
+    out[e] = t;
+  }
 }
 
 // ---------------------------------------------------------------------------
@@ -219,130 +277,333 @@ __global__ void __launch_bounds__(256) rowmat_kernel(const double* __restrict__ 
     }
 }
 
-// ---------------------------------------------------------------------------
-// Cholesky G = R^T R fused with the inverse of R, one workgroup of 1024
-// threads.  Element (r, c) of the working matrix lives in a register of
-// thread (r mod 32, c mod 32) (block-cyclic).  The upper triangle holds the
-// matrix being factored, the strict lower triangle the rows of Z = R^{-T}
-// (L = R^T, Z = L^{-1}); rows are kept unscaled and scaled at the end.
-// Step s: the owners of row s publish it (double-buffered LDS vector), every
-// thread reads the pivot d = W[s,s] and computes iv = 1/sqrt(d), then
-//   W[r,c] -= (W[s,r] iv^2) W[s,c]   for r > s and (c >= r or c < s)
-//   W[r,s] -= W[s,r] iv^2            for r > s (the Z diagonal iv enters)
-// which is the rank-1 update of the trailing matrix and the forward
-// substitution step of L Z = I.  One barrier per step.
-template <int NPT>
-__device__ __forceinline__ void chol_reg_body(const double* __restrict__ G, int ell,
-                                              double* __restrict__ R, double* __restrict__ Rinv,
-                                              int* status, double* rowbuf, double* inv,
-                                              double* sh) {
-  const int tid = threadIdx.x;
-  const int tr = tid & 31, tc = tid >> 5;
-  double w[NPT][NPT];
+// Y = X B on FP64 matrix cores, computed as Y^T = B^T X^T so that the
+// accumulator lanes run along rows of Y (coalesced column-major stores).  A
+// workgroup (4 waves) owns 64 rows x 64 columns of Y; wave w computes 32
+// columns x 32 rows as 2 x 2 tiles.  B^T is staged through LDS in chunks of
+// 32 of the contraction index; X is read straight from global memory (16
+// consecutive rows per lane group).  Rows and contraction indices past the
+// ends are clamped for the loads and masked to zero.
+__global__ void __launch_bounds__(256) rowmat_mfma_kernel(const double* __restrict__ X, int64_t ldx,
+                                                          int64_t rows, int ell,
+                                                          const double* __restrict__ B, int64_t ldb,
+                                                          MatOut o1, int pad1, MatOut o2, int pad2,
+                                                          const int* skip) {
+  if (skip && *skip) return;
+  constexpr int KB = 32, SP = KB + 1;
+  __shared__ double sbt[64 * SP];  // sbt[c * SP + k] = B[k0 + k][c0 + c]
+  const int tid = threadIdx.x, lane = tid & 63, w = tid >> 6;
+  const int g = lane >> 4, i = lane & 15;
+  const int64_t r0 = (int64_t)blockIdx.x * 64;
+  const int c0 = blockIdx.y * 64;
+  const int ellp = pad_ell(ell);
+  const int wc = (w & 1) * 32, wr = (w >> 1) * 32;
+  int64_t rr[2];
+  bool rok[2];
 #pragma unroll
-  for (int a = 0; a < NPT; ++a)
-#pragma unroll
-    for (int b = 0; b < NPT; ++b) {
-      const int r = tr + 32 * a, c = tc + 32 * b;
-      w[a][b] = (r < ell && c < ell && r <= c) ? G[(int64_t)c * ell + r] : 0.0;
-    }
-  if (tid == 0) {
-    double dmax = 0.0;
-    int bad = 0;
-    for (int i = 0; i < ell; ++i) {
-      const double d = G[(int64_t)i * ell + i];
-      if (!isfinite(d)) bad = 1;
-      if (d > dmax) dmax = d;
-    }
-    // a pivot below 4 l u max_i G_ii means the sketch's condition number is
-    // beyond ~ (4 l u)^(-1/2): CholeskyQR is not reliable, fall back
-    sh[0] = bad ? -1.0 : 4.0 * ell * 2.220446049250313e-16 * dmax;
+  for (int y = 0; y < 2; ++y) {
+    const int64_t r = r0 + wr + 16 * y + i;
+    rok[y] = r < rows;
+    rr[y] = rok[y] ? r : rows - 1;
   }
-  __syncthreads();
-  const double thr = sh[0];
-  if (thr < 0.0) {
-    if (tid == 0) atomicOr(status, 2);
-    return;
-  }
-  for (int s = 0; s < ell; ++s) {
-    double* row = rowbuf + (s & 1) * 256;
+  d4x acc[2][2];
 #pragma unroll
-    for (int a = 0; a < NPT; ++a) {
-      if (tr + 32 * a != s) continue;
+  for (int x = 0; x < 2; ++x)
 #pragma unroll
-      for (int b = 0; b < NPT; ++b) {
-        const int c = tc + 32 * b;
-        if (c < ell) row[c] = w[a][b];
-      }
+    for (int y = 0; y < 2; ++y) acc[x][y] = (d4x){0.0, 0.0, 0.0, 0.0};
+  for (int k0 = 0; k0 < ell; k0 += KB) {
+    for (int e = tid; e < 64 * KB; e += 256) {
+      const int k = e % KB, c = e / KB;
+      sbt[c * SP + k] = (k0 + k < ell && c0 + c < ell) ? B[(int64_t)(c0 + c) * ldb + k0 + k] : 0.0;
     }
     __syncthreads();
-    const double d = row[s];
-    if (!(d > thr) || !isfinite(d)) {
-      if (tid == 0) atomicOr(status, 1);
-      return;  // uniform: every thread read the same d
-    }
-    // 1/sqrt(d): hardware estimate refined by two Newton steps
-    double iv = __builtin_amdgcn_rsq(d);
-    iv = iv * (1.5 - 0.5 * d * iv * iv);
-    iv = iv * (1.5 - 0.5 * d * iv * iv);
-    const double iv2 = iv * iv;
-    if (tid == 0) inv[s] = iv;
-    double rc[NPT];
+    double xv[KB / 4][2];
 #pragma unroll
-    for (int b = 0; b < NPT; ++b) {
-      const int c = tc + 32 * b;
-      rc[b] = c < ell ? row[c] : 0.0;
-    }
+    for (int ks = 0; ks < KB / 4; ++ks) {
+      const int k = k0 + 4 * ks + g;
+      const int kc = k < ell ? k : ell - 1;
 #pragma unroll
-    for (int a = 0; a < NPT; ++a) {
-      if (32 * a + 31 <= s) continue;  // whole row block finished: uniform skip
-      const int r = tr + 32 * a;
-      if (r <= s || r >= ell) continue;
-      const double t = row[r] * iv2;
-#pragma unroll
-      for (int b = 0; b < NPT; ++b) {
-        const int c = tc + 32 * b;
-        if (c >= ell) continue;
-        if (c >= r || c < s)
-          w[a][b] -= t * rc[b];
-        else if (c == s)
-          w[a][b] -= t;
+      for (int y = 0; y < 2; ++y) {
+        const double v = X[(int64_t)kc * ldx + rr[y]];
+        xv[ks][y] = k < ell ? v : 0.0;
       }
     }
+#pragma unroll
+    for (int ks = 0; ks < KB / 4; ++ks) {
+      const int k = 4 * ks + g;
+      const double b0f = sbt[(wc + i) * SP + k], b1f = sbt[(wc + 16 + i) * SP + k];
+      acc[0][0] = __builtin_amdgcn_mfma_f64_16x16x4f64(b0f, xv[ks][0], acc[0][0], 0, 0, 0);
+      acc[0][1] = __builtin_amdgcn_mfma_f64_16x16x4f64(b0f, xv[ks][1], acc[0][1], 0, 0, 0);
+      acc[1][0] = __builtin_amdgcn_mfma_f64_16x16x4f64(b1f, xv[ks][0], acc[1][0], 0, 0, 0);
+      acc[1][1] = __builtin_amdgcn_mfma_f64_16x16x4f64(b1f, xv[ks][1], acc[1][1], 0, 0, 0);
+    }
+    __syncthreads();
   }
-  __syncthreads();
-  // outputs: element (r, c) of W gives
-  //   r < c : R[r,c] = W[r,c] iv_r
-  //   r = c : R[r,r] = sqrt(W[r,r]), Rinv[r,r] = iv_r
-  //   r > c : Rinv[c,r] = Z[r,c] = W[r,c] iv_r  (and zeros in the lower parts)
 #pragma unroll
-  for (int a = 0; a < NPT; ++a)
+  for (int x = 0; x < 2; ++x)
 #pragma unroll
-    for (int b = 0; b < NPT; ++b) {
-      const int r = tr + 32 * a, c = tc + 32 * b;
-      if (r >= ell || c >= ell) continue;
-      const int64_t rc_ = (int64_t)c * ell + r, cr = (int64_t)r * ell + c;
-      if (r < c) {
-        R[rc_] = w[a][b] * inv[r];
-      } else if (r == c) {
-        R[rc_] = sqrt(w[a][b]);
-        Rinv[rc_] = inv[r];
-      } else {
-        R[rc_] = 0.0;
-        Rinv[rc_] = 0.0;
-        Rinv[cr] = w[a][b] * inv[r];
+    for (int y = 0; y < 2; ++y) {
+      if (!rok[y]) continue;
+      const int64_t r = rr[y];
+#pragma unroll
+      for (int s = 0; s < 4; ++s) {
+        const int c = c0 + wc + 16 * x + g + 4 * s;
+        if (c < ell) {
+          if (o1.ptr) store_out(o1, r, c, acc[x][y][s]);
+          if (o2.ptr) store_out(o2, r, c, acc[x][y][s]);
+        } else if (c < ellp) {
+          if (o1.ptr && pad1) store_out(o1, r, c, 0.0);
+          if (o2.ptr && pad2) store_out(o2, r, c, 0.0);
+        }
       }
     }
 }
 
-template <int NPT>
-__global__ void __launch_bounds__(1024) chol_kernel(const double* G, int ell, double* R, double* Rinv,
-                                                    int* status, const int* skip) {
+// ---------------------------------------------------------------------------
+// Cholesky G = R^T R fused with R^{-1}, blocked, one workgroup of 1024
+// threads (16 waves).  The l x l matrix is cut into nb = ceil(l/16) block
+// rows and columns (padding: identity).  Tiles are 16 x 16 row-major:
+//   W(I, K), I <= K : the matrix being factored; ends as R(I, K)
+//   E(I, K), I >= K : Z = L^{-1} (L = R^T), built by the same row operations
+//   X               : U^{-1} of the current diagonal block (row-major)
+// Block step J:
+//   1. one wave factors the diagonal block D = U^T U (unblocked, in registers
+//      with lane shuffles) and writes U to W(J, J), U^{-T} to E(J, J) and
+//      U^{-1} to X;
+//   2. block row J: W(J, K) <- U^{-T} W(J, K) for K > J (rows of R) and
+//      E(J, M) <- U^{-T} E(J, M) for M < J (rows of Z);
+//   3. trailing update W(K, K2) -= R(J, K)^T R(J, K2) for J < K <= K2 and
+//      E(K, M) -= R(J, K)^T E(J, M) for K > J, M <= J.  Wave 0 takes the
+//      update of W(J+1, J+1) and goes straight on to step 1 of J + 1, so
+//      each block step costs two barriers.
+// Steps 2 and 3 are 16 x 16 x 16 products on FP64 matrix cores
+// (v_mfma_f64_16x16x4f64, lane l holds A(l%16, k), B(k, l%16) with
+// k = l/16 + 4 kstep; accumulator slot s is element (l/16 + 4s, l%16)).
+// A pivot <= 4 l u max_i G_ii (or not finite) is a breakdown: status bit 1,
+// and the caller's Householder fallback takes over.
+typedef double d4c __attribute__((ext_vector_type(4)));
+
+constexpr int kCholLdsNb = 8;  // tiles in LDS up to l = 128
+
+__device__ __forceinline__ d4c tile_acc_load(const double* t, int lane) {
+  const int g = lane >> 4, j = lane & 15;
+  d4c r;
+  r[0] = t[g * 16 + j];
+  r[1] = t[(g + 4) * 16 + j];
+  r[2] = t[(g + 8) * 16 + j];
+  r[3] = t[(g + 12) * 16 + j];
+  return r;
+}
+
+__device__ __forceinline__ void tile_acc_store(double* t, d4c v, int lane) {
+  const int g = lane >> 4, j = lane & 15;
+  t[g * 16 + j] = v[0];
+  t[(g + 4) * 16 + j] = v[1];
+  t[(g + 8) * 16 + j] = v[2];
+  t[(g + 12) * 16 + j] = v[3];
+}
+
+// acc + sgn * A^T B for row-major 16 x 16 tiles A, B
+__device__ __forceinline__ d4c tile_atb(const double* A, const double* B, d4c acc, double sgn,
+                                        int lane) {
+  const int g = lane >> 4, i = lane & 15;
+  double a[4], b[4];
+#pragma unroll
+  for (int ks = 0; ks < 4; ++ks) {
+    const int k = 4 * ks + g;
+    a[ks] = sgn * A[k * 16 + i];
+    b[ks] = B[k * 16 + i];
+  }
+#pragma unroll
+  for (int ks = 0; ks < 4; ++ks) acc = __builtin_amdgcn_mfma_f64_16x16x4f64(a[ks], b[ks], acc, 0, 0, 0);
+  return acc;
+}
+
+__device__ __forceinline__ double readlane_f64(double v, int l) {
+  const long long b = __double_as_longlong(v);
+  const int lo = __builtin_amdgcn_readlane((int)b, l);
+  const int hi = __builtin_amdgcn_readlane((int)(b >> 32), l);
+  return __longlong_as_double(((long long)hi << 32) | (unsigned)lo);
+}
+
+// One wave: D (16 x 16, symmetric, row-major at src) = U^T U.  Lane r (mod
+// 16) holds row r of [D | I] in registers.  Step s broadcasts row s with
+// v_readlane (a uniform lane index, no memory round trip) and eliminates it
+// from the rows below with multipliers D[r][s]/d_s (the whole trailing square
+// is updated, so the multipliers can be read from each lane's own column s);
+// at the end row r is scaled by 1/sqrt(d_r), giving [U | U^{-T}].  Returns
+// false on breakdown (the same on every lane: the pivot is a broadcast).
+__device__ __forceinline__ bool chol_diag16(const double* src, int base, int ell, double thr,
+                                            double* u_out, double* e_out, double* x_out, int lane) {
+  const int r = lane & 15;
+  double x[32];
+#pragma unroll
+  for (int c = 0; c < 16; ++c) {
+    x[c] = src[r * 16 + c];
+    x[16 + c] = r == c ? 1.0 : 0.0;
+  }
+  double myiv = 1.0;
+#pragma unroll
+  for (int s = 0; s < 16; ++s) {
+    const double d = readlane_f64(x[s], s);
+    if (base + s < ell && (!(d > thr) || !isfinite(d))) return false;
+    // 1/sqrt(d): hardware estimate refined by two Newton steps
+    double iv = __builtin_amdgcn_rsq(d);
+    iv = iv * (1.5 - 0.5 * d * iv * iv);
+    iv = iv * (1.5 - 0.5 * d * iv * iv);
+    if (r == s) myiv = iv;
+    const double m = x[s] * (iv * iv);
+    const bool below = r > s;
+#pragma unroll
+    for (int c = s + 1; c < 17 + s; ++c) {  // D columns s+1..15, Z columns 0..s
+      const double rc = readlane_f64(x[c], s);
+      if (below) x[c] -= m * rc;
+    }
+  }
+  if (lane < 16) {
+#pragma unroll
+    for (int c = 0; c < 16; ++c) {
+      u_out[r * 16 + c] = c >= r ? x[c] * myiv : 0.0;
+      const double z = x[16 + c] * myiv;
+      e_out[r * 16 + c] = z;
+      x_out[c * 16 + r] = z;
+    }
+  }
+  return true;
+}
+
+__device__ __forceinline__ int chol_widx(int nb, int I, int K) { return I * nb - I * (I - 1) / 2 + (K - I); }
+__device__ __forceinline__ int chol_eidx(int I, int K) { return I * (I + 1) / 2 + K; }
+
+template <bool kLds>
+__global__ void __launch_bounds__(1024) chol_kernel(const double* __restrict__ G, int ell,
+                                                    double* __restrict__ R, double* __restrict__ Rinv,
+                                                    int* status, const int* skip, double* work) {
   if (skip && *skip) return;
-  __shared__ double rowbuf[512];
-  __shared__ double inv[256];
-  __shared__ double sh[2];
-  chol_reg_body<NPT>(G, ell, R, Rinv, status, rowbuf, inv, sh);
+  constexpr int kLdsTiles = kLds ? kCholLdsNb * (kCholLdsNb + 1) : 1;
+  __shared__ double lds_tiles[kLdsTiles * 256];
+  __shared__ double xt[256], dbuf[256];
+  __shared__ double red[8];
+  __shared__ double thr_s;
+  __shared__ int flag;
+  const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6, nwaves = blockDim.x >> 6;
+  const int nb = (ell + 15) / 16;
+  const int nw = nb * (nb + 1) / 2;
+  double* wt = kLds ? lds_tiles : work;  // W tiles, then E tiles
+  double* et = wt + (size_t)nw * 256;
+  auto W = [&](int I, int K) { return wt + (size_t)chol_widx(nb, I, K) * 256; };
+  auto E = [&](int I, int K) { return et + (size_t)chol_eidx(I, K) * 256; };
+
+  // largest diagonal entry (and whether any is not finite)
+  if (tid < 256) {
+    const double d = tid < ell ? G[(int64_t)tid * ell + tid] : 0.0;
+    double mx = isfinite(d) ? d : -1.0;
+    double bad = isfinite(d) ? 0.0 : 1.0;
+#pragma unroll
+    for (int off = 32; off > 0; off >>= 1) {
+      mx = fmax(mx, __shfl_xor(mx, off, 64));
+      bad = fmax(bad, __shfl_xor(bad, off, 64));
+    }
+    if (lane == 0) {
+      red[wave] = mx;
+      red[4 + wave] = bad;
+    }
+  }
+  // tiles: W from G (identity in the padding), E zero
+  for (int e = tid; e < nw * 256; e += blockDim.x) {
+    const int t = e >> 8, r = (e >> 4) & 15, c = e & 15;
+    int I = 0, rem = t;
+    while (rem >= nb - I) {
+      rem -= nb - I;
+      ++I;
+    }
+    const int gi = 16 * I + r, gj = 16 * (I + rem) + c;
+    wt[e] = (gi < ell && gj < ell) ? G[(int64_t)gj * ell + gi] : (gi == gj ? 1.0 : 0.0);
+    et[e] = 0.0;
+  }
+  if (tid == 0) {
+    const double dmax = fmax(fmax(red[0], red[1]), fmax(red[2], red[3]));
+    const double bad = fmax(fmax(red[4], red[5]), fmax(red[6], red[7]));
+    // a pivot below 4 l u max_i G_ii means the sketch's condition number is
+    // beyond ~ (4 l u)^(-1/2): CholeskyQR is not reliable, fall back
+    thr_s = bad != 0.0 ? -1.0 : 4.0 * ell * 2.220446049250313e-16 * dmax;
+    flag = 0;
+  }
+  __syncthreads();
+  const double thr = thr_s;
+  if (thr < 0.0) {
+    if (tid == 0) atomicOr(status, 2);
+    return;
+  }
+  if (wave == 0 && !chol_diag16(W(0, 0), 0, ell, thr, W(0, 0), E(0, 0), xt, lane) && lane == 0) flag = 1;
+  __syncthreads();
+  if (flag) {
+    if (tid == 0) atomicOr(status, 1);
+    return;
+  }
+  for (int J = 0; J < nb; ++J) {
+    // 2. block row J
+    const int nW = nb - 1 - J;
+    for (int o = wave; o < nW + J; o += nwaves) {
+      double* T = o < nW ? W(J, J + 1 + o) : E(J, o - nW);
+      d4c acc = {0.0, 0.0, 0.0, 0.0};
+      acc = tile_atb(xt, T, acc, 1.0, lane);
+      tile_acc_store(T, acc, lane);
+    }
+    __syncthreads();
+    if (nW == 0) break;
+    // 3. trailing update; wave 0: W(J+1, J+1), then the next diagonal block
+    if (wave == 0) {
+      d4c acc = tile_acc_load(W(J + 1, J + 1), lane);
+      acc = tile_atb(W(J, J + 1), W(J, J + 1), acc, -1.0, lane);
+      tile_acc_store(dbuf, acc, lane);
+      if (!chol_diag16(dbuf, 16 * (J + 1), ell, thr, W(J + 1, J + 1), E(J + 1, J + 1), xt, lane) &&
+          lane == 0)
+        flag = 1;
+    } else {
+      const int nWops = nW * (nW + 1) / 2;
+      const int nops = nWops - 1 + nW * (J + 1);
+      for (int o = wave - 1; o < nops; o += nwaves - 1) {
+        int q = o + 1;  // index 0 of the W list is W(J+1, J+1)
+        if (q < nWops) {
+          int a = 0, len = nW;
+          while (q >= len) {
+            q -= len;
+            ++a;
+            --len;
+          }
+          const int K = J + 1 + a, K2 = K + q;
+          double* T = W(K, K2);
+          d4c acc = tile_acc_load(T, lane);
+          acc = tile_atb(W(J, K), W(J, K2), acc, -1.0, lane);
+          tile_acc_store(T, acc, lane);
+        } else {
+          q -= nWops;
+          const int K = J + 1 + q / (J + 1), M = q % (J + 1);
+          double* T = E(K, M);
+          d4c acc = tile_acc_load(T, lane);
+          acc = tile_atb(W(J, K), E(J, M), acc, -1.0, lane);
+          tile_acc_store(T, acc, lane);
+        }
+      }
+    }
+    __syncthreads();
+    if (flag) {
+      if (tid == 0) atomicOr(status, 1);
+      return;
+    }
+  }
+  // R (upper, zeros below) and R^{-1} = Z^T, column-major
+  for (int e = tid; e < ell * ell; e += blockDim.x) {
+    const int r = e % ell, c = e / ell;
+    if (r <= c) {
+      R[e] = W(r >> 4, c >> 4)[(r & 15) * 16 + (c & 15)];
+      Rinv[e] = E(c >> 4, r >> 4)[(c & 15) * 16 + (r & 15)];
+    } else {
+      R[e] = 0.0;
+      Rinv[e] = 0.0;
+    }
+  }
 }
 
 // ---------------------------------------------------------------------------
@@ -574,24 +835,24 @@ hipError_t launch_sum_partials(const Partials& p, int ell, int ncols, double* ou
 }
 
 int xty_splits(int64_t rows, int ell) {
-  const int nt = (ell + XT - 1) / XT;
-  int s = 512 / (nt * nt);
-  const int64_t maxs = (rows + XR - 1) / XR;
+  // about 512 workgroups for a Gram matrix, at least 64 rows per split
+  int s = 512 / xty_regions(ell, 1);
+  const int64_t maxs = (rows + 63) / 64;
   if (s > maxs) s = (int)maxs;
   return s < 1 ? 1 : s;
 }
 
 hipError_t launch_xty(const double* Xa, int64_t lda, const double* Xb, int64_t ldb, int64_t rows,
                       int ell, double* part, int splits, const int* skip, hipStream_t st) {
-  const int nt = (ell + XT - 1) / XT;
-  xty_kernel<<<dim3(nt * nt * splits), dim3(256), 0, st>>>(Xa, lda, Xb, ldb, rows, ell, part, splits,
-                                                          skip);
+  const int sym = (Xa == Xb && lda == ldb) ? 1 : 0;
+  xty_kernel<<<dim3(xty_regions(ell, sym) * splits), dim3(256), 0, st>>>(Xa, lda, Xb, ldb, rows, ell, part,
+                                                                         splits, sym, skip);
   return hipGetLastError();
 }
 
 hipError_t launch_reduce(const double* part, int splits, int64_t elems, double* out, const int* skip,
                          hipStream_t st) {
-  reduce_kernel<<<dim3((unsigned)((elems + 63) / 64)), dim3(256), 0, st>>>(part, splits, elems, out, skip);
+  reduce_kernel<<<dim3((unsigned)((elems + 63) / 64)), dim3(1024), 0, st>>>(part, splits, elems, out, skip);
   return hipGetLastError();
 }
 
@@ -601,23 +862,24 @@ hipError_t launch_rowmat(const double* X, int64_t ldx, int64_t rows, int ell, co
   if (rows == 0) return hipSuccess;
   const int ellp = pad_ell(ell);
   dim3 grid((unsigned)((rows + 63) / 64), (unsigned)((ellp + 63) / 64));
-  rowmat_kernel<<<grid, dim3(256), 0, st>>>(X, ldx, rows, ell, B, ldb, perm, o1, pad1, o2, pad2, skip);
+  if (perm)
+    rowmat_kernel<<<grid, dim3(256), 0, st>>>(X, ldx, rows, ell, B, ldb, perm, o1, pad1, o2, pad2, skip);
+  else
+    rowmat_mfma_kernel<<<grid, dim3(256), 0, st>>>(X, ldx, rows, ell, B, ldb, o1, pad1, o2, pad2, skip);
   return hipGetLastError();
 }
 
+size_t chol_work_bytes(int ell) {
+  const int nb = (ell + 15) / 16;
+  return nb <= kCholLdsNb ? 0 : (size_t)nb * (nb + 1) * 256 * sizeof(double);
+}
+
 hipError_t launch_chol(const double* G, int ell, double* R, double* Rinv, int* status,
-                       const int* skip, hipStream_t st) {
-  const int npt = (ell + 31) / 32;
-  if (npt <= 4)
-    chol_kernel<4><<<dim3(1), dim3(1024), 0, st>>>(G, ell, R, Rinv, status, skip);
-  else if (npt == 5)
-    chol_kernel<5><<<dim3(1), dim3(1024), 0, st>>>(G, ell, R, Rinv, status, skip);
-  else if (npt == 6)
-    chol_kernel<6><<<dim3(1), dim3(1024), 0, st>>>(G, ell, R, Rinv, status, skip);
-  else if (npt == 7)
-    chol_kernel<7><<<dim3(1), dim3(1024), 0, st>>>(G, ell, R, Rinv, status, skip);
+                       const int* skip, double* work, hipStream_t st) {
+  if ((ell + 15) / 16 <= kCholLdsNb)
+    chol_kernel<true><<<dim3(1), dim3(1024), 0, st>>>(G, ell, R, Rinv, status, skip, nullptr);
   else
-    chol_kernel<8><<<dim3(1), dim3(1024), 0, st>>>(G, ell, R, Rinv, status, skip);
+    chol_kernel<false><<<dim3(1), dim3(1024), 0, st>>>(G, ell, R, Rinv, status, skip, work);
   return hipGetLastError();
 }
 
