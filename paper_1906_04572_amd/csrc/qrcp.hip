@@ -1,12 +1,17 @@
 // Column-pivoted QR of the l x l core (Sec. 3.1 eq. 8; Algorithm 1 QRCP step):
 // D P = Qt R by Businger-Golub pivoting and Householder reflectors.
 //
-// Pivot loop: one workgroup of 1024 threads (l <= 256); four threads serve
-// each logical column.  Columns are never moved: the logical -> original index map piv
-// is permuted instead, and column data stays at its original position.  Two
-// barriers per step: (A) every owner computes its trailing norm; (B) every
-// thread redundantly finds the pivot and the reflector from shared data (no
-// serial phase) and updates its own column.
+// Pivot loop: one workgroup; four threads serve each column.  Columns are
+// never moved: a logical position -> original column map is permuted
+// instead.  Every wave redundantly finds the pivot and the reflector from
+// the shared norms (no serial phase), then every owner updates its own
+// column and computes its next trailing norm.
+//   l <= 128: qrcp_reg_kernel, 512 threads, each column in the registers of
+//             its four owners (thread k holds rows k, k+4, ...) and mirrored
+//             in LDS for the pivot broadcast; one barrier per step (the norm
+//             arrays are double-buffered); Qt formed in the same launch;
+//   l <= 256: qrcp_pivot_global + qrcp_formq_global, 1024 threads, the
+//             working matrix in device memory, two barriers per step.
 //
 // The arithmetic order is fixed so that the pivot sequence is a function of
 // the input bits only (each product and sum rounded separately: this file is
@@ -20,8 +25,8 @@
 //           v = W[s:, p] with v_0 = x0 - alpha; vtv = v0*v0 + t_p; tau = 2/vtv
 //   update  d_j = sum4_{i = s..l-1} v_i*W[i,j];
 //           f_j = d_j*tau; W[i,j] = W[i,j] - f_j*v_i
-// Qt = H_0 H_1 ... H_{l-1} is formed afterwards by a second kernel (backward
-// accumulation, one thread per column); it does not influence the pivots.
+// Qt = H_0 H_1 ... H_{l-1} is formed afterwards (backward accumulation); it
+// does not influence the pivots.
 // diag(R) is made non-negative by flipping rows of R and columns of Qt.
 #include "internal.hpp"
 
@@ -30,7 +35,7 @@
 namespace corutv {
 namespace {
 
-constexpr int kQrcpLdsMax = 128;  // working matrix in LDS up to this size
+constexpr int kQrcpRegMax = 128;  // columns in registers up to this size
 
 // W: row-major l x l (element (i, c) at W[i*l + c], c = original column).
 // 1024 threads: thread t serves logical column t/4 and the residue class
@@ -159,17 +164,6 @@ __device__ __forceinline__ void qrcp_pivot_body(double* __restrict__ W, double* 
   if (tid < ell) piv[tid] = pfin[tid];
 }
 
-__global__ void __launch_bounds__(1024) qrcp_pivot_lds(const double* D, int64_t ldd, int trans, int ell,
-                                                      double* Rout, int32_t* piv, double* Vout,
-                                                      double* tauout, double* signout) {
-  __shared__ double W[kQrcpLdsMax * kQrcpLdsMax];
-  __shared__ double nrm[256], tl[256], alph[256];
-  __shared__ int pv[512];
-  qrcp_pivot_body(W, nrm, tl, pv, alph, D, ldd, trans, ell, Rout, piv, Vout, tauout);
-  __syncthreads();
-  if ((int)threadIdx.x < ell) signout[threadIdx.x] = alph[threadIdx.x] < 0.0 ? -1.0 : 1.0;
-}
-
 __global__ void __launch_bounds__(1024) qrcp_pivot_global(const double* D, int64_t ldd, int trans,
                                                          int ell, double* Rout, int32_t* piv,
                                                          double* Vout, double* tauout,
@@ -179,6 +173,302 @@ __global__ void __launch_bounds__(1024) qrcp_pivot_global(const double* D, int64
   qrcp_pivot_body(work, nrm, tl, pv, alph, D, ldd, trans, ell, Rout, piv, Vout, tauout);
   __syncthreads();
   if ((int)threadIdx.x < ell) signout[threadIdx.x] = alph[threadIdx.x] < 0.0 ? -1.0 : 1.0;
+}
+
+// ---------------------------------------------------------------------------
+// l <= 128.  Thread t serves column c = t/4 and holds w[q] = W[4q + k, c]
+// (k = t%4).  A sum4 over rows r0, r0+1, ... is then, on each lane, a
+// sequential sum over its own rows in increasing order: lane k holds the
+// chain of positions congruent to (k - r0) mod 4.  Terms of rows before r0
+// enter as exact zeros (adding +-0 leaves the bits of a sum unchanged).
+// Cross-lane steps use DPP (quad permutes inside a column's four lanes, a
+// row-broadcast reduction for the pivot) rather than LDS permutes.
+template <int CTRL, int ROWMASK>
+__device__ __forceinline__ double dpp_f64(double v) {
+  const long long b = __double_as_longlong(v);
+  const int lo = __builtin_amdgcn_update_dpp((int)b, (int)b, CTRL, ROWMASK, 0xF, false);
+  const int hi = __builtin_amdgcn_update_dpp((int)(b >> 32), (int)(b >> 32), CTRL, ROWMASK, 0xF, false);
+  return __longlong_as_double(((long long)hi << 32) | (unsigned)lo);
+}
+
+__device__ __forceinline__ double uniform_f64(double v) {
+  const long long b = __double_as_longlong(v);
+  const int lo = __builtin_amdgcn_readfirstlane((int)b);
+  const int hi = __builtin_amdgcn_readfirstlane((int)(b >> 32));
+  return __longlong_as_double(((long long)hi << 32) | (unsigned)lo);
+}
+
+// (a0 + a1) + (a2 + a3) over the four lanes of a column, a_j being the chain
+// of class j; lane k holds class (k - r0) mod 4.  Same bits on all four.
+__device__ __forceinline__ double combine4_rot(double a, int k, int r0) {
+  const double x1 = dpp_f64<0xB1, 0xF>(a);  // lane k ^ 1
+  const double x2 = dpp_f64<0x4E, 0xF>(a);  // lane k ^ 2
+  const double x3 = dpp_f64<0x1B, 0xF>(a);  // lane k ^ 3
+  double v[4];
+#pragma unroll
+  for (int cls = 0; cls < 4; ++cls) {
+    const int m = ((cls + r0) & 3) ^ k;
+    v[cls] = m == 0 ? a : (m == 1 ? x1 : (m == 2 ? x2 : x3));
+  }
+  return (v[0] + v[1]) + (v[2] + v[3]);
+}
+
+// largest value over the wave (NaN-free input), the same on every lane
+__device__ __forceinline__ double wave_max(double v) {
+  v = fmax(v, dpp_f64<0xB1, 0xF>(v));   // quad_perm xor 1
+  v = fmax(v, dpp_f64<0x4E, 0xF>(v));   // quad_perm xor 2
+  v = fmax(v, dpp_f64<0x141, 0xF>(v));  // row_half_mirror
+  v = fmax(v, dpp_f64<0x140, 0xF>(v));  // row_mirror
+  v = fmax(v, dpp_f64<0x142, 0xA>(v));  // row_bcast:15
+  v = fmax(v, dpp_f64<0x143, 0xC>(v));  // row_bcast:31
+  const long long b = __double_as_longlong(v);
+  const int lo = __builtin_amdgcn_readlane((int)b, 63);
+  const int hi = __builtin_amdgcn_readlane((int)(b >> 32), 63);
+  return __longlong_as_double(((long long)hi << 32) | (unsigned)lo);
+}
+
+constexpr int kMirrorLd = 132;  // LDS column stride of the mirror (doubles, >= 128)
+constexpr int kSeg = 8;         // row blocks per uniformly skipped segment
+
+// The reflector a column would get as the pivot of a step: from its squared
+// norm acc = x0*x0 + tail (x0 the head entry), nr = sqrt(acc),
+// alpha = -sign(x0) nr, v0 = x0 - alpha, tau = 2 / (v0*v0 + tail).  Each
+// owner evaluates this for its own column when it publishes its norm, so the
+// pivot step only has to look the winner's values up.
+__device__ __forceinline__ void reflector_of(double acc, double x0, double tail, double& alpha, double& v0,
+                                             double& tau) {
+  const double nr = sqrt(acc);
+  alpha = 0.0;
+  v0 = 0.0;
+  tau = 0.0;
+  if (nr != 0.0) {
+    alpha = x0 >= 0.0 ? -nr : nr;
+    v0 = x0 - alpha;
+    const double vtv = v0 * v0 + tail;
+    tau = 2.0 / vtv;
+  }
+}
+
+template <int NR>
+__global__ void __launch_bounds__(512) __attribute__((amdgpu_waves_per_eu(1, 2)))
+qrcp_reg_kernel(const double* __restrict__ D, int64_t ldd, int trans, int ell, double* __restrict__ Qout,
+                double* __restrict__ Rout, int32_t* __restrict__ piv) {
+  // M[c * kMirrorLd + i] = W[i, c] (rows l..127 zero), refreshed by each
+  // owner after its update; after the loop the mirror of the pivot column of
+  // step s is turned into the reflector v_s (0 above row s, v0 at s)
+  __shared__ double M[kQrcpRegMax * kMirrorLd];
+  // per logical position, double-buffered: norm, and the reflector the
+  // column there would give; original column index
+  __shared__ double nrm[2][kQrcpRegMax], ralpha[2][kQrcpRegMax], rv0[2][kQrcpRegMax],
+      rtau[2][kQrcpRegMax];
+  __shared__ int colat[2][kQrcpRegMax];
+  __shared__ double alph[kQrcpRegMax], taus[kQrcpRegMax], v0s[kQrcpRegMax];
+  __shared__ int pcol[kQrcpRegMax];
+  constexpr int NS = (NR + kSeg - 1) / kSeg;
+  const int tid = threadIdx.x, lane = tid & 63;
+  const int c = tid >> 2, k = tid & 3;
+  const bool col_ok = c < ell;
+  const int cl = col_ok ? c : ell - 1;
+  double* mc = M + c * kMirrorLd;
+  double w[NR];
+#pragma unroll
+  for (int q = 0; q < NR; ++q) {
+    const int row = 4 * q + k;
+    const int rl = row < ell ? row : ell - 1;
+    const double v = trans ? D[(int64_t)rl * ldd + cl] : D[(int64_t)cl * ldd + rl];
+    w[q] = (row < ell && col_ok) ? v : 0.0;
+    mc[row] = w[q];
+  }
+  int mypos = c;
+  // norms of step 0: head row 0, tail rows 1..
+  if (col_ok) {
+    double a = 0.0;
+#pragma unroll
+    for (int q = 0; q < NR; ++q) {
+      const double sq = w[q] * w[q];
+      a = a + (q > 0 || k >= 1 ? sq : 0.0);
+    }
+    const double tail = combine4_rot(a, k, 1);
+    if (k == 0) {
+      const double acc = w[0] * w[0] + tail;
+      double al, v0, ta;
+      reflector_of(acc, w[0], tail, al, v0, ta);
+      nrm[0][c] = acc;
+      ralpha[0][c] = al;
+      rv0[0][c] = v0;
+      rtau[0][c] = ta;
+      colat[0][c] = c;
+    }
+  }
+  __syncthreads();
+  for (int s = 0; s < ell; s = __builtin_amdgcn_readfirstlane(s + 1)) {
+    const int b = s & 1;
+    // pivot: largest norm (NaN never wins), lowest position on ties
+    const int j0 = s + lane, j1 = j0 + 64;
+    double c0 = j0 < ell ? nrm[b][j0] : -1.0;
+    double c1 = j1 < ell ? nrm[b][j1] : -1.0;
+    c0 = c0 >= 0.0 ? c0 : -1.0;
+    c1 = c1 >= 0.0 ? c1 : -1.0;
+    const double gm = wave_max(fmax(c0, c1));
+    int p = s;  // only NaN norms: keep the current column
+    if (gm >= 0.0) {
+      const unsigned long long m0 = __ballot(c0 == gm);
+      p = m0 ? s + __ffsll((long long)m0) - 1 : s + 64 + __ffsll((long long)__ballot(c1 == gm)) - 1;
+    }
+    p = __builtin_amdgcn_readfirstlane(p);
+    const int cp = __builtin_amdgcn_readfirstlane(colat[b][p]);
+    const double alpha = uniform_f64(ralpha[b][p]);
+    const double v0 = uniform_f64(rv0[b][p]);
+    const double tau = uniform_f64(rtau[b][p]);
+    if (tid == 0) {
+      alph[s] = alpha;
+      taus[s] = tau;
+      v0s[s] = v0;
+      pcol[s] = cp;
+    }
+    if (c == cp)
+      mypos = s;
+    else if (mypos == s)
+      mypos = p;
+    const bool act = col_ok && mypos > s;
+    const int qs = s >> 2, gs = qs / kSeg;
+    // v = (0 above row s, v0, W[s+1:, cp]) from the mirror of column cp: the
+    // segment holding row s is masked, earlier segments hold only rows < s
+    if (act && tau != 0.0) {
+      const double* mp = M + cp * kMirrorLd;
+      double vv[NR];
+#pragma unroll
+      for (int g = 0; g < NS; ++g) {
+        if (g > gs) {
+#pragma unroll
+          for (int q = g * kSeg; q < g * kSeg + kSeg && q < NR; ++q) vv[q] = mp[4 * q + k];
+        } else if (g == gs) {
+#pragma unroll
+          for (int q = g * kSeg; q < g * kSeg + kSeg && q < NR; ++q) {
+            const double x = mp[4 * q + k];
+            const int row = 4 * q + k;
+            vv[q] = row < s ? 0.0 : (row == s ? v0 : x);
+          }
+        }
+      }
+      double a = 0.0;
+#pragma unroll
+      for (int g = 0; g < NS; ++g)
+        if (g >= gs) {
+#pragma unroll
+          for (int q = g * kSeg; q < g * kSeg + kSeg && q < NR; ++q) a = a + vv[q] * w[q];
+        }
+      const double f = combine4_rot(a, k, s) * tau;
+#pragma unroll
+      for (int g = 0; g < NS; ++g)
+        if (g >= gs) {
+#pragma unroll
+          for (int q = g * kSeg; q < g * kSeg + kSeg && q < NR; ++q) {
+            w[q] = w[q] - f * vv[q];
+            mc[4 * q + k] = w[q];
+          }
+        }
+    }
+    if (act && s + 1 < ell) {
+      // norm of step s + 1 (head row s + 1, tail rows s + 2..) and the
+      // reflector this column would give
+      const int qh = (s + 1) >> 2;
+      const int gt = ((s + 2) >> 2) / kSeg;
+      double a = 0.0, hv = 0.0;
+#pragma unroll
+      for (int g = 0; g < NS; ++g) {
+        if (g > gt) {
+#pragma unroll
+          for (int q = g * kSeg; q < g * kSeg + kSeg && q < NR; ++q) a = a + w[q] * w[q];
+        } else if (g == gt) {
+#pragma unroll
+          for (int q = g * kSeg; q < g * kSeg + kSeg && q < NR; ++q) {
+            const double sq = w[q] * w[q];
+            a = a + (4 * q + k >= s + 2 ? sq : 0.0);
+          }
+        }
+      }
+#pragma unroll
+      for (int g = 0; g < NS; ++g)
+        if (g == qh / kSeg) {
+#pragma unroll
+          for (int q = g * kSeg; q < g * kSeg + kSeg && q < NR; ++q) hv = q == qh ? w[q] : hv;
+        }
+      const double tail = combine4_rot(a, k, s + 2);
+      if (k == ((s + 1) & 3)) {
+        const double acc = hv * hv + tail;
+        double al, rv, ta;
+        reflector_of(acc, hv, tail, al, rv, ta);
+        nrm[b ^ 1][mypos] = acc;
+        ralpha[b ^ 1][mypos] = al;
+        rv0[b ^ 1][mypos] = rv;
+        rtau[b ^ 1][mypos] = ta;
+        colat[b ^ 1][mypos] = c;
+      }
+    }
+    __syncthreads();
+  }
+  // R[r][j] = W[r][piv[j]] above the diagonal, alpha_j on it; rows with a
+  // negative diagonal flipped.  Column-major.  The mirror of each column
+  // becomes the reflector of the step that chose it.
+  if (col_ok) {
+    const int jj = mypos;
+    const double v0 = v0s[jj];
+#pragma unroll
+    for (int q = 0; q < NR; ++q) {
+      const int r = 4 * q + k;
+      if (r < ell) {
+        double v = r < jj ? w[q] : (r == jj ? alph[jj] : 0.0);
+        if (alph[r] < 0.0) v = -v;
+        Rout[(int64_t)jj * ell + r] = v;
+        if (r <= jj) mc[r] = r == jj ? v0 : 0.0;
+      }
+    }
+    if (k == 0) piv[jj] = c;
+  }
+  __syncthreads();
+  // Qt = H_0 (H_1 (... H_{l-1} I)): every column is independent, so each
+  // group of four lanes runs the backward loop on its own (no barriers)
+#pragma unroll
+  for (int q = 0; q < NR; ++q) w[q] = (4 * q + k == c) ? 1.0 : 0.0;
+  for (int s = ell - 1; s >= 0; s = __builtin_amdgcn_readfirstlane(s - 1)) {
+    const double ts = taus[s];
+    if (col_ok && c >= s && ts != 0.0) {
+      const double* mp = M + pcol[s] * kMirrorLd;
+      const int gs = (s >> 2) / kSeg;
+      double vv[NR];
+#pragma unroll
+      for (int g = 0; g < NS; ++g)
+        if (g >= gs) {
+#pragma unroll
+          for (int q = g * kSeg; q < g * kSeg + kSeg && q < NR; ++q) vv[q] = mp[4 * q + k];
+        }
+      double a = 0.0;
+#pragma unroll
+      for (int g = 0; g < NS; ++g)
+        if (g >= gs) {
+#pragma unroll
+          for (int q = g * kSeg; q < g * kSeg + kSeg && q < NR; ++q) a += vv[q] * w[q];
+        }
+      a += dpp_f64<0xB1, 0xF>(a);
+      a += dpp_f64<0x4E, 0xF>(a);
+      const double dd = a * ts;
+#pragma unroll
+      for (int g = 0; g < NS; ++g)
+        if (g >= gs) {
+#pragma unroll
+          for (int q = g * kSeg; q < g * kSeg + kSeg && q < NR; ++q) w[q] -= dd * vv[q];
+        }
+    }
+  }
+  if (col_ok) {
+    const double sg = alph[c] < 0.0 ? -1.0 : 1.0;
+#pragma unroll
+    for (int q = 0; q < NR; ++q) {
+      const int row = 4 * q + k;
+      if (row < ell) Qout[(int64_t)c * ell + row] = sg * w[q];
+    }
+  }
 }
 
 // Qt = H_0 (H_1 (... H_{l-1} I)), one thread per column; Q in LDS (row-major).
@@ -214,13 +504,6 @@ __device__ __forceinline__ void qrcp_formq_body(double* __restrict__ Q, double* 
   }
 }
 
-__global__ void __launch_bounds__(1024) qrcp_formq_lds(const double* V, const double* tau,
-                                                      const double* sign, int ell, double* Qout) {
-  __shared__ double Q[kQrcpLdsMax * kQrcpLdsMax];
-  __shared__ double vb[512];
-  qrcp_formq_body(Q, vb, V, tau, sign, ell, Qout);
-}
-
 __global__ void __launch_bounds__(1024) qrcp_formq_global(const double* V, const double* tau,
                                                          const double* sign, int ell, double* Qout,
                                                          double* work) {
@@ -238,9 +521,16 @@ hipError_t launch_qrcp(const double* D, int64_t ldd, int trans, int ell, double*
   double* scratch = work + l2;
   double* tau = work + 2 * l2;
   double* sign = tau + ell;
-  if (ell <= kQrcpLdsMax) {
-    qrcp_pivot_lds<<<dim3(1), dim3(1024), 0, st>>>(D, ldd, trans, ell, R, piv, V, tau, sign);
-    qrcp_formq_lds<<<dim3(1), dim3(1024), 0, st>>>(V, tau, sign, ell, Qt);
+  if (ell <= 32) {
+    qrcp_reg_kernel<8><<<dim3(1), dim3(512), 0, st>>>(D, ldd, trans, ell, Qt, R, piv);
+  } else if (ell <= 64) {
+    qrcp_reg_kernel<16><<<dim3(1), dim3(512), 0, st>>>(D, ldd, trans, ell, Qt, R, piv);
+  } else if (ell <= 96) {
+    qrcp_reg_kernel<24><<<dim3(1), dim3(512), 0, st>>>(D, ldd, trans, ell, Qt, R, piv);
+  } else if (ell <= 112) {
+    qrcp_reg_kernel<28><<<dim3(1), dim3(512), 0, st>>>(D, ldd, trans, ell, Qt, R, piv);
+  } else if (ell <= kQrcpRegMax) {
+    qrcp_reg_kernel<32><<<dim3(1), dim3(512), 0, st>>>(D, ldd, trans, ell, Qt, R, piv);
   } else {
     qrcp_pivot_global<<<dim3(1), dim3(1024), 0, st>>>(D, ldd, trans, ell, R, piv, V, tau, sign, scratch);
     qrcp_formq_global<<<dim3(1), dim3(1024), 0, st>>>(V, tau, sign, ell, Qt, scratch);
