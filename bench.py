@@ -8,7 +8,13 @@ CholeskyQR2 bases, the core, its QRCP and the lifts), inputs resident in HBM.
 
 Printed: one JSON line with the throughput, the dominant kernel's roofline
 (sketch passes, timed with HIP events on the library's stream inside the
-timed region) and the float64 oracle timed on the host on a bounded sample.
+timed region), the float64 oracle timed on the host on a bounded sample, and
+a serving leg: a Poisson stream of requests over a pool of device-resident
+matrices (log-uniform m in [1000, 40000], n in [500, 20000], k in [5, 150],
+sigma_i = exp(-i/k) + 1e-4 noise, p = 10, q in {1, 2}) served one at a time
+in FP64 and with continuous batching in FP64, BF16 and split-BF16, with
+p50/p99 latency (arrival to completion) and the reconstruction error of the
+reduced-precision forms against FP64 on sampled requests.
 """
 import argparse
 import json
@@ -40,6 +46,161 @@ def cpu_threads():
         return os.cpu_count()
 
 
+def measured_traffic():
+    """HBM bytes per sketch launch from the committed FETCH_SIZE/WRITE_SIZE
+    counter summary, or None when the kernel source changed since then."""
+    import hashlib
+
+    path = os.path.join(ROOT, "profiles", "traffic_sketch_f32_20000x15000_k100_q1.txt")
+    src = os.path.join(ROOT, "paper_1906_04572_amd", "csrc", "sketch_gemm.hip")
+    try:
+        text = open(path).read()
+        h = hashlib.sha256(open(src, "rb").read()).hexdigest()
+    except OSError:
+        return None
+    val, ok = None, False
+    for line in text.splitlines():
+        if line.startswith("traffic_bytes_per_launch ="):
+            val = int(line.split("=")[1])
+        if line.startswith("source_sha256(") and line.split("=")[1].strip() == h:
+            ok = True
+    return val if ok else None
+
+
+def pct(xs, p):
+    xs = sorted(xs)
+    if not xs:
+        return None
+    i = min(len(xs) - 1, max(0, int(np.ceil(p / 100.0 * len(xs))) - 1))
+    return xs[i]
+
+
+def serving_leg(cu, torch, n_req, pool_size, seed=5, load=0.8, slots=3):
+    """Serving measurement; returns a dict for the JSON line."""
+    from workloads import serving_pool, serving_stream
+
+    dev = torch.device("cuda", 0)
+    shapes = serving_pool(pool_size, seed)
+    g = torch.Generator(device=dev)
+    g.manual_seed(seed)
+    pool64, pool32 = [], []
+    log("serving: generating %d pool matrices on the device" % pool_size)
+    for sh in shapes:
+        m, n, r, k = sh["m"], sh["n"], sh["r"], sh["k"]
+        U0 = torch.linalg.qr(torch.randn(m, r, generator=g, device=dev, dtype=torch.float64)).Q
+        V0 = torch.linalg.qr(torch.randn(n, r, generator=g, device=dev, dtype=torch.float64)).Q
+        sig = torch.exp(-torch.arange(1, r + 1, device=dev, dtype=torch.float64) / k)
+        A = (U0 * sig) @ V0.T.contiguous()
+        A += 1e-4 * torch.randn(m, n, generator=g, device=dev, dtype=torch.float64)
+        pool64.append(A)
+        pool32.append(A.float())
+        del U0, V0
+    torch.cuda.synchronize()
+    p_over = 10
+    need = max(cu.workspace_bytes(sh["m"], sh["n"], sh["k"], p_over, 2, "f64") for sh in shapes)
+    streams = [torch.cuda.current_stream()] + [torch.cuda.Stream() for _ in range(slots)]
+    ctx = cu.Context(workspace_bytes=slots * need, streams=streams)
+
+    def operand(e, prec):
+        return pool64[e] if prec == "f64" else pool32[e]
+
+    # saturation throughput of the one-at-a-time FP64 path on the stream's mix
+    cal = serving_stream(min(48, n_req), pool_size, 1.0, seed + 1)
+    for r in cal[:8]:  # warm the per-shape launch configurations
+        sh = shapes[r["entry"]]
+        for prec in ("f64", "bf16", "bf16x3"):
+            ctx.decompose(operand(r["entry"], prec), sh["k"], p_over, r["q"], r["seed"], prec=prec)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for r in cal:
+        sh = shapes[r["entry"]]
+        ctx.decompose(pool64[r["entry"]], sh["k"], p_over, r["q"], r["seed"], prec="f64")
+    sat = len(cal) / (time.perf_counter() - t0)
+    qps = load * sat
+    reqs = serving_stream(n_req, pool_size, qps, seed + 2, tags=("f64", "bf16x3"))
+
+    def one_at_a_time(prec, reqs):
+        lat = []
+        t0 = time.perf_counter()
+        for r in reqs:
+            while time.perf_counter() - t0 < r["t"]:
+                time.sleep(0.0001)
+            sh = shapes[r["entry"]]
+            ctx.decompose(operand(r["entry"], prec), sh["k"], p_over, r["q"], r["seed"], prec=prec)
+            lat.append(time.perf_counter() - t0 - r["t"])
+        return lat, time.perf_counter() - t0
+
+    def batched(prec_of, reqs):
+        lat = []
+        pend = {}
+        i = 0
+        t0 = time.perf_counter()
+        while i < len(reqs) or pend:
+            now = time.perf_counter() - t0
+            moved = False
+            while i < len(reqs) and reqs[i]["t"] <= now:
+                r = reqs[i]
+                sh = shapes[r["entry"]]
+                prec = prec_of(r)
+                try:
+                    tk = ctx.submit(operand(r["entry"], prec), sh["k"], p_over, r["q"], r["seed"], prec=prec)
+                except cu.CorutvError as e:
+                    if e.code == cu.E_BUSY:
+                        break
+                    raise
+                pend[tk] = r["t"]
+                i += 1
+                moved = True
+            for tk in list(pend):
+                if ctx.poll(tk) is not None:
+                    lat.append(time.perf_counter() - t0 - pend.pop(tk))
+                    moved = True
+            if not moved:
+                if time.perf_counter() - t0 > 300.0:
+                    raise RuntimeError("serving leg: %d requests still pending after 300 s" % len(pend))
+                time.sleep(0.0001)
+        return lat, time.perf_counter() - t0
+
+    def summary(lat, span):
+        return {"p50_ms": round(pct(lat, 50) * 1e3, 3), "p99_ms": round(pct(lat, 99) * 1e3, 3),
+                "mean_ms": round(float(np.mean(lat)) * 1e3, 3), "decomp_per_s": round(len(lat) / span, 2)}
+
+    modes = {}
+    log("serving: %d requests at %.1f/s (%.0f%% of the one-at-a-time FP64 saturation %.1f/s)"
+        % (n_req, qps, load * 100, sat))
+    modes["f64_one_at_a_time"] = summary(*one_at_a_time("f64", reqs))
+    modes["f64_batched"] = summary(*batched(lambda r: "f64", reqs))
+    modes["bf16x3_batched"] = summary(*batched(lambda r: "bf16x3", reqs))
+    modes["bf16_batched"] = summary(*batched(lambda r: "bf16", reqs))
+    modes["mixed_f64_bf16x3_batched"] = summary(*batched(lambda r: r["tag"], reqs))
+    # saturation: the same requests all arriving at once
+    burst = [dict(r, t=0.0) for r in reqs]
+    saturation = {"f64_one_at_a_time": summary(*one_at_a_time("f64", burst))["decomp_per_s"],
+                  "f64_batched": summary(*batched(lambda r: "f64", burst))["decomp_per_s"],
+                  "bf16x3_batched": summary(*batched(lambda r: "bf16x3", burst))["decomp_per_s"],
+                  "bf16_batched": summary(*batched(lambda r: "bf16", burst))["decomp_per_s"]}
+    # reconstruction error of the reduced-precision forms on sampled requests
+    errs = {"bf16": [], "bf16x3": []}
+    for r in reqs[:: max(1, len(reqs) // 12)][:12]:
+        sh = shapes[r["entry"]]
+        e64 = ctx.decompose(pool64[r["entry"]], sh["k"], p_over, r["q"], r["seed"], prec="f64",
+                            want_err=True)[4]["rel_err"]
+        for prec in errs:
+            e = ctx.decompose(pool32[r["entry"]], sh["k"], p_over, r["q"], r["seed"], prec=prec,
+                              want_err=True)[4]["rel_err"]
+            errs[prec].append(abs(e - e64))
+    ctx.close()
+    eq = {prec: {"max_abs_diff_vs_f64": float(max(v)), "within_1e-5": int(sum(x <= 1e-5 for x in v)),
+                 "sampled": len(v)} for prec, v in errs.items()}
+    return {"requests": n_req, "pool": pool_size, "slots": slots, "qps": round(qps, 2),
+            "f64_one_at_a_time_saturation_per_s": round(sat, 2), "load": load, "modes": modes,
+            "saturation_decomp_per_s": saturation,
+            "equal_error": eq,
+            "workload": "Poisson stream; pool of %d device-resident matrices, m log-uniform [1000,40000], "
+                        "n log-uniform [500,20000], k uniform [5,150], sigma_i=exp(-i/k)+1e-4 noise, "
+                        "p=10, q in {1,2}" % pool_size}
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -50,6 +211,9 @@ def main():
     ap.add_argument("--cpu-sample", type=int, default=2, help="oracle decompositions timed on the host")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-variants", action="store_true")
+    ap.add_argument("--serving-requests", type=int, default=160)
+    ap.add_argument("--serving-pool", type=int, default=12)
+    ap.add_argument("--no-serving", action="store_true")
     args = ap.parse_args()
     if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) != 1:
         print("bench.py measures one GPU only: this build has no multi-GPU path "
@@ -94,7 +258,8 @@ def main():
     achieved = flops_pass / (avg_pass_ms * 1e-3) / 1e12
     peak, bound = PEAK[args.prec]
     roof = {"bound": bound, "achieved": round(achieved, 2), "peak": peak, "unit": "TFLOP/s",
-            "frac": round(achieved / peak, 4), "traffic": None,
+            "frac": round(achieved / peak, 4),
+            "traffic": measured_traffic() if args.prec == "f32" and args.q == 1 else None,
             "kernel": "sketch_kernel (one pass over A)", "avg_pass_ms": round(avg_pass_ms, 4),
             "min_pass_ms": round(st["min_ms"], 4), "max_pass_ms": round(st["max_ms"], 4),
             "passes_timed": st["passes"], "hbm_GBps": round(bytes_pass / (avg_pass_ms * 1e-3) / 1e9, 1),
@@ -118,6 +283,12 @@ def main():
                 "frac_of_peak": round(flops_pass / (vpass * 1e-3) / 1e12 / PEAK[prec][0], 4)}
             del Av
     ctx.close()
+    del A_main, A32
+    torch.cuda.empty_cache()
+
+    serving = None
+    if not args.no_serving:
+        serving = serving_leg(cu, torch, args.serving_requests, args.serving_pool)
 
     cpu = None
     parity = {"rel_err_gpu": rel_gpu}
@@ -152,6 +323,7 @@ def main():
         "cpu_baseline": cpu,
         "parity": parity,
         "variants": variants,
+        "serving": serving,
     }
     print(json.dumps(line), flush=True)
 

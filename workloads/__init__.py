@@ -21,6 +21,9 @@ Shapes and structure:
   are either uniform in [-amp, amp] or drawn from {-amp, +amp} (Table 1).
 * ``serving_requests`` -- a Poisson stream of decomposition requests with
   log-uniform m, n, uniform k, sigma_i = exp(-i/k) truncated at 1e-4.
+* ``serving_pool`` / ``serving_stream`` -- the same distributions split into
+  a pool of distinct request matrices (shape and rank) and a Poisson stream
+  of requests that each pick a pool entry, q, a precision tag and a seed.
 """
 import numpy as np
 
@@ -126,3 +129,31 @@ def serving_matrix(m, n, k, seed, dtype=np.float64):
     """sigma_i = exp(-i/k) for i <= min(ceil(9.2 k), min(m, n) // 2), plus 1e-4 noise."""
     r = int(min(np.ceil(9.2 * k), min(m, n) // 2))
     return decaying(m, n, r, 1e-4, seed, kind="exp", tau=float(k), dtype=dtype)
+
+
+def serving_pool(count, seed, m_range=(1000, 40000), n_range=(500, 20000), k_range=(5, 150), p=10):
+    """count distinct request shapes: list of dicts {m, n, k, r} with m, n
+    log-uniform, k uniform, r = min(ceil(9.2 k), min(m, n) // 2) decaying
+    singular values (exp(-i/k) down to 1e-4)."""
+    rng = _rng(seed)
+    out = []
+    for _ in range(count):
+        m = int(np.exp(rng.uniform(np.log(m_range[0]), np.log(m_range[1]))))
+        n = int(np.exp(rng.uniform(np.log(n_range[0]), np.log(n_range[1]))))
+        k = int(rng.integers(k_range[0], k_range[1] + 1))
+        k = int(min(k, min(m, n) - p))
+        r = int(min(np.ceil(9.2 * k), min(m, n) // 2))
+        out.append(dict(m=m, n=n, k=k, r=r))
+    return out
+
+
+def serving_stream(count, pool_size, qps, seed, tags=("f64", "bf16")):
+    """Poisson arrivals at rate qps: list of dicts {t, entry, q, tag, seed}."""
+    rng = _rng(seed)
+    t = np.cumsum(rng.exponential(1.0 / qps, size=count))
+    entry = rng.integers(0, pool_size, size=count)
+    q = rng.integers(1, 3, size=count)
+    tag = rng.integers(0, len(tags), size=count)
+    om = rng.integers(0, 2**62, size=count)
+    return [dict(t=float(t[i]), entry=int(entry[i]), q=int(q[i]), tag=tags[int(tag[i])], seed=int(om[i]))
+            for i in range(count)]
