@@ -10,8 +10,12 @@
 //             its four owners (thread k holds rows k, k+4, ...) and mirrored
 //             in LDS for the pivot broadcast; one barrier per step (the norm
 //             arrays are double-buffered); Qt formed in the same launch;
+//   l <= 192: qrcp_big_kernel, the same register layout (768 threads at
+//             most), pivot column broadcast through LDS, reflectors staged
+//             through device memory for Qt;
 //   l <= 256: qrcp_pivot_global + qrcp_formq_global, 1024 threads, the
-//             working matrix in device memory, two barriers per step.
+//             working matrix in device memory (column-major), two barriers
+//             per step.
 //
 // The arithmetic order is fixed so that the pivot sequence is a function of
 // the input bits only (each product and sum rounded separately: this file is
@@ -37,7 +41,7 @@ namespace {
 
 constexpr int kQrcpRegMax = 128;  // columns in registers up to this size
 
-// W: row-major l x l (element (i, c) at W[i*l + c], c = original column).
+// W: column-major l x l (element (i, c) at W[c*l + i], c = original column).
 // 1024 threads: thread t serves logical column t/4 and the residue class
 // k = t%4 of the sum4 partial sums (positions k, k+4, ... of each ordered
 // term list).  The four lanes of a column are adjacent, so the combination
@@ -65,7 +69,7 @@ __device__ __forceinline__ void qrcp_pivot_body(double* __restrict__ W, double* 
   const int nt = blockDim.x;
   for (int e = tid; e < ell * ell; e += nt) {
     const int i = e / ell, c = e % ell;
-    W[e] = trans ? D[(int64_t)i * ldd + c] : D[(int64_t)c * ldd + i];
+    W[(int64_t)c * ell + i] = trans ? D[(int64_t)i * ldd + c] : D[(int64_t)c * ldd + i];
   }
   if (tid < ell) pv[tid] = tid;  // buffer 0
   __syncthreads();
@@ -79,12 +83,12 @@ __device__ __forceinline__ void qrcp_pivot_body(double* __restrict__ W, double* 
       const int c = pin[j];
       double a = 0.0;
       for (int i = s + 1 + k; i < ell; i += 4) {
-        const double w = W[i * ell + c];
+        const double w = W[(int64_t)c * ell + i];
         a = a + w * w;
       }
       const double t = combine4(a);
       if (k == 0) {
-        const double h = W[s * ell + c];
+        const double h = W[(int64_t)c * ell + s];
         tl[j] = t;
         nrm[j] = h * h + t;
       }
@@ -120,7 +124,7 @@ __device__ __forceinline__ void qrcp_pivot_body(double* __restrict__ W, double* 
     const double nr = sqrt(best);
     double tau = 0.0, alpha = 0.0, v0 = 0.0;
     if (nr != 0.0) {
-      const double x0 = W[s * ell + cp];
+      const double x0 = W[(int64_t)cp * ell + s];
       alpha = x0 >= 0.0 ? -nr : nr;
       v0 = x0 - alpha;
       const double vtv = v0 * v0 + tl[p];
@@ -134,17 +138,17 @@ __device__ __forceinline__ void qrcp_pivot_body(double* __restrict__ W, double* 
       const int c = j == p ? pin[s] : pin[j];
       // terms at positions q = i - s: q = 0 -> v0 W[s,c]; q > 0 -> W[i,cp] W[i,c]
       double a = 0.0;
-      if (k == 0) a = a + v0 * W[s * ell + c];
-      for (int i = s + (k == 0 ? 4 : k); i < ell; i += 4) a = a + W[i * ell + cp] * W[i * ell + c];
+      if (k == 0) a = a + v0 * W[(int64_t)c * ell + s];
+      for (int i = s + (k == 0 ? 4 : k); i < ell; i += 4) a = a + W[(int64_t)cp * ell + i] * W[(int64_t)c * ell + i];
       const double d = combine4(a);
       const double f = d * tau;
-      if (k == 0) W[s * ell + c] = W[s * ell + c] - f * v0;
+      if (k == 0) W[(int64_t)c * ell + s] = W[(int64_t)c * ell + s] - f * v0;
       for (int i = s + (k == 0 ? 4 : k); i < ell; i += 4)
-        W[i * ell + c] = W[i * ell + c] - f * W[i * ell + cp];
+        W[(int64_t)c * ell + i] = W[(int64_t)c * ell + i] - f * W[(int64_t)cp * ell + i];
     }
     // reflector of step s: v_s = (v0, W[s+1:, cp]); column cp is not touched
     // by later steps (its logical position s < every later trailing column)
-    if (tid < ell) Vout[(int64_t)s * ell + tid] = tid < s ? 0.0 : (tid == s ? v0 : W[tid * ell + cp]);
+    if (tid < ell) Vout[(int64_t)s * ell + tid] = tid < s ? 0.0 : (tid == s ? v0 : W[(int64_t)cp * ell + tid]);
     cur ^= 1;
     __syncthreads();
   }
@@ -155,7 +159,7 @@ __device__ __forceinline__ void qrcp_pivot_body(double* __restrict__ W, double* 
     const int r = e % ell, jj = e / ell;  // column-major: row r, column jj
     double v = 0.0;
     if (jj > r)
-      v = W[r * ell + pfin[jj]];
+      v = W[(int64_t)pfin[jj] * ell + r];
     else if (jj == r)
       v = alph[r];
     if (alph[r] < 0.0) v = -v;
@@ -471,6 +475,226 @@ qrcp_reg_kernel(const double* __restrict__ D, int64_t ldd, int trans, int ell, d
   }
 }
 
+// ---------------------------------------------------------------------------
+// 128 < l <= 192: the same per-column register layout with 4 * ceil(l/4)
+// rows per column (NR = 40 or 48 per thread), 16 NR threads (at most 12
+// waves, so a thread may hold 96 registers of column data).  The l x l
+// mirror would not fit in LDS, so the pivot column is broadcast through a
+// zero-padded LDS vector written by its owners after the pivot search (two
+// barriers per step), and each reflector is also written to device memory;
+// Qt is then formed from chunks of reflectors staged through LDS.
+constexpr int kBigMax = 192;
+constexpr int kVChunk = 64;
+
+template <int NR>
+__global__ void __launch_bounds__(16 * NR)
+qrcp_big_kernel(const double* __restrict__ D, int64_t ldd, int trans, int ell, double* __restrict__ Qout,
+                double* __restrict__ Rout, int32_t* __restrict__ piv, double* __restrict__ Vg) {
+  constexpr int LP = 4 * NR;              // padded rows and columns
+  constexpr int NC = (LP + 63) / 64;      // pivot candidates per lane
+  constexpr int NS = (NR + kSeg - 1) / kSeg;
+  __shared__ double nrm[2][LP], ralpha[2][LP], rv0[2][LP], rtau[2][LP];
+  __shared__ int colat[2][LP];
+  __shared__ double vcol[LP];
+  __shared__ double alph[LP], taus[LP];
+  __shared__ double vch[kVChunk * LP];
+  const int tid = threadIdx.x, lane = tid & 63, nt = blockDim.x;
+  const int c = tid >> 2, k = tid & 3;
+  const bool col_ok = c < ell;
+  const int cl = col_ok ? c : ell - 1;
+  double w[NR];
+#pragma unroll
+  for (int q = 0; q < NR; ++q) {
+    const int row = 4 * q + k;
+    const int rl = row < ell ? row : ell - 1;
+    const double v = trans ? D[(int64_t)rl * ldd + cl] : D[(int64_t)cl * ldd + rl];
+    w[q] = (row < ell && col_ok) ? v : 0.0;
+  }
+  for (int i = tid; i < LP; i += nt) vcol[i] = 0.0;
+  int mypos = c;
+  if (col_ok) {
+    double a = 0.0;
+#pragma unroll
+    for (int q = 0; q < NR; ++q) {
+      const double sq = w[q] * w[q];
+      a = a + (q > 0 || k >= 1 ? sq : 0.0);
+    }
+    const double tail = combine4_rot(a, k, 1);
+    if (k == 0) {
+      const double acc = w[0] * w[0] + tail;
+      double al, v0, ta;
+      reflector_of(acc, w[0], tail, al, v0, ta);
+      nrm[0][c] = acc;
+      ralpha[0][c] = al;
+      rv0[0][c] = v0;
+      rtau[0][c] = ta;
+      colat[0][c] = c;
+    }
+  }
+  __syncthreads();
+  for (int s = 0; s < ell; s = __builtin_amdgcn_readfirstlane(s + 1)) {
+    const int b = s & 1;
+    // pivot: largest norm (NaN never wins), lowest position on ties; the
+    // candidates of round h are positions s + 64h + lane, so the first
+    // round holding the maximum gives the lowest position
+    double cand[NC];
+    double cb = -1.0;
+#pragma unroll
+    for (int h = 0; h < NC; ++h) {
+      const int j = s + lane + 64 * h;
+      const double v = j < ell ? nrm[b][j] : -1.0;
+      cand[h] = v >= 0.0 ? v : -1.0;
+      cb = fmax(cb, cand[h]);
+    }
+    const double gm = wave_max(cb);
+    int p = s;  // only NaN norms: keep the current column
+    if (gm >= 0.0) {
+#pragma unroll
+      for (int h = NC - 1; h >= 0; --h) {
+        const unsigned long long m = __ballot(cand[h] == gm);
+        if (m) p = s + 64 * h + __ffsll((long long)m) - 1;
+      }
+    }
+    p = __builtin_amdgcn_readfirstlane(p);
+    const int cp = __builtin_amdgcn_readfirstlane(colat[b][p]);
+    const double alpha = uniform_f64(ralpha[b][p]);
+    const double v0 = uniform_f64(rv0[b][p]);
+    const double tau = uniform_f64(rtau[b][p]);
+    if (c == cp) {  // reflector v_s = (0 above row s, v0, W[s+1:, cp])
+#pragma unroll
+      for (int q = 0; q < NR; ++q) {
+        const int row = 4 * q + k;
+        if (row < ell) {
+          const double v = row < s ? 0.0 : (row == s ? v0 : w[q]);
+          vcol[row] = v;
+          Vg[(int64_t)s * ell + row] = v;
+        }
+      }
+    }
+    if (tid == 0) {
+      alph[s] = alpha;
+      taus[s] = tau;
+    }
+    if (c == cp)
+      mypos = s;
+    else if (mypos == s)
+      mypos = p;
+    const bool act = col_ok && mypos > s;
+    __syncthreads();
+    const int gs = (s >> 2) / kSeg;
+    if (act && tau != 0.0) {
+      double a = 0.0;
+#pragma unroll
+      for (int g = 0; g < NS; ++g)
+        if (g >= gs) {
+#pragma unroll
+          for (int q = g * kSeg; q < g * kSeg + kSeg && q < NR; ++q) a = a + vcol[4 * q + k] * w[q];
+        }
+      const double f = combine4_rot(a, k, s) * tau;
+#pragma unroll
+      for (int g = 0; g < NS; ++g)
+        if (g >= gs) {
+#pragma unroll
+          for (int q = g * kSeg; q < g * kSeg + kSeg && q < NR; ++q) w[q] = w[q] - f * vcol[4 * q + k];
+        }
+    }
+    if (act && s + 1 < ell) {
+      const int qh = (s + 1) >> 2;
+      const int gt = ((s + 2) >> 2) / kSeg;
+      double a = 0.0, hv = 0.0;
+#pragma unroll
+      for (int g = 0; g < NS; ++g) {
+        if (g > gt) {
+#pragma unroll
+          for (int q = g * kSeg; q < g * kSeg + kSeg && q < NR; ++q) a = a + w[q] * w[q];
+        } else if (g == gt) {
+#pragma unroll
+          for (int q = g * kSeg; q < g * kSeg + kSeg && q < NR; ++q) {
+            const double sq = w[q] * w[q];
+            a = a + (4 * q + k >= s + 2 ? sq : 0.0);
+          }
+        }
+      }
+#pragma unroll
+      for (int g = 0; g < NS; ++g)
+        if (g == qh / kSeg) {
+#pragma unroll
+          for (int q = g * kSeg; q < g * kSeg + kSeg && q < NR; ++q) hv = q == qh ? w[q] : hv;
+        }
+      const double tail = combine4_rot(a, k, s + 2);
+      if (k == ((s + 1) & 3)) {
+        const double acc = hv * hv + tail;
+        double al, rv, ta;
+        reflector_of(acc, hv, tail, al, rv, ta);
+        nrm[b ^ 1][mypos] = acc;
+        ralpha[b ^ 1][mypos] = al;
+        rv0[b ^ 1][mypos] = rv;
+        rtau[b ^ 1][mypos] = ta;
+        colat[b ^ 1][mypos] = c;
+      }
+    }
+    __syncthreads();
+  }
+  if (col_ok) {
+    const int jj = mypos;
+#pragma unroll
+    for (int q = 0; q < NR; ++q) {
+      const int r = 4 * q + k;
+      if (r < ell) {
+        double v = r < jj ? w[q] : (r == jj ? alph[jj] : 0.0);
+        if (alph[r] < 0.0) v = -v;
+        Rout[(int64_t)jj * ell + r] = v;
+      }
+    }
+    if (k == 0) piv[jj] = c;
+  }
+  // Qt = H_0 (H_1 (... H_{l-1} I)), reflectors staged through LDS in chunks
+  // of kVChunk (last chunk first); within a chunk every column runs on its
+  // own (no barriers)
+#pragma unroll
+  for (int q = 0; q < NR; ++q) w[q] = (4 * q + k == c) ? 1.0 : 0.0;
+  for (int end = ell; end > 0; end -= kVChunk) {
+    const int lo = end > kVChunk ? end - kVChunk : 0;
+    __syncthreads();
+    for (int e = tid; e < (end - lo) * LP; e += nt) {
+      const int si = e / LP, i = e % LP;
+      vch[e] = i < ell ? Vg[(int64_t)(lo + si) * ell + i] : 0.0;
+    }
+    __syncthreads();
+    for (int s = end - 1; s >= lo; s = __builtin_amdgcn_readfirstlane(s - 1)) {
+      const double ts = taus[s];
+      if (col_ok && c >= s && ts != 0.0) {
+        const double* v = vch + (s - lo) * LP;
+        const int gs = (s >> 2) / kSeg;
+        double a = 0.0;
+#pragma unroll
+        for (int g = 0; g < NS; ++g)
+          if (g >= gs) {
+#pragma unroll
+            for (int q = g * kSeg; q < g * kSeg + kSeg && q < NR; ++q) a += v[4 * q + k] * w[q];
+          }
+        a += dpp_f64<0xB1, 0xF>(a);
+        a += dpp_f64<0x4E, 0xF>(a);
+        const double dd = a * ts;
+#pragma unroll
+        for (int g = 0; g < NS; ++g)
+          if (g >= gs) {
+#pragma unroll
+            for (int q = g * kSeg; q < g * kSeg + kSeg && q < NR; ++q) w[q] -= dd * v[4 * q + k];
+          }
+      }
+    }
+  }
+  if (col_ok) {
+    const double sg = alph[c] < 0.0 ? -1.0 : 1.0;
+#pragma unroll
+    for (int q = 0; q < NR; ++q) {
+      const int row = 4 * q + k;
+      if (row < ell) Qout[(int64_t)c * ell + row] = sg * w[q];
+    }
+  }
+}
+
 // Qt = H_0 (H_1 (... H_{l-1} I)), one thread per column; Q in LDS (row-major).
 // The reflector of the next step is staged into LDS (double-buffered) while
 // the current one is applied, so each step has one barrier.
@@ -490,17 +714,17 @@ __device__ __forceinline__ void qrcp_formq_body(double* __restrict__ Q, double* 
     const double ts = tau[s];
     if (ts != 0.0 && j >= s && j < ell) {
       double a = 0.0;
-      for (int i = s + k; i < ell; i += 4) a += v[i] * Q[i * ell + j];
+      for (int i = s + k; i < ell; i += 4) a += v[i] * Q[(int64_t)j * ell + i];
       a += __shfl_xor(a, 1, 64);
       a += __shfl_xor(a, 2, 64);
       const double d = a * ts;
-      for (int i = s + k; i < ell; i += 4) Q[i * ell + j] -= d * v[i];
+      for (int i = s + k; i < ell; i += 4) Q[(int64_t)j * ell + i] -= d * v[i];
     }
     __syncthreads();
   }
   for (int e = tid; e < ell * ell; e += nt) {
     const int i = e % ell, c = e / ell;  // column-major output
-    Qout[e] = sign[c] * Q[i * ell + c];
+    Qout[e] = sign[c] * Q[e];
   }
 }
 
@@ -531,6 +755,10 @@ hipError_t launch_qrcp(const double* D, int64_t ldd, int trans, int ell, double*
     qrcp_reg_kernel<28><<<dim3(1), dim3(512), 0, st>>>(D, ldd, trans, ell, Qt, R, piv);
   } else if (ell <= kQrcpRegMax) {
     qrcp_reg_kernel<32><<<dim3(1), dim3(512), 0, st>>>(D, ldd, trans, ell, Qt, R, piv);
+  } else if (ell <= 160) {
+    qrcp_big_kernel<40><<<dim3(1), dim3(640), 0, st>>>(D, ldd, trans, ell, Qt, R, piv, V);
+  } else if (ell <= kBigMax) {
+    qrcp_big_kernel<48><<<dim3(1), dim3(768), 0, st>>>(D, ldd, trans, ell, Qt, R, piv, V);
   } else {
     qrcp_pivot_global<<<dim3(1), dim3(1024), 0, st>>>(D, ldd, trans, ell, R, piv, V, tau, sign, scratch);
     qrcp_formq_global<<<dim3(1), dim3(1024), 0, st>>>(V, tau, sign, ell, Qt, scratch);

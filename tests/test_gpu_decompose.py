@@ -87,6 +87,7 @@ def test_plain_config_2000x1500_rank20_lower(ctx):
     (3000, 250, 5, 5, 1, "auto", "row"),
     (700, 700, 100, 28, 1, "auto", "row"),
     (2100, 1900, 150, 50, 0, "upper", "row"),
+    (1800, 1500, 120, 20, 1, "lower", "row"),
 ])
 def test_f64_cases(ctx, m, n, k, p, q, tri, layout):
     _say("f64", m, n, k, p, q, tri, layout)

@@ -106,7 +106,7 @@ def _cores():
     A = noisy_low_rank(400, 300, 20, 1e-6, seed=1)
     out.append(("c1-like", corutv(A, 20, 10, 1, seed=1)["D"]))
     rng = np.random.default_rng(5)
-    for ell in (10, 30, 110, 128, 129, 200, 256):
+    for ell in (10, 30, 110, 128, 129, 150, 180, 200, 256):
         out.append(("gauss%d" % ell, rng.standard_normal((ell, ell)) * np.logspace(0, -8, ell)))
     D = rng.standard_normal((40, 6)) @ rng.standard_normal((6, 40))
     out.append(("rank6", D))
