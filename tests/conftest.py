@@ -10,4 +10,4 @@ if ROOT not in sys.path:
 
 def pytest_configure(config):
     config.addinivalue_line("markers", "gpu: needs an MI355X (runs through the C-ABI library)")
-    config.addinivalue_line("markers", "slow: CPU test that takes more than ~20 s")
+    config.addinivalue_line("markers", "slow: test that takes more than ~20 s")

@@ -182,3 +182,63 @@ def test_precision_forms_polynomial_decay(ctx, prec, bound):
     assert d <= bound
     assert np.max(np.abs(U.T @ U - np.eye(220))) <= 1e-5
     assert np.max(np.abs(V.T @ V - np.eye(220))) <= 1e-5
+
+
+@pytest.mark.slow
+def test_full_size_20000x15000_f32_against_oracle(ctx):
+    """The 20000 x 15000 plain configuration at its real size, in the launch
+    configuration bench.py times (F32, k = 100, p = 10, q = 1): |e_gpu -
+    e_oracle| <= 1e-5 with the oracle in float64 on the same float32 data,
+    orthonormal bases to FP32 accuracy, exactly triangular T."""
+    _say("full size 20000x15000 f32 q=1 vs oracle")
+    A = decaying(20000, 15000, 300, 1e-4, seed=2, kind="exp", tau=25.0, dtype=np.float32)
+    U, T, V, piv, info = _run(ctx, A, 100, 10, 1, 1, "f32", "auto")
+    A64 = A.astype(np.float64)
+    ref = corutv(A64, 100, 10, 1, seed=1)
+    e_ref = rel_err(A64, ref["U"], ref["T"], ref["V"])
+    print("full size: e_gpu %.10e e_oracle %.10e" % (info["rel_err"], e_ref))
+    assert abs(info["rel_err"] - e_ref) <= 1e-5
+    assert abs(rel_err(A64, U, T, V) - e_ref) <= 1e-5
+    assert np.max(np.abs(U.T @ U - np.eye(110))) <= 1e-5
+    assert np.max(np.abs(V.T @ V - np.eye(110))) <= 1e-5
+    assert np.all(np.tril(T, -1) == 0)
+
+
+@pytest.mark.slow
+def test_full_size_precision_forms_50000x30000(ctx):
+    """The precision-form configuration at its real size (50000 x 30000,
+    sigma_i = i^-1.5 for i <= 1000 plus 1e-5 noise, k = 200, p = 20, q = 2;
+    l = 220).  Too large for the host oracle; checked through properties
+    that hold at any size: each reduced-precision form against the GPU FP64
+    path on the same data (itself oracle-checked at smaller sizes), the
+    bases orthonormal and T triangular.  The data is drawn on the device
+    (seeded torch generator) from the same recipe."""
+    _say("full size 50000x30000 precision forms")
+    m, n, r = 50000, 30000, 1000
+    g = torch.Generator(device="cuda")
+    g.manual_seed(3)
+    U0 = torch.linalg.qr(torch.randn(m, r, generator=g, device="cuda", dtype=torch.float64)).Q
+    V0 = torch.linalg.qr(torch.randn(n, r, generator=g, device="cuda", dtype=torch.float64)).Q
+    sig = torch.arange(1, r + 1, device="cuda", dtype=torch.float64) ** -1.5
+    A = (U0 * sig) @ V0.T.contiguous()
+    del U0, V0
+    A += 1e-5 * torch.randn(m, n, generator=g, device="cuda", dtype=torch.float64)
+    A32 = A.float()
+    A = A32.double()  # the FP64 path sees exactly the float32 data
+    import paper_1906_04572_amd as cu
+
+    need = max(cu.workspace_bytes(m, n, 200, 20, 2, p) for p in ("f64", "f32"))
+    big = cu.Context(workspace_bytes=need)
+    e64 = big.decompose(A, 200, 20, 2, 11, prec="f64", want_err=True)[4]["rel_err"]
+    del A
+    for prec, bound in (("bf16x3", 1e-5), ("f32", 1e-5), ("bf16", 2e-3)):
+        U, T, V, piv, info = big.decompose(A32, 200, 20, 2, 11, prec=prec, want_err=True)
+        d = abs(info["rel_err"] - e64)
+        print("50000x30000 %s: e %.8e e_f64 %.8e |diff| %.3e" % (prec, info["rel_err"], e64, d))
+        assert d <= bound
+        Ud, Vd = U.double(), V.double()
+        eye = torch.eye(220, dtype=torch.float64, device="cuda")
+        assert torch.max(torch.abs(Ud.T @ Ud - eye)).item() <= 1e-5
+        assert torch.max(torch.abs(Vd.T @ Vd - eye)).item() <= 1e-5
+        assert torch.all(torch.tril(T, -1) == 0).item()
+    big.close()
