@@ -233,15 +233,15 @@ def main():
     ws = max(cu.workspace_bytes(M, N, K_RANK, P_OVER, 2, p) for p in ("f32", "f64"))
     ctx = cu.Context(workspace_bytes=ws)
 
-    def timed(A, prec, q, steps, warmup):
+    def timed(A, prec, q, steps, warmup, core="pass"):
         out = ctx.alloc_outputs(A, K_RANK, P_OVER)
         for i in range(warmup):
-            ctx.decompose(A, K_RANK, P_OVER, q, seed=1000 + i, prec=prec, out=out)
+            ctx.decompose(A, K_RANK, P_OVER, q, seed=1000 + i, prec=prec, out=out, core=core)
         ctx.pass_timing(True, reset=True)
         torch.cuda.synchronize()
         t0 = time.perf_counter()
         for i in range(steps):
-            ctx.decompose(A, K_RANK, P_OVER, q, seed=i + 1, prec=prec, out=out)
+            ctx.decompose(A, K_RANK, P_OVER, q, seed=i + 1, prec=prec, out=out, core=core)
         torch.cuda.synchronize()
         dt = time.perf_counter() - t0
         st = ctx.pass_stats()
@@ -270,17 +270,23 @@ def main():
 
     variants = {}
     if not args.no_variants:
-        for prec, q in (("f32", 0), ("f32", 2), ("f64", 1)):
-            if prec == args.prec and q == args.q:
+        for prec, q, core in (("f32", 0, "pass"), ("f32", 2, "pass"), ("f64", 1, "pass"), ("f32", 1, "rz"),
+                              ("bf16x3", 1, "pass"), ("bf16", 1, "pass")):
+            if prec == args.prec and q == args.q and core == "pass":
                 continue
-            Av = A32 if prec == "f32" else A32.double()
-            vdt, vst = timed(Av, prec, q, 5, 2)
+            Av = A32 if prec != "f64" else A32.double()
+            vdt, vst = timed(Av, prec, q, 5, 2, core=core)
             vpass = vst["total_ms"] / max(vst["passes"], 1)
-            variants["%s_q%d" % (prec, q)] = {
+            name = "%s_q%d" % (prec, q) + ("_core_rz" if core == "rz" else "")
+            peak_v = PEAK.get(prec, PEAK["f32"])[0]
+            variants[name] = {
                 "corutv_per_s": round(5 / vdt, 2), "ms_per_step": round(vdt / 5 * 1e3, 3),
                 "avg_pass_ms": round(vpass, 4),
                 "sketch_tflops": round(flops_pass / (vpass * 1e-3) / 1e12, 2),
-                "frac_of_peak": round(flops_pass / (vpass * 1e-3) / 1e12 / PEAK[prec][0], 4)}
+                "hbm_GBps": round(M * N * (8 if prec == "f64" else 4) / (vpass * 1e-3) / 1e9, 1),
+                "passes_per_step": 2 * q + (2 if core == "rz" else 3)}
+            if prec in PEAK:
+                variants[name]["frac_of_peak"] = round(flops_pass / (vpass * 1e-3) / 1e12 / peak_v, 4)
             del Av
     ctx.close()
     del A_main, A32

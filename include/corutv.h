@@ -79,8 +79,15 @@ typedef struct corutv_opts {
   int32_t tri;       /* enum corutv_tri                                      */
   int32_t want_err;  /* nonzero: compute ||A - U T V^T||_F / ||A||_F (one    */
                      /* extra pass over A, not part of the method)           */
-  int32_t flags;     /* reserved, 0                                          */
+  int32_t flags;     /* CORUTV_FLAG_* bits; other bits must be 0             */
 } corutv_opts;
+
+/* corutv_opts.flags: form the core from the R factor of the second sketch
+ * instead of a third pass over A.  With Q2 R_Z = Z = A^T Q1 the core is
+ * D = Q1^T A Q2 = R_Z^T exactly (Sec. 3.1, eqs. 5-7), so the decomposition
+ * needs 2q + 2 passes instead of 2q + 3 and returns the same factors in exact
+ * arithmetic (in floating point D differs at the rounding level of the passes). */
+#define CORUTV_FLAG_CORE_FROM_RZ 1
 
 typedef struct corutv_info {
   double rel_err;        /* relative Frobenius error if want_err, else -1       */

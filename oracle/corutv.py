@@ -39,9 +39,13 @@ def _qf(X):
     return householder_qr(X)[0]
 
 
-def corutv(A, k, p, q, seed, tri="auto", sub=0, mode="stabilized"):
+def corutv(A, k, p, q, seed, tri="auto", sub=0, mode="stabilized", core="pass"):
     """Rank-l CoR-UTV of A (l = k + p).  Returns a dict with U, T, V, piv and
-    the intermediates Omega, Q1, Q2, D (and R_Z in stabilized mode)."""
+    the intermediates Omega, Q1, Q2, D (and R_Z in stabilized mode).
+
+    core: "pass" forms D = Q1^T (A Q2) (eq. 7, one more product with A);
+    "rz" (stabilized mode) takes D = R_Z^T from the QR of the second sketch
+    Z = A^T Q1 = Q2 R_Z, since then Q1^T A Q2 = (A^T Q1)^T Q2 = R_Z^T Q2^T Q2."""
     A = np.asarray(A, dtype=np.float64)
     m, n = A.shape
     ell = k + p
@@ -53,7 +57,7 @@ def corutv(A, k, p, q, seed, tri="auto", sub=0, mode="stabilized"):
         raise ValueError("tri must be auto, upper or lower")
     if m < n:
         inner = corutv(A.T, k, p, q, seed, tri="lower" if tri == "upper" else "upper",
-                       sub=sub, mode=mode)
+                       sub=sub, mode=mode, core=core)
         out = dict(inner)
         out.update(U=inner["V"], T=inner["T"].T.copy(), V=inner["U"], transposed=True)
         return out
@@ -79,7 +83,12 @@ def corutv(A, k, p, q, seed, tri="auto", sub=0, mode="stabilized"):
     else:
         raise ValueError("mode must be literal or stabilized")
 
-    D = Q1.T @ (A @ Q2)
+    if core == "pass":
+        D = Q1.T @ (A @ Q2)
+    elif core == "rz" and mode == "stabilized":
+        D = res["R_Z"].T.copy()
+    else:
+        raise ValueError("core must be pass, or rz in stabilized mode")
     if tri == "upper":
         Qt, R, piv = qrcp(D)
         U, T, V = Q1 @ Qt, R, Q2[:, piv]

@@ -15,6 +15,8 @@ LIB_PATH = os.path.join(_HERE, "libcorutv.so")
 
 OK, PENDING = 0, 1
 E_INVAL, E_NOMEM, E_BUSY, E_NUMERIC, E_DEVICE, E_NOTFOUND = -1, -2, -3, -4, -5, -6
+FLAG_CORE_FROM_RZ = 1  # core D = R_Z^T (2q + 2 passes)
+CORE = {"pass": 0, "rz": FLAG_CORE_FROM_RZ}
 F64, F32 = 0, 1
 COL_MAJOR, ROW_MAJOR = 0, 1
 PREC = {"f64": 0, "f32": 1, "bf16": 2, "bf16x3": 3}
@@ -195,12 +197,13 @@ class Context:
         piv = torch.zeros(ell, dtype=torch.int32, device=A.device)
         return U, T, V, piv
 
-    def decompose(self, A, k, p, q, seed, prec="f64", tri="auto", want_err=False, out=None):
-        """Returns (U, T, V, piv, info dict)."""
+    def decompose(self, A, k, p, q, seed, prec="f64", tri="auto", want_err=False, out=None, core="pass"):
+        """Returns (U, T, V, piv, info dict).  core: "pass" (D = Q1^T (A Q2)) or
+        "rz" (D = R_Z^T from the QR of the second sketch, one pass fewer)."""
         U, T, V, piv = out if out is not None else self.alloc_outputs(A, k, p)
         ell = k + p
         info = Info()
-        opts = Opts(PREC[prec], TRI[tri], 1 if want_err else 0, 0)
+        opts = Opts(PREC[prec], TRI[tri], 1 if want_err else 0, CORE[core])
         mu, mv = mat(U), mat(V)
         rc = lib.corutv_decompose(self.h, ctypes.byref(mat(A)), k, p, q, seed, ctypes.byref(opts),
                                   ctypes.byref(mu), T.data_ptr(), ell, ctypes.byref(mv), piv.data_ptr(),
@@ -210,11 +213,11 @@ class Context:
         d["tri"] = TRI_NAME.get(d["tri"], d["tri"])
         return U, T, V, piv, d
 
-    def decompose_rc(self, A, k, p, q, seed, prec="f64", tri="auto", want_err=False, out=None):
+    def decompose_rc(self, A, k, p, q, seed, prec="f64", tri="auto", want_err=False, out=None, core="pass"):
         """Like decompose but returns the status code instead of raising."""
         U, T, V, piv = out if out is not None else self.alloc_outputs(A, k, p)
         info = Info()
-        opts = Opts(PREC[prec], TRI[tri], 1 if want_err else 0, 0)
+        opts = Opts(PREC[prec], TRI[tri], 1 if want_err else 0, CORE[core])
         mu, mv = mat(U), mat(V)
         return lib.corutv_decompose(self.h, ctypes.byref(mat(A)), k, p, q, seed, ctypes.byref(opts),
                                     ctypes.byref(mu), T.data_ptr(), k + p, ctypes.byref(mv),
@@ -282,10 +285,10 @@ class Context:
         return L, S, info.as_dict()
 
     # -- serving --------------------------------------------------------------
-    def submit(self, A, k, p, q, seed, prec="f64", tri="auto", want_err=False, out=None):
+    def submit(self, A, k, p, q, seed, prec="f64", tri="auto", want_err=False, out=None, core="pass"):
         U, T, V, piv = out if out is not None else self.alloc_outputs(A, k, p)
         req = Request(mat(A), mat(U), mat(V), T.data_ptr(), k + p, piv.data_ptr(), k, p, q, 0, seed,
-                      Opts(PREC[prec], TRI[tri], 1 if want_err else 0, 0))
+                      Opts(PREC[prec], TRI[tri], 1 if want_err else 0, CORE[core]))
         t = ctypes.c_uint64(0)
         _check(lib.corutv_submit(self.h, ctypes.byref(req), ctypes.byref(t)), "submit")
         self._live[t.value] = (A, U, T, V, piv)

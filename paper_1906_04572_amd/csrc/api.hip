@@ -180,6 +180,7 @@ int validate(const DecArgs& d) {
   if (prec == P_F64 && d.A.dtype != CORUTV_F64) return CORUTV_E_INVAL;
   if (prec != P_F64 && d.A.dtype != CORUTV_F32) return CORUTV_E_INVAL;
   if (d.opts.tri < CORUTV_TRI_AUTO || d.opts.tri > CORUTV_TRI_LOWER) return CORUTV_E_INVAL;
+  if ((uint32_t)d.opts.flags & ~(uint32_t)CORUTV_FLAG_CORE_FROM_RZ) return CORUTV_E_INVAL;
   return CORUTV_OK;
 }
 
@@ -196,7 +197,7 @@ struct Enqueued {
 // CholeskyQR2 with FP64 Gram and Cholesky, Householder after a breakdown.
 // Outputs: q64 (FP64, may be scratch) and, for the F32 path, q32.
 hipError_t qr_from_partials(const Plan& pl, char* ws, const Partials& pp, int64_t rows, int64_t ld,
-                            double* q64, float* q32, int* st, hipStream_t s) {
+                            double* q64, float* q32, int* st, hipStream_t s, double* rfac = nullptr) {
   const int ell = pl.ell;
   double* x0 = (double*)(ws + pl.o_x0);
   double* x1 = (double*)(ws + pl.o_x1);
@@ -219,7 +220,8 @@ hipError_t qr_from_partials(const Plan& pl, char* ws, const Partials& pp, int64_
     return e;
   if ((e = launch_xty(x1, ld, x1, ld, rows, ell, xp, splits, st, s)) != hipSuccess) return e;
   if ((e = launch_reduce(xp, splits, l2, G, st, s)) != hipSuccess) return e;
-  if ((e = launch_chol(G, ell, R, Ri, st, st, cw, s)) != hipSuccess) return e;
+  double* R2 = R + l2;  // the second factor goes beside the first
+  if ((e = launch_chol(G, ell, R2, Ri, st, st, cw, s)) != hipSuccess) return e;
   MatOut o1, o2;
   o1.ptr = q64;
   o1.ld = ld;
@@ -230,7 +232,10 @@ hipError_t qr_from_partials(const Plan& pl, char* ws, const Partials& pp, int64_
   }
   if ((e = launch_rowmat(x1, ld, rows, ell, Ri, ell, nullptr, o1, 1, o2, 1, st, s)) != hipSuccess)
     return e;
-  return launch_householder_qr(x0, ld, rows, ell, x1, ld, q64, ld, q32, ld, nullptr, st, s);
+  // optional R factor: R2 R1 on the Cholesky route, the Householder R after a
+  // breakdown (each kernel checks the status word)
+  if (rfac && (e = launch_trprod(R2, R, ell, rfac, st, s)) != hipSuccess) return e;
+  return launch_householder_qr(x0, ld, rows, ell, x1, ld, q64, ld, q32, ld, rfac, st, s);
 }
 
 // Enqueue a whole decomposition on stream s using the workspace at ws.
@@ -313,17 +318,25 @@ int enqueue_decompose(corutv_ctx* ctx, const Plan& pl, char* ws, const DecArgs& 
     HIPOK(passA(wsrc));
     HIPOK(qr_from_partials(pl, ws, pp, mm, ldm, q1, f64 ? nullptr : (float*)qop, st + nqr++, s));
   }
-  // Z = P^T Q1; Q2 = qf(Z)
+  // Z = P^T Q1; Q2, R_Z = qf(Z)
+  const bool core_rz = (d.opts.flags & CORUTV_FLAG_CORE_FROM_RZ) != 0;
   HIPOK(passAt(qsrc));
-  HIPOK(qr_from_partials(pl, ws, pp, nn, ldn, q2, f64 ? nullptr : (float*)wop, st + nqr++, s));
-  // core D = Q1^T (P Q2)
-  HIPOK(passA(wsrc));
-  HIPOK(launch_sum_partials(pp, ell, ellp, x0, nullptr, ldm, s));
-  const int sp = xty_splits(mm, ell);
-  HIPOK(launch_xty(q1, ldm, x0, ldm, mm, ell, xp, sp, nullptr, s));
-  HIPOK(launch_reduce(xp, sp, (int64_t)ell * ell, core, nullptr, s));
-  // QRCP of D (upper) or of D^T (lower)
-  HIPOK(launch_qrcp(core, ell, lower_inner ? 1 : 0, ell, qt, rt, piv, qw, s));
+  HIPOK(qr_from_partials(pl, ws, pp, nn, ldn, q2, f64 ? nullptr : (float*)wop, st + nqr++, s,
+                         core_rz ? core : nullptr));
+  if (core_rz) {
+    // D = Q1^T P Q2 = R_Z^T (Q2 R_Z = Z = P^T Q1): no pass over A; the
+    // QRCP of D reads R_Z transposed, the QRCP of D^T reads R_Z as is
+    HIPOK(launch_qrcp(core, ell, lower_inner ? 0 : 1, ell, qt, rt, piv, qw, s));
+  } else {
+    // core D = Q1^T (P Q2)
+    HIPOK(passA(wsrc));
+    HIPOK(launch_sum_partials(pp, ell, ellp, x0, nullptr, ldm, s));
+    const int sp = xty_splits(mm, ell);
+    HIPOK(launch_xty(q1, ldm, x0, ldm, mm, ell, xp, sp, nullptr, s));
+    HIPOK(launch_reduce(xp, sp, (int64_t)ell * ell, core, nullptr, s));
+    // QRCP of D (upper) or of D^T (lower)
+    HIPOK(launch_qrcp(core, ell, lower_inner ? 1 : 0, ell, qt, rt, piv, qw, s));
+  }
   // lifts in the oriented problem: Uo (mm x ell), Vo (nn x ell), To
   //   upper: Uo = Q1 Qt, To = R, Vo = Q2[:, piv]
   //   lower: Uo = Q1[:, piv], To = R^T, Vo = Q2 Qt
@@ -350,7 +363,7 @@ int enqueue_decompose(corutv_ctx* ctx, const Plan& pl, char* ws, const DecArgs& 
   const bool t_lower_user = transposed ? !lower_inner : lower_inner;
   HIPOK(launch_copy_tri(tt, ell, transposed ? 1 : 0, t_lower_user ? 0 : 1, d.T, d.ldt, s));
   if (d.piv) HIPOK(hipMemcpyAsync(d.piv, piv, (size_t)ell * 4, hipMemcpyDeviceToDevice, s));
-  int passes = 2 * d.q + 3;
+  int passes = 2 * d.q + (core_rz ? 2 : 3);
   double* sum = (double*)(ws + pl.o_sum);
   if (want_err) {
     // residual of P ~ Uo To Vo^T on the big row-major view of A:
@@ -502,7 +515,7 @@ int corutv_decompose(corutv_ctx* ctx, const corutv_mat* A, int32_t k, int32_t p,
   if (hipEventCreate(&e0) != hipSuccess || hipEventCreate(&e1) != hipSuccess) return poison(ctx);
   hipEventRecord(e0, s);
   Enqueued eq;
-  const int npass = 2 * q + 3;
+  const int npass = 2 * q + ((opts->flags & CORUTV_FLAG_CORE_FROM_RZ) ? 2 : 3);
   if (ctx->timing) {
     while ((int)ctx->ev_pool.size() < 2 * npass) {
       hipEvent_t e;

@@ -91,6 +91,11 @@ size_t chol_work_bytes(int ell);
 hipError_t launch_chol(const double* G, int ell, double* R, double* Rinv, int* status,
                        const int* skip, double* work, hipStream_t st);
 
+// R = R2 R1 (upper triangular, column-major ld ell) when *status shows the
+// Cholesky route was taken; otherwise does nothing.
+hipError_t launch_trprod(const double* R2, const double* R1, int ell, double* R, const int* status,
+                         hipStream_t st);
+
 // Householder thin QR of X (rows x ell, column-major FP64) -> Q (diag R >= 0,
 // FP64 and optionally a float copy), R (nullable); runs only when
 // (*status & 3) == 1 (a Cholesky breakdown on finite data).  work: rows x ell.

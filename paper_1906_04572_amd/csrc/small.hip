@@ -816,7 +816,29 @@ __global__ void fill_int_kernel(int* p, int n, int v) {
   if (i < n) p[i] = v;
 }
 
+// R = R2 R1 for two upper triangular l x l factors (column-major, ld l):
+// the R factor of CholeskyQR2 (X = Q' R1, Q' = Q R2).  Runs only when the
+// QR took the Cholesky route ((*status & 3) == 0); after a breakdown the
+// Householder fallback writes R itself.
+__global__ void __launch_bounds__(256) trprod_kernel(const double* __restrict__ R2,
+                                                     const double* __restrict__ R1, int ell,
+                                                     double* __restrict__ R, const int* status) {
+  if ((*status & 3) != 0) return;
+  const int e = blockIdx.x * 256 + threadIdx.x;
+  if (e >= ell * ell) return;
+  const int i = e % ell, j = e / ell;
+  double v = 0.0;
+  for (int t = i; t <= j; ++t) v = fma(R2[(int64_t)t * ell + i], R1[(int64_t)j * ell + t], v);
+  R[e] = i <= j ? v : 0.0;
+}
+
 }  // namespace
+
+hipError_t launch_trprod(const double* R2, const double* R1, int ell, double* R, const int* status,
+                         hipStream_t st) {
+  trprod_kernel<<<dim3((ell * ell + 255) / 256), dim3(256), 0, st>>>(R2, R1, ell, R, status);
+  return hipGetLastError();
+}
 
 // ---------------------------------------------------------------------------
 hipError_t launch_sum_partials(const Partials& p, int ell, int ncols, double* out64, float* out32,

@@ -242,3 +242,60 @@ def test_full_size_precision_forms_50000x30000(ctx):
         assert torch.max(torch.abs(Vd.T @ Vd - eye)).item() <= 1e-5
         assert torch.all(torch.tril(T, -1) == 0).item()
     big.close()
+
+
+@pytest.mark.parametrize("m,n,k,p,q,tri,layout,prec", [
+    (1200, 900, 20, 10, 1, "upper", "row", "f64"), (900, 1200, 20, 10, 2, "auto", "col", "f64"),
+    (1037, 613, 17, 6, 1, "lower", "col", "f64"), (1800, 1500, 120, 20, 1, "auto", "row", "f64"),
+    (3000, 2000, 50, 10, 1, "auto", "row", "f32"), (2000, 3000, 60, 10, 0, "lower", "col", "f32"),
+])
+def test_core_from_rz_against_oracle(ctx, m, n, k, p, q, tri, layout, prec):
+    """Core D = R_Z^T (2q + 2 passes) against the oracle's core="rz": F64 to
+    the 1e-10 bars, F32 |e_gpu - e_oracle| <= 1e-5."""
+    _say("core rz", m, n, k, p, q, tri, layout, prec)
+    dt = np.float64 if prec == "f64" else np.float32
+    A = decaying(m, n, min(m, n) // 2, 1e-4, seed=m + 2 * n, kind="exp", tau=max(k / 2, 3)).astype(dt)
+    A64 = A.astype(np.float64)
+    U, T, V, piv, info = ctx.decompose(_dev(A, layout), k, p, q, 77, prec=prec, tri=tri, want_err=True,
+                                       core="rz")
+    got = (U.cpu().numpy().astype(np.float64), T.cpu().numpy(), V.cpu().numpy().astype(np.float64),
+           piv.cpu().numpy(), info)
+    assert info["passes"] == 2 * q + 2 + 1  # + the residual pass
+    ref = corutv(A64, k, p, q, seed=77, tri=tri, core="rz")
+    if prec == "f64":
+        _check_f64(A64, k, p, q, 77, tri, got, ref)
+    else:
+        e_ref = rel_err(A64, ref["U"], ref["T"], ref["V"])
+        assert abs(info["rel_err"] - e_ref) <= 1e-5
+        assert abs(rel_err(A64, got[0], got[1], got[2]) - e_ref) <= 1e-5
+
+
+def test_core_from_rz_after_cholesky_breakdown(ctx):
+    """Exactly low-rank A: the QR of Z falls back to Householder, whose R
+    then gives the core; the factorization is still exact."""
+    _say("core rz, fallback")
+    A = noisy_low_rank(1500, 1100, 12, 0.0, seed=3)
+    U, T, V, piv, info = _run_core_rz(ctx, A)
+    assert info["qr_fallbacks"] >= 1
+    assert info["rel_err"] <= 1e-12
+    assert rel_err(A, U, T, V) <= 1e-12
+
+
+def _run_core_rz(ctx, A):
+    U, T, V, piv, info = ctx.decompose(_dev(A, "row"), 12, 8, 1, 9, prec="f64", want_err=True, core="rz")
+    return U.cpu().numpy(), T.cpu().numpy(), V.cpu().numpy(), piv.cpu().numpy(), info
+
+
+def test_unknown_flag_bits_are_rejected(ctx):
+    import ctypes
+
+    import paper_1906_04572_amd as cu
+
+    A = torch.from_numpy(decaying(300, 200, 20, 1e-3, seed=1)).cuda()
+    U, T, V, piv = ctx.alloc_outputs(A, 10, 5)
+    info = cu.Info()
+    opts = cu.Opts(cu.PREC["f64"], 0, 0, 2)
+    rc = cu.lib.corutv_decompose(ctx.h, ctypes.byref(cu.mat(A)), 10, 5, 1, 3, ctypes.byref(opts),
+                                 ctypes.byref(cu.mat(U)), T.data_ptr(), 15, ctypes.byref(cu.mat(V)),
+                                 piv.data_ptr(), ctypes.byref(info))
+    assert rc == cu.E_INVAL

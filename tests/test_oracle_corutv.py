@@ -195,3 +195,21 @@ def test_planted_mistakes_are_caught():
     Tbad = r["T"].copy()
     Tbad[0] *= -1
     assert rel_err(A, r["U"], Tbad, r["V"]) > 1e-3
+
+
+@pytest.mark.parametrize("m,n,q,tri", [(300, 200, 1, "upper"), (300, 200, 0, "lower"), (150, 260, 2, "auto")])
+def test_core_from_rz_gives_the_same_factorization(m, n, q, tri):
+    """core="rz" (D = R_Z^T, one product with A fewer) and core="pass" give the
+    same rank-l approximation and the same leading pivots: the two cores
+    differ only by rounding (Sec. 3.1 eqs. 5-7)."""
+    A = decaying(m, n, 80, 1e-6, seed=m + q, kind="exp", tau=6.0)
+    a = corutv(A, 15, 5, q, seed=7, tri=tri)
+    b = corutv(A, 15, 5, q, seed=7, tri=tri, core="rz")
+    nA = np.linalg.norm(A)
+    assert np.linalg.norm(a["D"] - b["D"]) <= 1e-13 * nA
+    Aa = a["U"] @ a["T"] @ a["V"].T
+    Ab = b["U"] @ b["T"] @ b["V"].T
+    assert np.linalg.norm(Aa - Ab) <= 1e-12 * nA
+    np.testing.assert_array_equal(a["piv"][:10], b["piv"][:10])
+    with pytest.raises(ValueError):
+        corutv(A, 15, 5, q, seed=7, mode="literal", core="rz")
