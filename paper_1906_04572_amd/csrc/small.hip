@@ -426,47 +426,51 @@ __device__ __forceinline__ double readlane_f64(double v, int l) {
   return __longlong_as_double(((long long)hi << 32) | (unsigned)lo);
 }
 
-// One wave: D (16 x 16, symmetric, row-major at src) = U^T U.  Lane r (mod
-// 16) holds row r of [D | I] in registers.  Step s broadcasts row s with
-// v_readlane (a uniform lane index, no memory round trip) and eliminates it
-// from the rows below with multipliers D[r][s]/d_s (the whole trailing square
-// is updated, so the multipliers can be read from each lane's own column s);
-// at the end row r is scaled by 1/sqrt(d_r), giving [U | U^{-T}].  Returns
-// false on breakdown (the same on every lane: the pivot is a broadcast).
+// One wave: D (16 x 16, symmetric, row-major at src) = U^T U.  Lane c < 32
+// holds column c of [D | I] in registers (x[r] = row r).  Step s needs the
+// pivot d_s and the multipliers D[r][s]/d_s of the rows below: column s,
+// broadcast from lane s with v_readlane (a uniform lane index); the pivot
+// row is each lane's own x[s], so rows r > s update as
+// x[r] -= (D[r][s]/d_s) x[s].  The row scaling by 1/sqrt(d_r) that turns
+// [L D' | L^-1] into [U | U^{-T}] is done once at the end.  Returns false on
+// breakdown (the same on every lane: the pivot is a broadcast).
 __device__ __forceinline__ bool chol_diag16(const double* src, int base, int ell, double thr,
                                             double* u_out, double* e_out, double* x_out, int lane) {
-  const int r = lane & 15;
-  double x[32];
+  const int c = lane & 31;
+  double x[16];
 #pragma unroll
-  for (int c = 0; c < 16; ++c) {
-    x[c] = src[r * 16 + c];
-    x[16 + c] = r == c ? 1.0 : 0.0;
-  }
-  double myiv = 1.0;
+  for (int r = 0; r < 16; ++r) x[r] = c < 16 ? src[r * 16 + c] : (r == c - 16 ? 1.0 : 0.0);
+  double dd[16];
 #pragma unroll
   for (int s = 0; s < 16; ++s) {
     const double d = readlane_f64(x[s], s);
     if (base + s < ell && (!(d > thr) || !isfinite(d))) return false;
-    // 1/sqrt(d): hardware estimate refined by two Newton steps
-    double iv = __builtin_amdgcn_rsq(d);
-    iv = iv * (1.5 - 0.5 * d * iv * iv);
-    iv = iv * (1.5 - 0.5 * d * iv * iv);
-    if (r == s) myiv = iv;
-    const double m = x[s] * (iv * iv);
-    const bool below = r > s;
+    dd[s] = d;
+    // 1/d: hardware estimate refined by two Newton steps
+    double rd = __builtin_amdgcn_rcp(d);
+    rd = fma(rd, fma(-d, rd, 1.0), rd);
+    rd = fma(rd, fma(-d, rd, 1.0), rd);
+    const double piv_row = x[s];
 #pragma unroll
-    for (int c = s + 1; c < 17 + s; ++c) {  // D columns s+1..15, Z columns 0..s
-      const double rc = readlane_f64(x[c], s);
-      if (below) x[c] -= m * rc;
+    for (int r = s + 1; r < 16; ++r) {
+      const double m = readlane_f64(x[r], s) * rd;  // D[r][s] / d_s
+      x[r] -= m * piv_row;
     }
   }
-  if (lane < 16) {
+  if (lane < 32) {
 #pragma unroll
-    for (int c = 0; c < 16; ++c) {
-      u_out[r * 16 + c] = c >= r ? x[c] * myiv : 0.0;
-      const double z = x[16 + c] * myiv;
-      e_out[r * 16 + c] = z;
-      x_out[c * 16 + r] = z;
+    for (int r = 0; r < 16; ++r) {
+      // 1/sqrt(d_r): hardware estimate refined by two Newton steps
+      double iv = __builtin_amdgcn_rsq(dd[r]);
+      iv = iv * (1.5 - 0.5 * dd[r] * iv * iv);
+      iv = iv * (1.5 - 0.5 * dd[r] * iv * iv);
+      const double v = x[r] * iv;
+      if (c < 16) {
+        u_out[r * 16 + c] = c >= r ? v : 0.0;
+      } else {
+        e_out[r * 16 + (c - 16)] = v;
+        x_out[(c - 16) * 16 + r] = v;
+      }
     }
   }
   return true;
@@ -509,18 +513,16 @@ __global__ void __launch_bounds__(1024) chol_kernel(const double* __restrict__ G
       red[4 + wave] = bad;
     }
   }
-  // tiles: W from G (identity in the padding), E zero
-  for (int e = tid; e < nw * 256; e += blockDim.x) {
-    const int t = e >> 8, r = (e >> 4) & 15, c = e & 15;
-    int I = 0, rem = t;
-    while (rem >= nb - I) {
-      rem -= nb - I;
-      ++I;
-    }
-    const int gi = 16 * I + r, gj = 16 * (I + rem) + c;
-    wt[e] = (gi < ell && gj < ell) ? G[(int64_t)gj * ell + gi] : (gi == gj ? 1.0 : 0.0);
-    et[e] = 0.0;
+  // tiles: W from G (identity in the padding); consecutive threads read
+  // consecutive entries of a column of G
+  for (int e = tid; e < nb * nb * 256; e += blockDim.x) {
+    const int tt = e >> 8, tI = tt / nb, tK = tt - tI * nb;
+    if (tI > tK) continue;
+    const int cc = e & 15, rr = (e >> 4) & 15;
+    const int gi = 16 * tI + cc, gj = 16 * tK + rr;  // tile element (cc, rr) = G(gi, gj)
+    W(tI, tK)[cc * 16 + rr] = (gi < ell && gj < ell) ? G[(int64_t)gj * ell + gi] : (gi == gj ? 1.0 : 0.0);
   }
+  for (int e = tid; e < nw * 256; e += blockDim.x) et[e] = 0.0;
   if (tid == 0) {
     const double dmax = fmax(fmax(red[0], red[1]), fmax(red[2], red[3]));
     const double bad = fmax(fmax(red[4], red[5]), fmax(red[6], red[7]));
@@ -593,15 +595,23 @@ __global__ void __launch_bounds__(1024) chol_kernel(const double* __restrict__ G
       return;
     }
   }
-  // R (upper, zeros below) and R^{-1} = Z^T, column-major
-  for (int e = tid; e < ell * ell; e += blockDim.x) {
-    const int r = e % ell, c = e / ell;
-    if (r <= c) {
-      R[e] = W(r >> 4, c >> 4)[(r & 15) * 16 + (c & 15)];
-      Rinv[e] = E(c >> 4, r >> 4)[(c & 15) * 16 + (r & 15)];
-    } else {
-      R[e] = 0.0;
-      Rinv[e] = 0.0;
+  // R (upper, zeros below) and R^{-1} = Z^T, column-major; one 16 x 16
+  // block per wave at a time, 16 lanes writing 16 consecutive rows
+  for (int tt = wave; tt < nb * nb; tt += nwaves) {
+    const int I = tt % nb, K = tt / nb;  // row block, column block
+#pragma unroll
+    for (int u = 0; u < 4; ++u) {
+      const int rr = lane & 15, cc = (lane >> 4) + 4 * u;
+      const int r = 16 * I + rr, c = 16 * K + cc;
+      if (r >= ell || c >= ell) continue;
+      double vr = 0.0, vi = 0.0;
+      if (I <= K) {
+        vr = W(I, K)[rr * 16 + cc];
+        if (r <= c) vi = E(K, I)[cc * 16 + rr];
+        if (r > c) vr = 0.0;
+      }
+      R[(int64_t)c * ell + r] = vr;
+      Rinv[(int64_t)c * ell + r] = vi;
     }
   }
 }
