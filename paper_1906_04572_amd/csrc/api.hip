@@ -37,7 +37,7 @@ struct Plan {
   // byte offsets
   size_t o_wop = 0, o_qop = 0, o_part = 0, o_x0 = 0, o_x1 = 0, o_q1 = 0, o_q2 = 0, o_xp = 0,
          o_g = 0, o_r = 0, o_rinv = 0, o_core = 0, o_qt = 0, o_rt = 0, o_qw = 0, o_tt = 0,
-         o_piv = 0, o_st = 0, o_res = 0, o_sum = 0, o_cw = 0;
+         o_piv = 0, o_st = 0, o_res = 0, o_sum = 0, o_cw = 0, o_sbf = 0;
   size_t total = 0;
 };
 
@@ -92,6 +92,7 @@ bool make_plan(int64_t m, int64_t n, int k, int p, int q, int prec, Plan* pl) {
   pl->o_res = take((size_t)residual_blocks(pl->mm) * 2 * 8);
   pl->o_sum = take(2 * 8);
   pl->o_cw = take(chol_work_bytes((int)ell));
+  if (prec == P_BF16 || prec == P_BF16X3) pl->o_sbf = take(sketch_bf16_bytes(pl->ellp, pl->ldx));
   pl->total = off;
   return true;
 }
@@ -295,14 +296,14 @@ int enqueue_decompose(corutv_ctx* ctx, const Plan& pl, char* ws, const DecArgs& 
   auto passA = [&](const void* opnd) {  // P X, X nn x ell -> mm x ell
     mark();
     hipError_t e = launch_sketch(prec, tA, d.A.ptr, d.A.ld, Rb, Cb, opnd, ldn, ellp, part,
-                                 pl.part_elems, &pp, ctx->num_cu, s);
+                                 pl.part_elems, &pp, ctx->num_cu, s, ws + pl.o_sbf);
     mark();
     return e;
   };
   auto passAt = [&](const void* opnd) {  // P^T Y, Y mm x ell -> nn x ell
     mark();
     hipError_t e = launch_sketch(prec, tAt, d.A.ptr, d.A.ld, Rb, Cb, opnd, ldm, ellp, part,
-                                 pl.part_elems, &pp, ctx->num_cu, s);
+                                 pl.part_elems, &pp, ctx->num_cu, s, ws + pl.o_sbf);
     mark();
     return e;
   };
@@ -598,16 +599,20 @@ int corutv_sketch(corutv_ctx* ctx, const corutv_mat* A, int32_t trans, int32_t p
   const int64_t Rb = a_col ? n : m, Cb = a_col ? m : n;
   const int t = (a_col ? 1 : 0) ^ trans;
   const int64_t cap = partials_capacity(nout, klen, ellp, prec);
-  const size_t need = align256((size_t)ellp * ldk * es) + align256((size_t)cap * es);
+  const bool bf = prec == P_BF16 || prec == P_BF16X3;
+  const size_t need = align256((size_t)ellp * ldk * es) + align256((size_t)cap * es) +
+                      (bf ? align256(sketch_bf16_bytes(ellp, ldk)) : 0);
   if (need > ctx->ws_bytes) return CORUTV_E_NOMEM;
   std::lock_guard<std::mutex> lk(ctx->run_mu);
   hipStream_t s = ctx->streams[0];
   char* xs = ctx->ws;
   char* part = ctx->ws + align256((size_t)ellp * ldk * es);
+  char* sbf = part + align256((size_t)cap * es);
   HIPOK(hipMemsetAsync(xs, 0, (size_t)ellp * ldk * es, s));
   HIPOK(hipMemcpy2DAsync(xs, ldk * es, X, ldx * es, klen * es, ell, hipMemcpyDeviceToDevice, s));
   Partials pp;
-  HIPOK(launch_sketch(prec, t, A->ptr, A->ld, Rb, Cb, xs, ldk, ellp, part, cap, &pp, ctx->num_cu, s));
+  HIPOK(launch_sketch(prec, t, A->ptr, A->ld, Rb, Cb, xs, ldk, ellp, part, cap, &pp, ctx->num_cu, s,
+                      bf ? sbf : nullptr));
   HIPOK(launch_sum_partials(pp, ell, ell, prec == P_F64 ? (double*)Y : nullptr,
                             prec == P_F64 ? nullptr : (float*)Y, ldy, s));
   if (hipStreamSynchronize(s) != hipSuccess) return poison(ctx);

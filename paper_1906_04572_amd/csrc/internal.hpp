@@ -45,9 +45,12 @@ hipError_t launch_omega(int64_t n, int ell, int ellp, uint64_t seed, uint32_t su
 // with Q (R x l) stored as S[c*lds + i].  Writes partial tiles into `part`
 // (whose geometry is filled in here).
 // part_elems: capacity of part_buf in elements; the grid shrinks to fit.
+// sbf: for the bf16 forms, scratch of sketch_bf16_bytes(ellp, lds) bytes that
+// receives the bf16 hi/lo split of S (unused otherwise, may be null).
 hipError_t launch_sketch(int prec, int trans, const void* A, int64_t lda, int64_t R, int64_t C,
                          const void* S, int64_t lds, int ellp, void* part_buf, int64_t part_elems,
-                         Partials* part, int num_cu, hipStream_t st);
+                         Partials* part, int num_cu, hipStream_t st, void* sbf);
+inline size_t sketch_bf16_bytes(int ellp, int64_t lds) { return 2 * (size_t)ellp * lds * 2; }
 // Capacity (elements) that covers every grid launch_sketch may pick on a
 // 256-CU device.
 int64_t partials_capacity(int64_t n_out, int64_t k_len, int ellp, int prec);

@@ -60,6 +60,7 @@ struct SketchArgs {
   int64_t N;  // output length (rows of Y / Z)
   int64_t K;  // reduction length
   const void* S;
+  const void* S2;  // bf16 forms: the lo parts of the pre-split skinny operand
   int64_t lds;
   void* P;
   int tiles, nk, nkx, gx, maxslot;
@@ -288,15 +289,19 @@ __device__ __forceinline__ void split8(const float* x, bf8& hi, bf8& lo, bool wa
   }
 }
 
+// The skinny operand arrives pre-split into bf16 hi (S) and lo (S2) parts
+// (split_bf16_kernel, same rounding), so it is staged into LDS as bf16 and
+// fed to the matrix cores without per-wave conversion.
 template <int MB, bool TRANS, int NB, bool X3>
 __global__ void __launch_bounds__(256) sketch_bf16_kernel(SketchArgs a) {
   constexpr int KC = 32;                 // k values per LDS stage = one MFMA block
   constexpr int ELLP = MB * 16;
-  constexpr int LDK = KC + 4;
+  constexpr int LDKB = KC + 8;           // LDS row stride in bf16 (16 bytes of pad)
   constexpr int TW = 64 * NB;
-  constexpr int VPR = KC / 4;
+  constexpr int VPR = KC / 8;            // 16-byte vectors per skinny row per stage
   constexpr int SPASS = (ELLP * VPR + 255) / 256;
-  __shared__ __attribute__((aligned(16))) float lds_s[2][ELLP * LDK];
+  constexpr int NPART = X3 ? 2 : 1;
+  __shared__ __attribute__((aligned(16))) __bf16 lds_s[NPART][2][ELLP * LDKB];
 
   const int tid = threadIdx.x;
   const int lane = tid & 63, wave = tid >> 6;
@@ -304,7 +309,7 @@ __global__ void __launch_bounds__(256) sketch_bf16_kernel(SketchArgs a) {
   const int x = blockIdx.x & 7;
   const int jw = blockIdx.x >> 3;
   const float* __restrict__ A = (const float*)a.A;
-  const float* __restrict__ S = (const float*)a.S;
+  const __bf16* __restrict__ Sp[2] = {(const __bf16*)a.S, (const __bf16*)a.S2};
   float* __restrict__ P = (float*)a.P;
   const int64_t U = (int64_t)a.tiles * a.nkx;
   int64_t u = (int64_t)jw * U / a.gx;
@@ -326,25 +331,29 @@ __global__ void __launch_bounds__(256) sketch_bf16_kernel(SketchArgs a) {
       for (int nb = 0; nb < NB; ++nb) acc[mb][nb] = f4{0, 0, 0, 0};
 
     if (gk0 < gk1) {
-      f4 sreg[SPASS];
+      f4 sreg[NPART][SPASS];  // raw 16-byte vectors of 8 bf16
       float bcur[NB * 8], bnext[NB * 8];  // [nb][8 k values]
       // unconditional loads from clamped addresses; validity bits applied
       // when the prefetched chunk becomes current (see the FP32/FP64 kernel)
       auto load_skinny = [&](int kb) {
 #pragma unroll
-        for (int p = 0; p < SPASS; ++p) {
-          const int v = tid + 256 * p;
-          const int c = min(v / VPR, ELLP - 1), kv = v % VPR;
-          sreg[p] = *(const f4*)(S + (int64_t)c * a.lds + (int64_t)kb * KC + kv * 4);
-        }
+        for (int h = 0; h < NPART; ++h)
+#pragma unroll
+          for (int p = 0; p < SPASS; ++p) {
+            const int v = tid + 256 * p;
+            const int c = min(v / VPR, ELLP - 1), kv = v % VPR;
+            sreg[h][p] = *(const f4*)(Sp[h] + (int64_t)c * a.lds + (int64_t)kb * KC + kv * 8);
+          }
       };
       auto store_skinny = [&](int buf) {
 #pragma unroll
-        for (int p = 0; p < SPASS; ++p) {
-          const int v = tid + 256 * p;
-          const int c = v / VPR, kv = v % VPR;
-          if (c < ELLP) *(f4*)&lds_s[buf][c * LDK + kv * 4] = sreg[p];
-        }
+        for (int h = 0; h < NPART; ++h)
+#pragma unroll
+          for (int p = 0; p < SPASS; ++p) {
+            const int v = tid + 256 * p;
+            const int c = v / VPR, kv = v % VPR;
+            if (c < ELLP) *(f4*)&lds_s[h][buf][c * LDKB + kv * 8] = sreg[h][p];
+          }
       };
       auto load_b = [&](int kb, float* b, uint32_t& mask) {
         mask = 0;
@@ -409,15 +418,12 @@ __global__ void __launch_bounds__(256) sketch_bf16_kernel(SketchArgs a) {
         bf8 bh[NB], bl[NB];
 #pragma unroll
         for (int nb = 0; nb < NB; ++nb) split8(bcur + nb * 8, bh[nb], bl[nb], X3);
-        const float* ls = &lds_s[buf][0];
 #pragma unroll
         for (int mb = 0; mb < MB; ++mb) {
-          const float* src = ls + (mb * 16 + qd) * LDK + 8 * g;
-          const f4 v0 = *(const f4*)src;
-          const f4 v1 = *(const f4*)(src + 4);
-          const float sv[8] = {v0[0], v0[1], v0[2], v0[3], v1[0], v1[1], v1[2], v1[3]};
-          bf8 sh, sl;
-          split8(sv, sh, sl, X3);
+          const int off = (mb * 16 + qd) * LDKB + 8 * g;
+          const bf8 sh = *(const bf8*)&lds_s[0][buf][off];
+          bf8 sl;
+          if constexpr (X3) sl = *(const bf8*)&lds_s[NPART - 1][buf][off];
 #pragma unroll
           for (int nb = 0; nb < NB; ++nb) {
             if constexpr (X3) {
@@ -447,6 +453,18 @@ __global__ void __launch_bounds__(256) sketch_bf16_kernel(SketchArgs a) {
         }
       }
     u += kb1 - kb0;
+  }
+}
+
+// bf16 hi/lo split of the skinny operand (same rounding as split8)
+__global__ void split_bf16_kernel(const float* __restrict__ S, int64_t n, __bf16* __restrict__ H,
+                                  __bf16* __restrict__ L, int x3) {
+  for (int64_t e = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; e < n;
+       e += (int64_t)gridDim.x * blockDim.x) {
+    const float v = S[e];
+    const __bf16 h = (__bf16)v;
+    H[e] = h;
+    if (x3) L[e] = (__bf16)(v - (float)h);
   }
 }
 
@@ -575,7 +593,7 @@ int64_t partials_capacity(int64_t n_out, int64_t k_len, int ellp, int prec) {
 
 hipError_t launch_sketch(int prec, int trans, const void* A, int64_t lda, int64_t R, int64_t C,
                          const void* S, int64_t lds, int ellp, void* part_buf, int64_t part_elems,
-                         Partials* part, int num_cu, hipStream_t st) {
+                         Partials* part, int num_cu, hipStream_t st, void* sbf) {
   const bool f64 = prec == P_F64;
   const int mb = ellp / 16;
   void* fn = nullptr;
@@ -606,7 +624,20 @@ hipError_t launch_sketch(int prec, int trans, const void* A, int64_t lda, int64_
   a.N = N;
   a.K = K;
   a.S = S;
+  a.S2 = nullptr;
   a.lds = lds;
+  if (prec == P_BF16 || prec == P_BF16X3) {
+    // split the float skinny operand (ellp rows of stride lds) into bf16
+    if (!sbf) return hipErrorInvalidValue;
+    const int64_t ne = (int64_t)ellp * lds;
+    __bf16* H = (__bf16*)sbf;
+    __bf16* L = H + ne;
+    split_bf16_kernel<<<dim3(1024), dim3(256), 0, st>>>((const float*)S, ne, H, L, prec == P_BF16X3);
+    hipError_t e = hipGetLastError();
+    if (e != hipSuccess) return e;
+    a.S = H;
+    a.S2 = L;
+  }
   a.P = part_buf;
   a.tiles = part->tiles;
   a.nk = (int)((K + (128 / elem) - 1) / (128 / elem));
