@@ -56,7 +56,12 @@ enum corutv_layout { CORUTV_COL_MAJOR = 0, CORUTV_ROW_MAJOR = 1 };
  * in the tile loader, FP32 accumulation.  BF16X3: x = hi + lo split into two
  * bfloat16 parts, lo*hi + hi*lo + hi*hi accumulated in FP32.  In every form
  * the Gram matrices, Cholesky factors, the l x l core and its QRCP are FP64.
- * F64 needs an F64 A; F32/BF16/BF16X3 need an F32 A. */
+ * F64 needs an F64 A; F32/BF16/BF16X3 need an F32 A.
+ * The thin QRs of the sketches are CholeskyQR2 (two CholeskyQR steps).  In
+ * the F32/BF16/BF16X3 forms, whose bases are stored in FP32, a QR stops after
+ * the first step when u l (||R1||_F ||R1^-1||_F)^2 <= 2^-24 (u = 2^-53): the
+ * first step's loss of orthogonality, of order u cond(sketch)^2, is then
+ * below FP32 rounding. */
 enum corutv_prec { CORUTV_PREC_F64 = 0, CORUTV_PREC_F32 = 1, CORUTV_PREC_BF16 = 2, CORUTV_PREC_BF16X3 = 3 };
 /* Triangle of T.  AUTO follows Sec. 3: upper for m >= n, and for m < n the
  * method runs on A^T and returns a lower T.  UPPER/LOWER force the triangle
@@ -98,7 +103,8 @@ typedef struct corutv_info {
   int32_t tri;           /* CORUTV_TRI_UPPER or CORUTV_TRI_LOWER returned       */
   int32_t qr_fallbacks;  /* tall-skinny QRs that fell back to Householder       */
   int32_t passes;        /* passes over A: 2q + 3 (+1 with want_err)            */
-  int32_t reserved;
+  int32_t qr_one_step;   /* tall-skinny QRs that stopped after one CholeskyQR   */
+                         /* step (F32/BF16/BF16X3 only; see corutv_prec)       */
 } corutv_info;
 
 typedef struct corutv_config {

@@ -44,10 +44,10 @@ class Info(ctypes.Structure):
     _fields_ = [("rel_err", ctypes.c_double), ("a_fro", ctypes.c_double), ("gpu_ms", ctypes.c_double),
                 ("ell", ctypes.c_int32), ("transposed", ctypes.c_int32), ("tri", ctypes.c_int32),
                 ("qr_fallbacks", ctypes.c_int32), ("passes", ctypes.c_int32),
-                ("reserved", ctypes.c_int32)]
+                ("qr_one_step", ctypes.c_int32)]
 
     def as_dict(self):
-        return {f: getattr(self, f) for f, _ in self._fields_ if f != "reserved"}
+        return {f: getattr(self, f) for f, _ in self._fields_}
 
 
 class RpcaInfo(ctypes.Structure):

@@ -26,6 +26,10 @@ using namespace corutv;
 namespace {
 
 constexpr int kMaxQr = 64;  // status words (one per tall-skinny QR)
+// Reduced-precision forms store every basis in FP32, so a CholeskyQR step
+// whose orthogonality loss bound u l (||R||_F ||R^-1||_F)^2 is below the FP32
+// unit roundoff needs no second step.
+constexpr double kOneStepThr = 5.9604644775390625e-08;  // 2^-24
 
 struct Plan {
   int64_t mm = 0, nn = 0;  // oriented problem: mm >= nn rows of Q1 / Q2
@@ -197,8 +201,13 @@ struct Enqueued {
 // Thin QR of the sketch held in the stream-K partials `pp` (rows x ell):
 // CholeskyQR2 with FP64 Gram and Cholesky, Householder after a breakdown.
 // Outputs: q64 (FP64, may be scratch) and, for the F32 path, q32.
+// Thin QR of the sketch held as pass partials: CholeskyQR2 with FP64 Gram
+// matrices.  one_step: the first Cholesky may decide (status 4) that a
+// second step is not needed; then Q = X R1^-1 goes straight to the outputs
+// and the kernels of the second step return at once.
 hipError_t qr_from_partials(const Plan& pl, char* ws, const Partials& pp, int64_t rows, int64_t ld,
-                            double* q64, float* q32, int* st, hipStream_t s, double* rfac = nullptr) {
+                            double* q64, float* q32, int* st, hipStream_t s, double* rfac = nullptr,
+                            bool one_step = false) {
   const int ell = pl.ell;
   double* x0 = (double*)(ws + pl.o_x0);
   double* x1 = (double*)(ws + pl.o_x1);
@@ -213,16 +222,13 @@ hipError_t qr_from_partials(const Plan& pl, char* ws, const Partials& pp, int64_
   if ((e = launch_sum_partials(pp, ell, pl.ellp, x0, nullptr, ld, s)) != hipSuccess) return e;
   if ((e = launch_xty(x0, ld, x0, ld, rows, ell, xp, splits, nullptr, s)) != hipSuccess) return e;
   if ((e = launch_reduce(xp, splits, l2, G, nullptr, s)) != hipSuccess) return e;
-  if ((e = launch_chol(G, ell, R, Ri, st, nullptr, cw, s)) != hipSuccess) return e;
+  if ((e = launch_chol(G, ell, R, Ri, st, nullptr, cw, s, one_step ? kOneStepThr : 0.0)) != hipSuccess)
+    return e;
   MatOut ox1;
   ox1.ptr = x1;
   ox1.ld = ld;
-  if ((e = launch_rowmat(x0, ld, rows, ell, Ri, ell, nullptr, ox1, 1, MatOut(), 0, st, s)) != hipSuccess)
+  if ((e = launch_rowmat(x0, ld, rows, ell, Ri, ell, nullptr, ox1, 1, MatOut(), 0, st, s, true)) != hipSuccess)
     return e;
-  if ((e = launch_xty(x1, ld, x1, ld, rows, ell, xp, splits, st, s)) != hipSuccess) return e;
-  if ((e = launch_reduce(xp, splits, l2, G, st, s)) != hipSuccess) return e;
-  double* R2 = R + l2;  // the second factor goes beside the first
-  if ((e = launch_chol(G, ell, R2, Ri, st, st, cw, s)) != hipSuccess) return e;
   MatOut o1, o2;
   o1.ptr = q64;
   o1.ld = ld;
@@ -231,7 +237,14 @@ hipError_t qr_from_partials(const Plan& pl, char* ws, const Partials& pp, int64_
     o2.ld = ld;
     o2.dtype = CORUTV_F32;
   }
-  if ((e = launch_rowmat(x1, ld, rows, ell, Ri, ell, nullptr, o1, 1, o2, 1, st, s)) != hipSuccess)
+  if (one_step &&
+      (e = launch_rowmat(x0, ld, rows, ell, Ri, ell, nullptr, o1, 1, o2, 1, st, s, true, 4)) != hipSuccess)
+    return e;
+  if ((e = launch_xty(x1, ld, x1, ld, rows, ell, xp, splits, st, s)) != hipSuccess) return e;
+  if ((e = launch_reduce(xp, splits, l2, G, st, s)) != hipSuccess) return e;
+  double* R2 = R + l2;  // the second factor goes beside the first
+  if ((e = launch_chol(G, ell, R2, Ri, st, st, cw, s)) != hipSuccess) return e;
+  if ((e = launch_rowmat(x1, ld, rows, ell, Ri, ell, nullptr, o1, 1, o2, 1, st, s, true)) != hipSuccess)
     return e;
   // optional R factor: R2 R1 on the Cholesky route, the Householder R after a
   // breakdown (each kernel checks the status word)
@@ -311,19 +324,19 @@ int enqueue_decompose(corutv_ctx* ctx, const Plan& pl, char* ws, const DecArgs& 
   HIPOK(launch_omega(nn, ell, ellp, d.seed, d.sub, f64 ? (double*)wop : nullptr,
                      f64 ? nullptr : (float*)wop, ldn, s));
   HIPOK(passA(wop));
-  HIPOK(qr_from_partials(pl, ws, pp, mm, ldm, q1, f64 ? nullptr : (float*)qop, st + nqr++, s));
+  HIPOK(qr_from_partials(pl, ws, pp, mm, ldm, q1, f64 ? nullptr : (float*)qop, st + nqr++, s, nullptr, !f64));
   for (int it = 0; it < d.q; ++it) {
     // W = qf(P^T Q1); Q1 = qf(P W)
     HIPOK(passAt(qsrc));
-    HIPOK(qr_from_partials(pl, ws, pp, nn, ldn, q2, f64 ? nullptr : (float*)wop, st + nqr++, s));
+    HIPOK(qr_from_partials(pl, ws, pp, nn, ldn, q2, f64 ? nullptr : (float*)wop, st + nqr++, s, nullptr, !f64));
     HIPOK(passA(wsrc));
-    HIPOK(qr_from_partials(pl, ws, pp, mm, ldm, q1, f64 ? nullptr : (float*)qop, st + nqr++, s));
+    HIPOK(qr_from_partials(pl, ws, pp, mm, ldm, q1, f64 ? nullptr : (float*)qop, st + nqr++, s, nullptr, !f64));
   }
   // Z = P^T Q1; Q2, R_Z = qf(Z)
   const bool core_rz = (d.opts.flags & CORUTV_FLAG_CORE_FROM_RZ) != 0;
   HIPOK(passAt(qsrc));
   HIPOK(qr_from_partials(pl, ws, pp, nn, ldn, q2, f64 ? nullptr : (float*)wop, st + nqr++, s,
-                         core_rz ? core : nullptr));
+                         core_rz ? core : nullptr, !f64));
   if (core_rz) {
     // D = Q1^T P Q2 = R_Z^T (Q2 R_Z = Z = P^T Q1): no pass over A; the
     // QRCP of D reads R_Z transposed, the QRCP of D^T reads R_Z as is
@@ -398,16 +411,18 @@ int enqueue_decompose(corutv_ctx* ctx, const Plan& pl, char* ws, const DecArgs& 
 }
 
 int finish_info(const Enqueued& eq, const int* hst, const double* hsum, corutv_info* info) {
-  int fallbacks = 0, numeric = 0;
+  int fallbacks = 0, numeric = 0, single = 0;
   for (int i = 0; i < eq.nqr; ++i) {
     if (hst[i] & 2) numeric = 1;
     if ((hst[i] & 3) == 1) ++fallbacks;
+    if ((hst[i] & 7) == 4) ++single;
   }
   if (info) {
     info->ell = 0;
     info->transposed = eq.transposed;
     info->tri = eq.tri;
     info->qr_fallbacks = fallbacks;
+    info->qr_one_step = single;
     info->passes = eq.passes;
     info->rel_err = -1.0;
     info->a_fro = -1.0;
@@ -658,14 +673,14 @@ int corutv_tsqr(corutv_ctx* ctx, const double* X, int64_t rows, int32_t ell, int
   MatOut ox1;
   ox1.ptr = x1;
   ox1.ld = ld;
-  HIPOK(launch_rowmat(x0, ld, rows, ell, Ri, ell, nullptr, ox1, 1, MatOut(), 0, st, s));
+  HIPOK(launch_rowmat(x0, ld, rows, ell, Ri, ell, nullptr, ox1, 1, MatOut(), 0, st, s, true));
   HIPOK(launch_xty(x1, ld, x1, ld, rows, ell, xp, splits, st, s));
   HIPOK(launch_reduce(xp, splits, l2e, G, st, s));
   HIPOK(launch_chol(G, ell, R2, Ri, st, st, cw, s));
   MatOut oq;
   oq.ptr = qq;
   oq.ld = ld;
-  HIPOK(launch_rowmat(x1, ld, rows, ell, Ri, ell, nullptr, oq, 1, MatOut(), 0, st, s));
+  HIPOK(launch_rowmat(x1, ld, rows, ell, Ri, ell, nullptr, oq, 1, MatOut(), 0, st, s, true));
   HIPOK(launch_householder_qr(x0, ld, rows, ell, x1, ld, qq, ld, nullptr, 0, Rh, st, s));
   int hst = 0;
   HIPOK(hipMemcpyAsync(&hst, st, 4, hipMemcpyDeviceToHost, s));
@@ -681,7 +696,7 @@ int corutv_tsqr(corutv_ctx* ctx, const double* X, int64_t rows, int32_t ell, int
       MatOut orr;  // R = R2 R1
       orr.ptr = R;
       orr.ld = ldr;
-      HIPOK(launch_rowmat(R2, ell, ell, ell, R1, ell, nullptr, orr, 0, MatOut(), 0, nullptr, s));
+      HIPOK(launch_rowmat(R2, ell, ell, ell, R1, ell, nullptr, orr, 0, MatOut(), 0, nullptr, s, true));
     }
   }
   if (hipStreamSynchronize(s) != hipSuccess) return poison(ctx);

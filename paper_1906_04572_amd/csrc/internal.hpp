@@ -80,19 +80,24 @@ struct MatOut {
 // ldb; X column-major FP64).  When `perm` is given, Y[:, j] = X[:, perm[j]]
 // instead (B unused).  Outputs: up to two destinations (may be null).  Rows
 // >= rows are not written; columns ell..ellp-1 of FP64 skinny destinations
-// (dtype F64/F32 column-major with pad = 1) are zero-filled.
+// (dtype F64/F32 column-major with pad = 1) are zero-filled.  b_upper: B is
+// upper triangular (entries below the diagonal are zero and are skipped).
+// Runs only when *skip == run_val (skip may be null).
 hipError_t launch_rowmat(const double* X, int64_t ldx, int64_t rows, int ell, const double* B,
                          int64_t ldb, const int32_t* perm, MatOut o1, int pad1, MatOut o2, int pad2,
-                         const int* skip, hipStream_t st);
+                         const int* skip, hipStream_t st, bool b_upper = false, int run_val = 0);
 
 // Cholesky G = R^T R of an SPD ell x ell FP64 matrix (column-major, ld ell)
 // and the inverse of R, both written column-major (ld ell).  status gets
 // bit 1 on breakdown (non-positive or non-finite pivot) and bit 2 when the
 // input holds NaN/Inf.  Runs only when *skip == 0 (skip may be null).
 // work: chol_work_bytes(ell) bytes of device scratch (0 for ell <= 128).
+// single_thr > 0: on success, status also gets bit 3 (value 4) when
+// u * ell * ||R||_F^2 * ||R^-1||_F^2 <= single_thr, i.e. when one CholeskyQR
+// step already leaves an orthogonality loss below that level.
 size_t chol_work_bytes(int ell);
 hipError_t launch_chol(const double* G, int ell, double* R, double* Rinv, int* status,
-                       const int* skip, double* work, hipStream_t st);
+                       const int* skip, double* work, hipStream_t st, double single_thr = 0.0);
 
 // R = R2 R1 (upper triangular, column-major ld ell) when *status shows the
 // Cholesky route was taken; otherwise does nothing.

@@ -113,22 +113,22 @@ __global__ void __launch_bounds__(256) xty_kernel(const double* __restrict__ Xa,
   const int64_t per = (rows + splits - 1) / splits;
   const int64_t r0 = (int64_t)split * per;
   const int64_t r1 = r0 + per < rows ? r0 + per : rows;
-  // loader: thread covers column tid / 32 + 8 e, row tid % 32 of a chunk
+  // loader: thread covers column tid / 32 + 8 e, row tid % 32 of a chunk.
+  // Loads use clamped (always valid) addresses and are unconditional; the
+  // mask is applied when the values are stored to LDS, one iteration later,
+  // so the compiler cannot turn a masked load into a branch that waits for it.
   const int lr = tid & (XR - 1), lc = tid >> 5;
   double va[8], vb[8];
   auto fetch = [&](int64_t rb0) {
     const int64_t row = rb0 + lr;
-    const bool ok = row < r1;
-    const int64_t rr = ok ? row : r0;  // clamped: always a valid row
+    const int64_t rr = row < r1 ? row : r0;
 #pragma unroll
     for (int e = 0; e < 8; ++e) {
       const int c = lc + 8 * e;
       const int ca = a0 + c < ell ? a0 + c : ell - 1;
       const int cb = b0 + c < ell ? b0 + c : ell - 1;
-      const double x = Xa[(int64_t)ca * lda + rr];
-      const double y = Xb[(int64_t)cb * ldb + rr];
-      va[e] = (ok && a0 + c < ell) ? x : 0.0;
-      vb[e] = (ok && b0 + c < ell) ? y : 0.0;
+      va[e] = Xa[(int64_t)ca * lda + rr];
+      vb[e] = Xb[(int64_t)cb * ldb + rr];
     }
   };
   d4x acc[2][2];
@@ -138,10 +138,12 @@ __global__ void __launch_bounds__(256) xty_kernel(const double* __restrict__ Xa,
     for (int y = 0; y < 2; ++y) acc[x][y] = (d4x){0.0, 0.0, 0.0, 0.0};
   if (r0 < r1) fetch(r0);
   for (int64_t rb0 = r0; rb0 < r1; rb0 += XR) {
+    const bool rok = rb0 + lr < r1;
 #pragma unroll
     for (int e = 0; e < 8; ++e) {
-      sa[(lc + 8 * e) * XSP + lr] = va[e];
-      sb[(lc + 8 * e) * XSP + lr] = vb[e];
+      const int c = lc + 8 * e;
+      sa[c * XSP + lr] = (rok && a0 + c < ell) ? va[e] : 0.0;
+      sb[c * XSP + lr] = (rok && b0 + c < ell) ? vb[e] : 0.0;
     }
     __syncthreads();
     if (rb0 + XR < r1) fetch(rb0 + XR);
@@ -206,12 +208,24 @@ __device__ __forceinline__ void store_out(const MatOut& o, int64_t i, int c, dou
     ((float*)o.ptr)[off] = (float)v;
 }
 
+// The same with streaming (non-temporal) stores: results that the next
+// kernel reads anyway come from memory (each XCD's L2 is written back and
+// invalidated between kernels), so they need not stay dirty in L2 until the
+// end of the kernel.
+__device__ __forceinline__ void store_out_nt(const MatOut& o, int64_t i, int c, double v) {
+  const int64_t off = o.layout == CORUTV_COL_MAJOR ? (int64_t)c * o.ld + i : i * o.ld + c;
+  if (o.dtype == CORUTV_F64)
+    __builtin_nontemporal_store(v, (double*)o.ptr + off);
+  else
+    __builtin_nontemporal_store((float)v, (float*)o.ptr + off);
+}
+
 __global__ void __launch_bounds__(256) rowmat_kernel(const double* __restrict__ X, int64_t ldx,
                                                      int64_t rows, int ell, const double* __restrict__ B,
                                                      int64_t ldb, const int32_t* __restrict__ perm,
                                                      MatOut o1, int pad1, MatOut o2, int pad2,
-                                                     const int* skip) {
-  if (skip && *skip) return;
+                                                     const int* skip, int run_val) {
+  if (skip && *skip != run_val) return;
   constexpr int KB = 32;
   __shared__ double sx[64][KB + 1];
   __shared__ double sbm[KB][64 + 1];
@@ -279,84 +293,111 @@ __global__ void __launch_bounds__(256) rowmat_kernel(const double* __restrict__ 
 
 // Y = X B on FP64 matrix cores, computed as Y^T = B^T X^T so that the
 // accumulator lanes run along rows of Y (coalesced column-major stores).  A
-// workgroup (4 waves) owns 64 rows x 64 columns of Y; wave w computes 32
-// columns x 32 rows as 2 x 2 tiles.  B^T is staged through LDS in chunks of
-// 32 of the contraction index; X is read straight from global memory (16
-// consecutive rows per lane group).  Rows and contraction indices past the
-// ends are clamped for the loads and masked to zero.
+// workgroup (4 waves) owns 32 rows x 128 columns of Y; wave w computes rows
+// 16 (w & 1) .. + 15 for the four 16-column tiles of column half w >> 1, with
+// X read straight from global memory (16 consecutive rows per lane group).
+// B^T is staged through LDS in chunks of 32 of the contraction index (two
+// buffers, one barrier per chunk).  The next chunk's loads go to a second
+// register set before the current chunk's products.  Addresses past the ends
+// are clamped to valid entries, so every load is unconditional; only the
+// contraction indices past the end of a ragged last chunk are masked (X set
+// to zero there; B is finite, and columns past ell are never stored).  With
+// b_upper (B upper triangular) a tile skips the chunks that lie below its
+// diagonal.  32-row blocks keep the work per CU even at a few hundred blocks.
 __global__ void __launch_bounds__(256) rowmat_mfma_kernel(const double* __restrict__ X, int64_t ldx,
                                                           int64_t rows, int ell,
                                                           const double* __restrict__ B, int64_t ldb,
                                                           MatOut o1, int pad1, MatOut o2, int pad2,
-                                                          const int* skip) {
-  if (skip && *skip) return;
-  constexpr int KB = 32, SP = KB + 1;
-  __shared__ double sbt[64 * SP];  // sbt[c * SP + k] = B[k0 + k][c0 + c]
+                                                          int b_upper, const int* skip, int run_val) {
+  if (skip && *skip != run_val) return;
+  constexpr int KB = 32, SP = KB + 1, KS = KB / 4, NT = 4, CW = 128;
+  constexpr int BPT = KB * CW / 256;  // B values staged per thread and chunk
+  __shared__ double sbt[2][CW * SP];  // sbt[buf][c * SP + k] = B[k0 + k][c0 + c]
   const int tid = threadIdx.x, lane = tid & 63, w = tid >> 6;
   const int g = lane >> 4, i = lane & 15;
-  const int64_t r0 = (int64_t)blockIdx.x * 64;
-  const int c0 = blockIdx.y * 64;
+  const int64_t r0 = (int64_t)blockIdx.x * 32;
+  const int c0 = blockIdx.y * CW;
+  const int cw0 = 64 * (w >> 1);  // this wave's first column within the block
   const int ellp = pad_ell(ell);
-  const int wc = (w & 1) * 32, wr = (w >> 1) * 32;
-  int64_t rr[2];
-  bool rok[2];
+  const int ntw = (ellp - c0 - cw0) / 16;  // this wave's column tiles (may be <= 0)
+  const int nt = ntw < NT ? ntw : NT;
+  const int kend = b_upper ? (c0 + CW < ell ? c0 + CW : ell) : ell;
+  const int nchunk = (kend + KB - 1) / KB, nfull = kend / KB;
+  const int64_t rw = r0 + 16 * (w & 1) + i;
+  const bool rok = rw < rows;
+  const int64_t rr = rok ? rw : rows - 1;
+  // two register sets, used alternately, so the loads for chunk ci + 1 land
+  // in registers that the products of chunk ci do not read
+  double bq0[BPT], xq0[KS], bq1[BPT], xq1[KS];
+  auto fetch = [&](int k0, double (&bq)[BPT], double (&xq)[KS]) {
 #pragma unroll
-  for (int y = 0; y < 2; ++y) {
-    const int64_t r = r0 + wr + 16 * y + i;
-    rok[y] = r < rows;
-    rr[y] = rok[y] ? r : rows - 1;
-  }
-  d4x acc[2][2];
-#pragma unroll
-  for (int x = 0; x < 2; ++x)
-#pragma unroll
-    for (int y = 0; y < 2; ++y) acc[x][y] = (d4x){0.0, 0.0, 0.0, 0.0};
-  for (int k0 = 0; k0 < ell; k0 += KB) {
-    for (int e = tid; e < 64 * KB; e += 256) {
-      const int k = e % KB, c = e / KB;
-      sbt[c * SP + k] = (k0 + k < ell && c0 + c < ell) ? B[(int64_t)(c0 + c) * ldb + k0 + k] : 0.0;
+    for (int j = 0; j < BPT; ++j) {
+      const int e = tid + 256 * j, k = e % KB, c = e / KB;
+      const int kk = k0 + k < ell ? k0 + k : ell - 1;
+      const int cc = c0 + c < ell ? c0 + c : ell - 1;
+      bq[j] = B[(int64_t)cc * ldb + kk];
     }
-    __syncthreads();
-    double xv[KB / 4][2];
 #pragma unroll
-    for (int ks = 0; ks < KB / 4; ++ks) {
+    for (int ks = 0; ks < KS; ++ks) {
       const int k = k0 + 4 * ks + g;
-      const int kc = k < ell ? k : ell - 1;
-#pragma unroll
-      for (int y = 0; y < 2; ++y) {
-        const double v = X[(int64_t)kc * ldx + rr[y]];
-        xv[ks][y] = k < ell ? v : 0.0;
-      }
+      xq[ks] = X[(int64_t)(k < ell ? k : ell - 1) * ldx + rr];
     }
+  };
+  d4x acc[NT];
 #pragma unroll
-    for (int ks = 0; ks < KB / 4; ++ks) {
-      const int k = 4 * ks + g;
-      const double b0f = sbt[(wc + i) * SP + k], b1f = sbt[(wc + 16 + i) * SP + k];
-      acc[0][0] = __builtin_amdgcn_mfma_f64_16x16x4f64(b0f, xv[ks][0], acc[0][0], 0, 0, 0);
-      acc[0][1] = __builtin_amdgcn_mfma_f64_16x16x4f64(b0f, xv[ks][1], acc[0][1], 0, 0, 0);
-      acc[1][0] = __builtin_amdgcn_mfma_f64_16x16x4f64(b1f, xv[ks][0], acc[1][0], 0, 0, 0);
-      acc[1][1] = __builtin_amdgcn_mfma_f64_16x16x4f64(b1f, xv[ks][1], acc[1][1], 0, 0, 0);
+  for (int t = 0; t < NT; ++t) acc[t] = (d4x){0.0, 0.0, 0.0, 0.0};
+  auto chunk = [&](int ci, double (&bq)[BPT], double (&xq)[KS], double (&bn)[BPT], double (&xn)[KS]) {
+    const int k0 = ci * KB;
+    double* sb = sbt[ci & 1];
+#pragma unroll
+    for (int j = 0; j < BPT; ++j) {
+      const int e = tid + 256 * j, k = e % KB, c = e / KB;
+      sb[c * SP + k] = bq[j];
+    }
+    if (ci >= nfull) {  // ragged last chunk (uniform)
+#pragma unroll
+      for (int ks = 0; ks < KS; ++ks) xq[ks] = k0 + 4 * ks + g < kend ? xq[ks] : 0.0;
     }
     __syncthreads();
-  }
+    // unconditional, so that the wait counts are the same on every path (the
+    // last chunk reloads itself into the idle set)
+    fetch(ci + 1 < nchunk ? k0 + KB : k0, bn, xn);
+    __builtin_amdgcn_sched_barrier(0);
 #pragma unroll
-  for (int x = 0; x < 2; ++x)
+    for (int t = 0; t < NT; ++t) {
+      const int ct = cw0 + 16 * t;  // tile's first column within the block
+      // tile t needs this chunk unless all of it lies below B's diagonal
+      if (t < nt && (!b_upper || k0 <= c0 + ct + 15)) {
 #pragma unroll
-    for (int y = 0; y < 2; ++y) {
-      if (!rok[y]) continue;
-      const int64_t r = rr[y];
-#pragma unroll
-      for (int s = 0; s < 4; ++s) {
-        const int c = c0 + wc + 16 * x + g + 4 * s;
-        if (c < ell) {
-          if (o1.ptr) store_out(o1, r, c, acc[x][y][s]);
-          if (o2.ptr) store_out(o2, r, c, acc[x][y][s]);
-        } else if (c < ellp) {
-          if (o1.ptr && pad1) store_out(o1, r, c, 0.0);
-          if (o2.ptr && pad2) store_out(o2, r, c, 0.0);
+        for (int ks = 0; ks < KS; ++ks) {
+          const double bf = sb[(ct + i) * SP + 4 * ks + g];
+          acc[t] = __builtin_amdgcn_mfma_f64_16x16x4f64(bf, xq[ks], acc[t], 0, 0, 0);
         }
       }
     }
+    __builtin_amdgcn_sched_barrier(0);
+  };
+  fetch(0, bq0, xq0);
+  for (int ci = 0; ci < nchunk; ci += 2) {
+    chunk(ci, bq0, xq0, bq1, xq1);
+    if (ci + 1 < nchunk) chunk(ci + 1, bq1, xq1, bq0, xq0);
+  }
+  if (!rok) return;
+#pragma unroll
+  for (int t = 0; t < NT; ++t) {
+    if (t >= nt) break;
+#pragma unroll
+    for (int s = 0; s < 4; ++s) {
+      const int c = c0 + cw0 + 16 * t + g + 4 * s;
+      if (c < ell) {
+        if (o1.ptr) store_out_nt(o1, rr, c, acc[t][s]);
+        if (o2.ptr) store_out_nt(o2, rr, c, acc[t][s]);
+      } else if (c < ellp) {
+        if (o1.ptr && pad1) store_out_nt(o1, rr, c, 0.0);
+        if (o2.ptr && pad2) store_out_nt(o2, rr, c, 0.0);
+      }
+    }
+  }
 }
 
 // ---------------------------------------------------------------------------
@@ -417,6 +458,12 @@ __device__ __forceinline__ d4c tile_atb(const double* A, const double* B, d4c ac
 #pragma unroll
   for (int ks = 0; ks < 4; ++ks) acc = __builtin_amdgcn_mfma_f64_16x16x4f64(a[ks], b[ks], acc, 0, 0, 0);
   return acc;
+}
+
+__device__ __forceinline__ double wave_sum_f64(double v) {
+#pragma unroll
+  for (int off = 32; off > 0; off >>= 1) v += __shfl_xor(v, off, 64);
+  return v;
 }
 
 __device__ __forceinline__ double readlane_f64(double v, int l) {
@@ -482,12 +529,14 @@ __device__ __forceinline__ int chol_eidx(int I, int K) { return I * (I + 1) / 2 
 template <bool kLds>
 __global__ void __launch_bounds__(1024) chol_kernel(const double* __restrict__ G, int ell,
                                                     double* __restrict__ R, double* __restrict__ Rinv,
-                                                    int* status, const int* skip, double* work) {
+                                                    int* status, const int* skip, double* work,
+                                                    double single_thr) {
   if (skip && *skip) return;
   constexpr int kLdsTiles = kLds ? kCholLdsNb * (kCholLdsNb + 1) : 1;
   __shared__ double lds_tiles[kLdsTiles * 256];
   __shared__ double xt[256], dbuf[256];
   __shared__ double red[8];
+  __shared__ double red_r[16], red_i[16];
   __shared__ double thr_s;
   __shared__ int flag;
   const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6, nwaves = blockDim.x >> 6;
@@ -596,7 +645,9 @@ __global__ void __launch_bounds__(1024) chol_kernel(const double* __restrict__ G
     }
   }
   // R (upper, zeros below) and R^{-1} = Z^T, column-major; one 16 x 16
-  // block per wave at a time, 16 lanes writing 16 consecutive rows
+  // block per wave at a time, 16 lanes writing 16 consecutive rows.  The
+  // squared Frobenius norms of both are summed on the way.
+  double ssr = 0.0, ssi = 0.0;
   for (int tt = wave; tt < nb * nb; tt += nwaves) {
     const int I = tt % nb, K = tt / nb;  // row block, column block
 #pragma unroll
@@ -612,6 +663,28 @@ __global__ void __launch_bounds__(1024) chol_kernel(const double* __restrict__ G
       }
       R[(int64_t)c * ell + r] = vr;
       Rinv[(int64_t)c * ell + r] = vi;
+      ssr += vr * vr;
+      ssi += vi * vi;
+    }
+  }
+  if (single_thr > 0.0) {
+    // One CholeskyQR step leaves Q^T Q - I of order u kappa(X)^2, and
+    // kappa_2(R) <= ||R||_F ||R^-1||_F.  When u l (||R||_F ||R^-1||_F)^2 is at
+    // most single_thr, the second step is not needed: status bit 3.
+    ssr = wave_sum_f64(ssr);
+    ssi = wave_sum_f64(ssi);
+    if (lane == 0) {
+      red_r[wave] = ssr;
+      red_i[wave] = ssi;
+    }
+    __syncthreads();
+    if (tid == 0) {
+      double a = 0.0, b = 0.0;
+      for (int q = 0; q < nwaves; ++q) {
+        a += red_r[q];
+        b += red_i[q];
+      }
+      if (2.220446049250313e-16 * ell * a * b <= single_thr) atomicOr(status, 4);
     }
   }
 }
@@ -827,16 +900,21 @@ __global__ void fill_int_kernel(int* p, int n, int v) {
 }
 
 // R = R2 R1 for two upper triangular l x l factors (column-major, ld l):
-// the R factor of CholeskyQR2 (X = Q' R1, Q' = Q R2).  Runs only when the
-// QR took the Cholesky route ((*status & 3) == 0); after a breakdown the
-// Householder fallback writes R itself.
+// the R factor of CholeskyQR2 (X = Q' R1, Q' = Q R2); R = R1 when the QR
+// stopped after one step (status 4).  After a breakdown the Householder
+// fallback writes R itself.
 __global__ void __launch_bounds__(256) trprod_kernel(const double* __restrict__ R2,
                                                      const double* __restrict__ R1, int ell,
                                                      double* __restrict__ R, const int* status) {
-  if ((*status & 3) != 0) return;
+  const int sw = *status & 7;
+  if (sw != 0 && sw != 4) return;
   const int e = blockIdx.x * 256 + threadIdx.x;
   if (e >= ell * ell) return;
   const int i = e % ell, j = e / ell;
+  if (sw == 4) {  // one CholeskyQR step: R = R1
+    R[e] = R1[e];
+    return;
+  }
   double v = 0.0;
   for (int t = i; t <= j; ++t) v = fma(R2[(int64_t)t * ell + i], R1[(int64_t)j * ell + t], v);
   R[e] = i <= j ? v : 0.0;
@@ -890,14 +968,18 @@ hipError_t launch_reduce(const double* part, int splits, int64_t elems, double* 
 
 hipError_t launch_rowmat(const double* X, int64_t ldx, int64_t rows, int ell, const double* B,
                          int64_t ldb, const int32_t* perm, MatOut o1, int pad1, MatOut o2, int pad2,
-                         const int* skip, hipStream_t st) {
+                         const int* skip, hipStream_t st, bool b_upper, int run_val) {
   if (rows == 0) return hipSuccess;
   const int ellp = pad_ell(ell);
-  dim3 grid((unsigned)((rows + 63) / 64), (unsigned)((ellp + 63) / 64));
-  if (perm)
-    rowmat_kernel<<<grid, dim3(256), 0, st>>>(X, ldx, rows, ell, B, ldb, perm, o1, pad1, o2, pad2, skip);
-  else
-    rowmat_mfma_kernel<<<grid, dim3(256), 0, st>>>(X, ldx, rows, ell, B, ldb, o1, pad1, o2, pad2, skip);
+  if (perm) {
+    const dim3 grid((unsigned)((rows + 63) / 64), (unsigned)((ellp + 63) / 64));
+    rowmat_kernel<<<grid, dim3(256), 0, st>>>(X, ldx, rows, ell, B, ldb, perm, o1, pad1, o2, pad2, skip,
+                                              run_val);
+  } else {
+    const dim3 grid((unsigned)((rows + 31) / 32), (unsigned)((ellp + 127) / 128));
+    rowmat_mfma_kernel<<<grid, dim3(256), 0, st>>>(X, ldx, rows, ell, B, ldb, o1, pad1, o2, pad2,
+                                                   b_upper ? 1 : 0, skip, run_val);
+  }
   return hipGetLastError();
 }
 
@@ -907,11 +989,11 @@ size_t chol_work_bytes(int ell) {
 }
 
 hipError_t launch_chol(const double* G, int ell, double* R, double* Rinv, int* status,
-                       const int* skip, double* work, hipStream_t st) {
+                       const int* skip, double* work, hipStream_t st, double single_thr) {
   if ((ell + 15) / 16 <= kCholLdsNb)
-    chol_kernel<true><<<dim3(1), dim3(1024), 0, st>>>(G, ell, R, Rinv, status, skip, nullptr);
+    chol_kernel<true><<<dim3(1), dim3(1024), 0, st>>>(G, ell, R, Rinv, status, skip, nullptr, single_thr);
   else
-    chol_kernel<false><<<dim3(1), dim3(1024), 0, st>>>(G, ell, R, Rinv, status, skip, work);
+    chol_kernel<false><<<dim3(1), dim3(1024), 0, st>>>(G, ell, R, Rinv, status, skip, work, single_thr);
   return hipGetLastError();
 }
 

@@ -116,6 +116,44 @@ def test_f32_cases(ctx, m, n, k, p, q, layout):
     assert np.max(np.abs(V.T @ V - np.eye(ell))) <= 1e-5
 
 
+@pytest.mark.parametrize("prec", ["f32", "bf16x3", "f64"])
+def test_one_step_cholesky_qr_well_conditioned(ctx, prec):
+    # exp(-i/25) decay: the sketches have condition numbers of a few dozen, so
+    # in the FP32-stored forms every thin QR stops after one CholeskyQR step
+    # (u l (||R||_F ||R^-1||_F)^2 <= 2^-24); the F64 form always takes two
+    _say("one-step QR", prec)
+    A = decaying(3000, 2000, 300, 1e-4, seed=11, kind="exp", tau=25.0)
+    A = A if prec == "f64" else A.astype(np.float32)
+    U, T, V, piv, info = _run(ctx, A, 50, 10, 1, 5, prec, "auto")
+    print("qr_one_step", info["qr_one_step"], "fallbacks", info["qr_fallbacks"])
+    assert info["qr_fallbacks"] == 0
+    assert info["qr_one_step"] == (0 if prec == "f64" else 4)
+    A64 = A.astype(np.float64)
+    ref = corutv(A64, 50, 10, 1, seed=5)
+    e_ref = rel_err(A64, ref["U"], ref["T"], ref["V"])
+    assert abs(info["rel_err"] - e_ref) <= (1e-10 if prec == "f64" else 1e-5)
+    # the factors stay orthonormal to FP32 storage precision at least
+    ell = 60
+    assert np.max(np.abs(U.T @ U - np.eye(ell))) <= 1e-6
+    assert np.max(np.abs(V.T @ V - np.eye(ell))) <= 1e-6
+
+
+def test_one_step_cholesky_qr_refused_when_ill_conditioned(ctx):
+    # exp(-i/5) decay without noise: condition numbers near 1e5, where one
+    # step would lose orthogonality far above FP32 rounding, so the QRs take
+    # the second step (and CholeskyQR does not break down)
+    _say("one-step QR refused")
+    A = decaying(3000, 2000, 300, 0.0, seed=12, kind="exp", tau=5.0).astype(np.float32)
+    U, T, V, piv, info = _run(ctx, A, 50, 10, 0, 5, "f32", "auto")
+    print("qr_one_step", info["qr_one_step"], "fallbacks", info["qr_fallbacks"])
+    assert info["qr_one_step"] < 2
+    A64 = A.astype(np.float64)
+    ref = corutv(A64, 50, 10, 0, seed=5)
+    e_ref = rel_err(A64, ref["U"], ref["T"], ref["V"])
+    assert abs(info["rel_err"] - e_ref) <= 1e-5
+    assert np.max(np.abs(U.T @ U - np.eye(60))) <= 1e-5
+
+
 @pytest.mark.parametrize("prec", ["f64", "f32"])
 def test_exact_low_rank_is_recovered(ctx, prec):
     _say("exact rank", prec)
