@@ -244,6 +244,11 @@ __global__ void __launch_bounds__(256) sketch_kernel(SketchArgs a) {
                 acc[mb][nb] = M::op(sf[mb][tt], bv, acc[mb][nb]);
               }
         }
+        // FP32: keep the next chunk's masking behind this chunk's products:
+        // the scheduler would otherwise hoist it between them and wait there
+        // for the loads just issued.  (The FP64 kernel is faster without the
+        // barrier, which costs it registers.)
+        if constexpr (sizeof(T) == 4) __builtin_amdgcn_sched_barrier(0);
 #pragma unroll
         for (int e = 0; e < NB * KG * 4; ++e) bcur[e] = ((mnext >> e) & 1u) ? bnext[e] : T(0);
       }
