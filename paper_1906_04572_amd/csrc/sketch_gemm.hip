@@ -68,7 +68,7 @@ struct SketchArgs {
 };
 
 template <typename T, int MB, bool TRANS, int NB>
-__global__ void __launch_bounds__(256) sketch_kernel(SketchArgs a) {
+__global__ void __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(sizeof(T) == 4 ? 3 : 1))) sketch_kernel(SketchArgs a) {
   using M = Mma<T>;
   using acc_t = typename M::acc;
   using v16 = typename M::v16;
@@ -221,28 +221,28 @@ __global__ void __launch_bounds__(256) sketch_kernel(SketchArgs a) {
         const T* ls = &lds_s[buf][0];
 #pragma unroll
         for (int h = 0; h < KG; ++h) {
-          T sf[MB][4];
 #pragma unroll
           for (int mb = 0; mb < MB; ++mb) {
+            // one block row of the skinny operand at a time keeps few
+            // registers live (the products of different rows are independent)
+            T sf[4];
             const T* src = ls + (mb * 16 + qd) * LDK + 16 * h + 4 * g;
             if constexpr (sizeof(T) == 4) {
               const f4 vv = *(const f4*)src;
-              sf[mb][0] = vv[0]; sf[mb][1] = vv[1]; sf[mb][2] = vv[2]; sf[mb][3] = vv[3];
+              sf[0] = vv[0]; sf[1] = vv[1]; sf[2] = vv[2]; sf[3] = vv[3];
             } else {
               const d2 v0 = *(const d2*)src;
               const d2 v1 = *(const d2*)(src + 2);
-              sf[mb][0] = v0[0]; sf[mb][1] = v0[1]; sf[mb][2] = v1[0]; sf[mb][3] = v1[1];
+              sf[0] = v0[0]; sf[1] = v0[1]; sf[2] = v1[0]; sf[3] = v1[1];
             }
-          }
 #pragma unroll
-          for (int tt = 0; tt < 4; ++tt)
-#pragma unroll
-            for (int mb = 0; mb < MB; ++mb)
+            for (int tt = 0; tt < 4; ++tt)
 #pragma unroll
               for (int nb = 0; nb < NB; ++nb) {
                 const T bv = TRANS ? bcur[(h * 4 + tt) * NB + nb] : bcur[(nb * KG + h) * 4 + tt];
-                acc[mb][nb] = M::op(sf[mb][tt], bv, acc[mb][nb]);
+                acc[mb][nb] = M::op(sf[tt], bv, acc[mb][nb]);
               }
+          }
         }
         // FP32: keep the next chunk's masking behind this chunk's products:
         // the scheduler would otherwise hoist it between them and wait there
