@@ -56,7 +56,17 @@ __global__ void __launch_bounds__(256) sum_partials_kernel(Partials p, const T* 
     double v = 0.0;
     if (c < ell) {
       const T* src = P + (int64_t)c * p.tw + nl;
-      for (int k = 0; k < ns; ++k) v += (double)src[(int64_t)seg[k] * tile_elems];
+      // loads in groups of eight so their latencies overlap; the sum still
+      // runs over the slots in list order
+      int k = 0;
+      for (; k + 8 <= ns; k += 8) {
+        T l[8];
+#pragma unroll
+        for (int j = 0; j < 8; ++j) l[j] = src[(int64_t)seg[k + j] * tile_elems];
+#pragma unroll
+        for (int j = 0; j < 8; ++j) v += (double)l[j];
+      }
+      for (; k < ns; ++k) v += (double)src[(int64_t)seg[k] * tile_elems];
     }
     if (out64) out64[(int64_t)c * ld + n] = v;
     if (out32) out32[(int64_t)c * ld + n] = (float)v;
