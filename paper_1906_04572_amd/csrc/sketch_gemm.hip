@@ -64,11 +64,14 @@ struct SketchArgs {
   int64_t lds;
   void* P;
   int tiles, nk, nkx, gx, maxslot;
-  int vec;  // A rows 16-byte aligned: vector loads allowed
 };
 
-template <typename T, int MB, bool TRANS, int NB>
-__global__ void __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(sizeof(T) == 4 ? 3 : 1))) sketch_kernel(SketchArgs a) {
+// VEC: A rows 16-byte aligned (address and leading dimension), so vector
+// loads are allowed.  A template argument, not a runtime flag: a runtime
+// branch between the two load paths costs the compiler its exact count of
+// outstanding loads, and it then waits for more of them than needed.
+template <typename T, int MB, bool TRANS, int NB, bool VEC>
+__global__ void __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(sizeof(T) == 4 ? 3 : (MB <= 8 ? 2 : 1)))) sketch_kernel(SketchArgs a) {
   using M = Mma<T>;
   using acc_t = typename M::acc;
   using v16 = typename M::v16;
@@ -154,7 +157,7 @@ __global__ void __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(sizeof
               T* d = b + base;
 #pragma unroll
               for (int e = 0; e < 4; ++e) mask |= (uint32_t)(nok && k + e < a.K) << (base + e);
-              if (a.vec) {
+              if constexpr (VEC) {
                 // rows are 16-byte aligned and lda is a multiple of 4, so the
                 // 4-vector at k < K stays inside the row's allocation
                 const T* src = A + nc * a.lda + (k < a.K ? k : 0);
@@ -185,7 +188,7 @@ __global__ void __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(sizeof
               T* d = b + base;
 #pragma unroll
               for (int e = 0; e < NB; ++e) mask |= (uint32_t)(kok && n0 + e < a.N) << (base + e);
-              if (NB == 2 && a.vec) {
+              if constexpr (NB == 2 && VEC) {
                 // n0 is even and lda a multiple of 4: the pair at n0 < N is
                 // inside the row's allocation
                 const T* src = A + kc * a.lda + (n0 < a.N ? n0 : 0);
@@ -218,6 +221,9 @@ __global__ void __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(sizeof
         const int kn = kb + 1 < gk1 ? kb + 1 : kb;
         load_skinny(kn);
         load_b(kn, bnext, mnext);
+        // FP32: issue those loads here, ahead of the products (the scheduler
+        // would sink them towards their use at the end of the chunk)
+        if constexpr (sizeof(T) == 4) __builtin_amdgcn_sched_barrier(0);
         const T* ls = &lds_s[buf][0];
 #pragma unroll
         for (int h = 0; h < KG; ++h) {
@@ -297,7 +303,7 @@ __device__ __forceinline__ void split8(const float* x, bf8& hi, bf8& lo, bool wa
 // The skinny operand arrives pre-split into bf16 hi (S) and lo (S2) parts
 // (split_bf16_kernel, same rounding), so it is staged into LDS as bf16 and
 // fed to the matrix cores without per-wave conversion.
-template <int MB, bool TRANS, int NB, bool X3>
+template <int MB, bool TRANS, int NB, bool X3, bool VEC>
 __global__ void __launch_bounds__(256) sketch_bf16_kernel(SketchArgs a) {
   constexpr int KC = 32;                 // k values per LDS stage = one MFMA block
   constexpr int ELLP = MB * 16;
@@ -372,7 +378,7 @@ __global__ void __launch_bounds__(256) sketch_bf16_kernel(SketchArgs a) {
             float* d = b + nb * 8;
 #pragma unroll
             for (int e = 0; e < 8; ++e) mask |= (uint32_t)(nok && k + e < a.K) << (nb * 8 + e);
-            if (a.vec) {
+            if constexpr (VEC) {
               // lda is a multiple of 4: both 4-vectors at k < K (k a multiple
               // of 8) stay inside the row's 16-byte padded extent only when
               // k + 4 < K rounds up within lda; the second vector is clamped
@@ -396,7 +402,7 @@ __global__ void __launch_bounds__(256) sketch_bf16_kernel(SketchArgs a) {
             const int64_t n0 = nbase + NB * qd;
 #pragma unroll
             for (int e = 0; e < NB; ++e) mask |= (uint32_t)(kok && n0 + e < a.N) << (8 * e + tt);
-            if (NB == 2 && a.vec) {
+            if constexpr (NB == 2 && VEC) {
               const f2 vv = *(const f2*)(A + kc * a.lda + (n0 < a.N ? n0 : 0));
               b[tt] = vv[0];
               b[8 * (NB - 1) + tt] = vv[1];
@@ -420,6 +426,7 @@ __global__ void __launch_bounds__(256) sketch_bf16_kernel(SketchArgs a) {
         const int kn = kb + 1 < gk1 ? kb + 1 : kb;
         load_skinny(kn);
         load_b(kn, bnext, mnext);
+        __builtin_amdgcn_sched_barrier(0);  // loads ahead of the products
         bf8 bh[NB], bl[NB];
 #pragma unroll
         for (int nb = 0; nb < NB; ++nb) split8(bcur + nb * 8, bh[nb], bl[nb], X3);
@@ -473,60 +480,60 @@ __global__ void split_bf16_kernel(const float* __restrict__ S, int64_t n, __bf16
   }
 }
 
-template <int MB, bool TRANS, bool X3>
+template <int MB, bool TRANS, bool X3, bool VEC>
 void* bf16_ptr() {
   constexpr int NB = MB <= 8 ? 2 : 1;
-  return (void*)&sketch_bf16_kernel<MB, TRANS, NB, X3>;
+  return (void*)&sketch_bf16_kernel<MB, TRANS, NB, X3, VEC>;
 }
 
-template <bool TRANS, bool X3>
+template <bool TRANS, bool X3, bool VEC>
 void* pick_bf16(int mb) {
   switch (mb) {
-    case 1: return bf16_ptr<1, TRANS, X3>();
-    case 2: return bf16_ptr<2, TRANS, X3>();
-    case 3: return bf16_ptr<3, TRANS, X3>();
-    case 4: return bf16_ptr<4, TRANS, X3>();
-    case 5: return bf16_ptr<5, TRANS, X3>();
-    case 6: return bf16_ptr<6, TRANS, X3>();
-    case 7: return bf16_ptr<7, TRANS, X3>();
-    case 8: return bf16_ptr<8, TRANS, X3>();
-    case 9: return bf16_ptr<9, TRANS, X3>();
-    case 10: return bf16_ptr<10, TRANS, X3>();
-    case 11: return bf16_ptr<11, TRANS, X3>();
-    case 12: return bf16_ptr<12, TRANS, X3>();
-    case 13: return bf16_ptr<13, TRANS, X3>();
-    case 14: return bf16_ptr<14, TRANS, X3>();
-    case 15: return bf16_ptr<15, TRANS, X3>();
-    case 16: return bf16_ptr<16, TRANS, X3>();
+    case 1: return bf16_ptr<1, TRANS, X3, VEC>();
+    case 2: return bf16_ptr<2, TRANS, X3, VEC>();
+    case 3: return bf16_ptr<3, TRANS, X3, VEC>();
+    case 4: return bf16_ptr<4, TRANS, X3, VEC>();
+    case 5: return bf16_ptr<5, TRANS, X3, VEC>();
+    case 6: return bf16_ptr<6, TRANS, X3, VEC>();
+    case 7: return bf16_ptr<7, TRANS, X3, VEC>();
+    case 8: return bf16_ptr<8, TRANS, X3, VEC>();
+    case 9: return bf16_ptr<9, TRANS, X3, VEC>();
+    case 10: return bf16_ptr<10, TRANS, X3, VEC>();
+    case 11: return bf16_ptr<11, TRANS, X3, VEC>();
+    case 12: return bf16_ptr<12, TRANS, X3, VEC>();
+    case 13: return bf16_ptr<13, TRANS, X3, VEC>();
+    case 14: return bf16_ptr<14, TRANS, X3, VEC>();
+    case 15: return bf16_ptr<15, TRANS, X3, VEC>();
+    case 16: return bf16_ptr<16, TRANS, X3, VEC>();
     default: return nullptr;
   }
 }
 
-template <typename T, int MB, bool TRANS>
+template <typename T, int MB, bool TRANS, bool VEC>
 void* kernel_ptr() {
   constexpr int NB = MB <= 8 ? 2 : 1;
-  return (void*)&sketch_kernel<T, MB, TRANS, NB>;
+  return (void*)&sketch_kernel<T, MB, TRANS, NB, VEC>;
 }
 
-template <typename T, bool TRANS>
+template <typename T, bool TRANS, bool VEC>
 void* pick(int mb) {
   switch (mb) {
-    case 1: return kernel_ptr<T, 1, TRANS>();
-    case 2: return kernel_ptr<T, 2, TRANS>();
-    case 3: return kernel_ptr<T, 3, TRANS>();
-    case 4: return kernel_ptr<T, 4, TRANS>();
-    case 5: return kernel_ptr<T, 5, TRANS>();
-    case 6: return kernel_ptr<T, 6, TRANS>();
-    case 7: return kernel_ptr<T, 7, TRANS>();
-    case 8: return kernel_ptr<T, 8, TRANS>();
-    case 9: return kernel_ptr<T, 9, TRANS>();
-    case 10: return kernel_ptr<T, 10, TRANS>();
-    case 11: return kernel_ptr<T, 11, TRANS>();
-    case 12: return kernel_ptr<T, 12, TRANS>();
-    case 13: return kernel_ptr<T, 13, TRANS>();
-    case 14: return kernel_ptr<T, 14, TRANS>();
-    case 15: return kernel_ptr<T, 15, TRANS>();
-    case 16: return kernel_ptr<T, 16, TRANS>();
+    case 1: return kernel_ptr<T, 1, TRANS, VEC>();
+    case 2: return kernel_ptr<T, 2, TRANS, VEC>();
+    case 3: return kernel_ptr<T, 3, TRANS, VEC>();
+    case 4: return kernel_ptr<T, 4, TRANS, VEC>();
+    case 5: return kernel_ptr<T, 5, TRANS, VEC>();
+    case 6: return kernel_ptr<T, 6, TRANS, VEC>();
+    case 7: return kernel_ptr<T, 7, TRANS, VEC>();
+    case 8: return kernel_ptr<T, 8, TRANS, VEC>();
+    case 9: return kernel_ptr<T, 9, TRANS, VEC>();
+    case 10: return kernel_ptr<T, 10, TRANS, VEC>();
+    case 11: return kernel_ptr<T, 11, TRANS, VEC>();
+    case 12: return kernel_ptr<T, 12, TRANS, VEC>();
+    case 13: return kernel_ptr<T, 13, TRANS, VEC>();
+    case 14: return kernel_ptr<T, 14, TRANS, VEC>();
+    case 15: return kernel_ptr<T, 15, TRANS, VEC>();
+    case 16: return kernel_ptr<T, 16, TRANS, VEC>();
     default: return nullptr;
   }
 }
@@ -601,17 +608,22 @@ hipError_t launch_sketch(int prec, int trans, const void* A, int64_t lda, int64_
                          Partials* part, int num_cu, hipStream_t st, void* sbf) {
   const bool f64 = prec == P_F64;
   const int mb = ellp / 16;
+  const int elem = f64 ? 8 : 4;
+  const bool vec = (((uintptr_t)A) % 16 == 0) && ((lda * elem) % 16 == 0);
   void* fn = nullptr;
   if (prec == P_F64)
-    fn = trans ? pick<double, true>(mb) : pick<double, false>(mb);
+    fn = vec ? (trans ? pick<double, true, true>(mb) : pick<double, false, true>(mb))
+             : (trans ? pick<double, true, false>(mb) : pick<double, false, false>(mb));
   else if (prec == P_F32)
-    fn = trans ? pick<float, true>(mb) : pick<float, false>(mb);
+    fn = vec ? (trans ? pick<float, true, true>(mb) : pick<float, false, true>(mb))
+             : (trans ? pick<float, true, false>(mb) : pick<float, false, false>(mb));
   else if (prec == P_BF16)
-    fn = trans ? pick_bf16<true, false>(mb) : pick_bf16<false, false>(mb);
+    fn = vec ? (trans ? pick_bf16<true, false, true>(mb) : pick_bf16<false, false, true>(mb))
+             : (trans ? pick_bf16<true, false, false>(mb) : pick_bf16<false, false, false>(mb));
   else if (prec == P_BF16X3)
-    fn = trans ? pick_bf16<true, true>(mb) : pick_bf16<false, true>(mb);
+    fn = vec ? (trans ? pick_bf16<true, true, true>(mb) : pick_bf16<false, true, true>(mb))
+             : (trans ? pick_bf16<true, true, false>(mb) : pick_bf16<false, true, false>(mb));
   if (!fn) return hipErrorInvalidValue;
-  const int elem = f64 ? 8 : 4;
   const int64_t N = trans ? C : R;
   const int64_t K = trans ? R : C;
   int gx = (num_cu / 8) * occupancy_of(fn);
@@ -649,7 +661,6 @@ hipError_t launch_sketch(int prec, int trans, const void* A, int64_t lda, int64_
   a.nkx = part->nkx;
   a.gx = part->gx;
   a.maxslot = part->maxslot;
-  a.vec = (((uintptr_t)A) % 16 == 0) && ((lda * elem) % 16 == 0);
   void* args[] = {&a};
   return hipLaunchKernel((const void*)fn, dim3(8 * gx), dim3(256), args, 0, st);
 }
