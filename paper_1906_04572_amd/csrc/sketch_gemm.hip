@@ -305,7 +305,10 @@ __device__ __forceinline__ void split8(const float* x, bf8& hi, bf8& lo, bool wa
 // fed to the matrix cores without per-wave conversion.
 template <int MB, bool TRANS, int NB, bool X3, bool VEC>
 __global__ void __launch_bounds__(256) sketch_bf16_kernel(SketchArgs a) {
-  constexpr int KC = 32;                 // k values per LDS stage = one MFMA block
+  // k values per LDS stage: two MFMA blocks for BF16 (more bytes of A in
+  // flight per stage); one for BF16X3, whose registers allow no more
+  constexpr int KC = X3 ? 32 : 64;
+  constexpr int KB = KC / 32;            // MFMA blocks per stage
   constexpr int ELLP = MB * 16;
   constexpr int LDKB = KC + 8;           // LDS row stride in bf16 (16 bytes of pad)
   constexpr int TW = 64 * NB;
@@ -343,7 +346,7 @@ __global__ void __launch_bounds__(256) sketch_bf16_kernel(SketchArgs a) {
 
     if (gk0 < gk1) {
       f4 sreg[NPART][SPASS];  // raw 16-byte vectors of 8 bf16
-      float bcur[NB * 8], bnext[NB * 8];  // [nb][8 k values]
+      float bcur[NB * KB * 8], bnext[NB * KB * 8];  // [nb][block][8 k values]
       // unconditional loads from clamped addresses; validity bits applied
       // when the prefetched chunk becomes current (see the FP32/FP64 kernel)
       auto load_skinny = [&](int kb) {
@@ -374,43 +377,48 @@ __global__ void __launch_bounds__(256) sketch_bf16_kernel(SketchArgs a) {
             const int64_t n = nbase + nb * 16 + qd;
             const bool nok = n < a.N;
             const int64_t nc = nok ? n : a.N - 1;
-            const int64_t k = (int64_t)kb * KC + 8 * g;
-            float* d = b + nb * 8;
 #pragma unroll
-            for (int e = 0; e < 8; ++e) mask |= (uint32_t)(nok && k + e < a.K) << (nb * 8 + e);
-            if constexpr (VEC) {
-              // lda is a multiple of 4: both 4-vectors at k < K (k a multiple
-              // of 8) stay inside the row's 16-byte padded extent only when
-              // k + 4 < K rounds up within lda; the second vector is clamped
-              const float* src = A + nc * a.lda + (k < a.K ? k : 0);
-              const f4 v0 = *(const f4*)src;
-              const int64_t k2 = k + 4 < a.K ? k + 4 : (k < a.K ? k : 0);
-              const f4 v1 = *(const f4*)(A + nc * a.lda + k2);
-              d[0] = v0[0]; d[1] = v0[1]; d[2] = v0[2]; d[3] = v0[3];
-              d[4] = v1[0]; d[5] = v1[1]; d[6] = v1[2]; d[7] = v1[3];
-            } else {
+            for (int kk = 0; kk < KB; ++kk) {
+              const int64_t k = (int64_t)kb * KC + 32 * kk + 8 * g;
+              const int base = (nb * KB + kk) * 8;
+              float* d = b + base;
 #pragma unroll
-              for (int e = 0; e < 8; ++e) d[e] = A[nc * a.lda + (k + e < a.K ? k + e : 0)];
+              for (int e = 0; e < 8; ++e) mask |= (uint32_t)(nok && k + e < a.K) << (base + e);
+              if constexpr (VEC) {
+                // lda is a multiple of 4; the second 4-vector is clamped
+                const float* src = A + nc * a.lda + (k < a.K ? k : 0);
+                const f4 v0 = *(const f4*)src;
+                const int64_t k2 = k + 4 < a.K ? k + 4 : (k < a.K ? k : 0);
+                const f4 v1 = *(const f4*)(A + nc * a.lda + k2);
+                d[0] = v0[0]; d[1] = v0[1]; d[2] = v0[2]; d[3] = v0[3];
+                d[4] = v1[0]; d[5] = v1[1]; d[6] = v1[2]; d[7] = v1[3];
+              } else {
+#pragma unroll
+                for (int e = 0; e < 8; ++e) d[e] = A[nc * a.lda + (k + e < a.K ? k + e : 0)];
+              }
             }
           }
         } else {
 #pragma unroll
-          for (int tt = 0; tt < 8; ++tt) {
-            const int64_t k = (int64_t)kb * KC + 8 * g + tt;
-            const bool kok = k < a.K;
-            const int64_t kc = kok ? k : a.K - 1;
-            const int64_t n0 = nbase + NB * qd;
+          for (int kk = 0; kk < KB; ++kk)
 #pragma unroll
-            for (int e = 0; e < NB; ++e) mask |= (uint32_t)(kok && n0 + e < a.N) << (8 * e + tt);
-            if constexpr (NB == 2 && VEC) {
-              const f2 vv = *(const f2*)(A + kc * a.lda + (n0 < a.N ? n0 : 0));
-              b[tt] = vv[0];
-              b[8 * (NB - 1) + tt] = vv[1];
-            } else {
+            for (int tt = 0; tt < 8; ++tt) {
+              const int64_t k = (int64_t)kb * KC + 32 * kk + 8 * g + tt;
+              const bool kok = k < a.K;
+              const int64_t kc = kok ? k : a.K - 1;
+              const int64_t n0 = nbase + NB * qd;
 #pragma unroll
-              for (int e = 0; e < NB; ++e) b[8 * e + tt] = A[kc * a.lda + (n0 + e < a.N ? n0 + e : 0)];
+              for (int e = 0; e < NB; ++e)
+                mask |= (uint32_t)(kok && n0 + e < a.N) << ((e * KB + kk) * 8 + tt);
+              if constexpr (NB == 2 && VEC) {
+                const f2 vv = *(const f2*)(A + kc * a.lda + (n0 < a.N ? n0 : 0));
+                b[kk * 8 + tt] = vv[0];
+                b[(KB + kk) * 8 + tt] = vv[1];
+              } else {
+#pragma unroll
+                for (int e = 0; e < NB; ++e) b[(e * KB + kk) * 8 + tt] = A[kc * a.lda + (n0 + e < a.N ? n0 + e : 0)];
+              }
             }
-          }
         }
       };
 
@@ -418,7 +426,7 @@ __global__ void __launch_bounds__(256) sketch_bf16_kernel(SketchArgs a) {
       load_skinny(gk0);
       load_b(gk0, bcur, mcur);
 #pragma unroll
-      for (int e = 0; e < NB * 8; ++e) bcur[e] = ((mcur >> e) & 1u) ? bcur[e] : 0.f;
+      for (int e = 0; e < NB * KB * 8; ++e) bcur[e] = ((mcur >> e) & 1u) ? bcur[e] : 0.f;
       for (int kb = gk0; kb < gk1; ++kb, ++iter) {
         const int buf = iter & 1;
         store_skinny(buf);
@@ -427,26 +435,29 @@ __global__ void __launch_bounds__(256) sketch_bf16_kernel(SketchArgs a) {
         load_skinny(kn);
         load_b(kn, bnext, mnext);
         __builtin_amdgcn_sched_barrier(0);  // loads ahead of the products
-        bf8 bh[NB], bl[NB];
 #pragma unroll
-        for (int nb = 0; nb < NB; ++nb) split8(bcur + nb * 8, bh[nb], bl[nb], X3);
+        for (int kk = 0; kk < KB; ++kk) {
+          bf8 bh[NB], bl[NB];
 #pragma unroll
-        for (int mb = 0; mb < MB; ++mb) {
-          const int off = (mb * 16 + qd) * LDKB + 8 * g;
-          const bf8 sh = *(const bf8*)&lds_s[0][buf][off];
-          bf8 sl;
-          if constexpr (X3) sl = *(const bf8*)&lds_s[NPART - 1][buf][off];
+          for (int nb = 0; nb < NB; ++nb) split8(bcur + (nb * KB + kk) * 8, bh[nb], bl[nb], X3);
 #pragma unroll
-          for (int nb = 0; nb < NB; ++nb) {
-            if constexpr (X3) {
-              acc[mb][nb] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(sl, bh[nb], acc[mb][nb], 0, 0, 0);
-              acc[mb][nb] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(sh, bl[nb], acc[mb][nb], 0, 0, 0);
+          for (int mb = 0; mb < MB; ++mb) {
+            const int off = (mb * 16 + qd) * LDKB + 32 * kk + 8 * g;
+            const bf8 sh = *(const bf8*)&lds_s[0][buf][off];
+            bf8 sl;
+            if constexpr (X3) sl = *(const bf8*)&lds_s[NPART - 1][buf][off];
+#pragma unroll
+            for (int nb = 0; nb < NB; ++nb) {
+              if constexpr (X3) {
+                acc[mb][nb] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(sl, bh[nb], acc[mb][nb], 0, 0, 0);
+                acc[mb][nb] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(sh, bl[nb], acc[mb][nb], 0, 0, 0);
+              }
+              acc[mb][nb] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(sh, bh[nb], acc[mb][nb], 0, 0, 0);
             }
-            acc[mb][nb] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(sh, bh[nb], acc[mb][nb], 0, 0, 0);
           }
         }
 #pragma unroll
-        for (int e = 0; e < NB * 8; ++e) bcur[e] = ((mnext >> e) & 1u) ? bnext[e] : 0.f;
+        for (int e = 0; e < NB * KB * 8; ++e) bcur[e] = ((mnext >> e) & 1u) ? bnext[e] : 0.f;
       }
     }
     const int64_t slot = ((int64_t)x * a.gx + jw) * a.maxslot + (t - tfirst);
@@ -561,11 +572,13 @@ int occupancy_of(void* fn) {
   return occ;
 }
 
-void geometry(int64_t N, int64_t K, int ellp, int elem, int gx, Partials* p) {
+// k values per stage of each kernel family
+int kc_of(int prec) { return prec == P_F64 ? 16 : (prec == P_BF16 ? 64 : 32); }
+
+void geometry(int64_t N, int64_t K, int ellp, int elem, int kc, int gx, Partials* p) {
   const int mb = ellp / 16;
   const int nb = mb <= 8 ? 2 : 1;
   const int tw = 64 * nb;
-  const int kc = 128 / elem;
   p->ellp = ellp;
   p->tw = tw;
   p->elem = elem;
@@ -593,13 +606,17 @@ static int64_t need_elems(const Partials& p) {
 }
 
 int64_t partials_capacity(int64_t n_out, int64_t k_len, int ellp, int prec) {
+  // prec P_F32 stands for every float form (F32 and the bf16 ones)
   int64_t best = 0;
-  for (int occ = 1; occ <= kOccCap; ++occ) {
-    Partials p;
-    geometry(n_out, k_len, ellp, prec == P_F64 ? 8 : 4, 32 * occ, &p);
-    const int64_t e = need_elems(p);
-    if (e > best) best = e;
-  }
+  const int elem = prec == P_F64 ? 8 : 4;
+  const int kcs[2] = {kc_of(prec), kc_of(P_BF16)};
+  for (int v = 0; v < (prec == P_F64 ? 1 : 2); ++v)
+    for (int occ = 1; occ <= kOccCap; ++occ) {
+      Partials p;
+      geometry(n_out, k_len, ellp, elem, kcs[v], 32 * occ, &p);
+      const int64_t e = need_elems(p);
+      if (e > best) best = e;
+    }
   return best;
 }
 
@@ -628,10 +645,11 @@ hipError_t launch_sketch(int prec, int trans, const void* A, int64_t lda, int64_
   const int64_t K = trans ? R : C;
   int gx = (num_cu / 8) * occupancy_of(fn);
   if (gx < 1) gx = 1;
-  geometry(N, K, ellp, elem, gx, part);
+  const int kc = kc_of(prec);
+  geometry(N, K, ellp, elem, kc, gx, part);
   while (need_elems(*part) > part_elems && gx > 1) {
     gx = gx > 8 ? gx - 8 : gx - 1;
-    geometry(N, K, ellp, elem, gx, part);
+    geometry(N, K, ellp, elem, kc, gx, part);
   }
   if (need_elems(*part) > part_elems) return hipErrorInvalidValue;
   part->ptr = part_buf;
@@ -657,7 +675,7 @@ hipError_t launch_sketch(int prec, int trans, const void* A, int64_t lda, int64_
   }
   a.P = part_buf;
   a.tiles = part->tiles;
-  a.nk = (int)((K + (128 / elem) - 1) / (128 / elem));
+  a.nk = (int)((K + kc - 1) / kc);
   a.nkx = part->nkx;
   a.gx = part->gx;
   a.maxslot = part->maxslot;
