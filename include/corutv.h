@@ -91,7 +91,10 @@ typedef struct corutv_opts {
  * instead of a third pass over A.  With Q2 R_Z = Z = A^T Q1 the core is
  * D = Q1^T A Q2 = R_Z^T exactly (Sec. 3.1, eqs. 5-7), so the decomposition
  * needs 2q + 2 passes instead of 2q + 3 and returns the same factors in exact
- * arithmetic (in floating point D differs at the rounding level of the passes). */
+ * arithmetic (in floating point D differs at the rounding level of the passes).
+ * This is also the paper's single-revisit core Q1^T C1 (Q2^T Psi)^+ (Sec. 3.1,
+ * Algorithm 1): since Q1^T A = R_Z^T Q2^T, that expression equals R_Z^T
+ * whenever Q2^T Psi has full rank. */
 #define CORUTV_FLAG_CORE_FROM_RZ 1
 
 typedef struct corutv_info {

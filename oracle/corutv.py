@@ -45,7 +45,12 @@ def corutv(A, k, p, q, seed, tri="auto", sub=0, mode="stabilized", core="pass"):
 
     core: "pass" forms D = Q1^T (A Q2) (eq. 7, one more product with A);
     "rz" (stabilized mode) takes D = R_Z^T from the QR of the second sketch
-    Z = A^T Q1 = Q2 R_Z, since then Q1^T A Q2 = (A^T Q1)^T Q2 = R_Z^T Q2^T Q2."""
+    Z = A^T Q1 = Q2 R_Z, since then Q1^T A Q2 = (A^T Q1)^T Q2 = R_Z^T Q2^T Q2;
+    "approx" is the single-revisit core of Sec. 3.1 and Algorithm 1,
+    D_approx = Q1^T C1 (Q2^T Psi)^+, with C1 = A Psi the last product with A
+    and Psi the matrix it was formed from (Omega when q = 0, else the last
+    power iterate; the C2 that produced the last C1).  It equals D when
+    A = A Q2 Q2^T."""
     A = np.asarray(A, dtype=np.float64)
     m, n = A.shape
     ell = k + p
@@ -67,16 +72,20 @@ def corutv(A, k, p, q, seed, tri="auto", sub=0, mode="stabilized", core="pass"):
     if mode == "literal":
         C2 = Om
         for _ in range(q + 1):
+            Psi = C2
             C1 = A @ C2
             C2 = A.T @ C1
         Q1, R1 = householder_qr(C1)
         Q2, R2 = householder_qr(C2)
         res.update(C1=C1, C2=C2, R1=R1, R2=R2)
     elif mode == "stabilized":
-        Q1 = _qf(A @ Om)
+        Psi = Om
+        C1 = A @ Psi
+        Q1 = _qf(C1)
         for _ in range(q):
-            W = _qf(A.T @ Q1)
-            Q1 = _qf(A @ W)
+            Psi = _qf(A.T @ Q1)
+            C1 = A @ Psi
+            Q1 = _qf(C1)
         Z = A.T @ Q1
         Q2, RZ = householder_qr(Z)
         res.update(Z=Z, R_Z=RZ)
@@ -87,8 +96,11 @@ def corutv(A, k, p, q, seed, tri="auto", sub=0, mode="stabilized", core="pass"):
         D = Q1.T @ (A @ Q2)
     elif core == "rz" and mode == "stabilized":
         D = res["R_Z"].T.copy()
+    elif core == "approx":
+        D = Q1.T @ C1 @ np.linalg.pinv(Q2.T @ Psi)
+        res.update(Psi=Psi)
     else:
-        raise ValueError("core must be pass, or rz in stabilized mode")
+        raise ValueError("core must be pass, approx, or rz in stabilized mode")
     if tri == "upper":
         Qt, R, piv = qrcp(D)
         U, T, V = Q1 @ Qt, R, Q2[:, piv]

@@ -308,6 +308,27 @@ def test_core_from_rz_against_oracle(ctx, m, n, k, p, q, tri, layout, prec):
         assert abs(rel_err(A64, got[0], got[1], got[2]) - e_ref) <= 1e-5
 
 
+@pytest.mark.parametrize("q,prec", [(0, "f64"), (1, "f64"), (2, "f64"), (1, "f32")])
+def test_single_revisit_core_against_oracle(ctx, q, prec):
+    """The paper's single-revisit core Q1^T C1 (Q2^T Psi)^+, evaluated by the
+    oracle as printed (pseudo-inverse), against the GPU's R_Z^T core, which
+    is the same matrix: F64 to the 1e-10 bars, F32 |de| <= 1e-5."""
+    _say("single-revisit core", q, prec)
+    m, n, k, p = 1400, 1000, 30, 10
+    dt = np.float64 if prec == "f64" else np.float32
+    A = decaying(m, n, 500, 1e-4, seed=31 + q, kind="exp", tau=15.0).astype(dt)
+    A64 = A.astype(np.float64)
+    U, T, V, piv, info = ctx.decompose(_dev(A, "row"), k, p, q, 5, prec=prec, want_err=True, core="rz")
+    got = (U.cpu().numpy().astype(np.float64), T.cpu().numpy(), V.cpu().numpy().astype(np.float64),
+           piv.cpu().numpy(), info)
+    ref = corutv(A64, k, p, q, seed=5, core="approx")
+    if prec == "f64":
+        _check_f64(A64, k, p, q, 5, "upper", got, ref)
+    else:
+        e_ref = rel_err(A64, ref["U"], ref["T"], ref["V"])
+        assert abs(info["rel_err"] - e_ref) <= 1e-5
+
+
 def test_core_from_rz_after_cholesky_breakdown(ctx):
     """Exactly low-rank A: the QR of Z falls back to Householder, whose R
     then gives the core; the factorization is still exact."""

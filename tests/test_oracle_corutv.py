@@ -197,6 +197,51 @@ def test_planted_mistakes_are_caught():
     assert rel_err(A, r["U"], Tbad, r["V"]) > 1e-3
 
 
+@pytest.mark.parametrize("q", [0, 1, 2])
+def test_single_revisit_core_is_exact_when_the_range_is_captured(q):
+    """A of rank r <= l: A = A Q2 Q2^T exactly, so D_approx = Q1^T C1
+    (Q2^T Psi)^+ equals D = Q1^T A Q2 (Sec. 3.1): C1 = A Psi = A Q2 Q2^T Psi
+    and Q2^T Psi is invertible."""
+    rng = np.random.default_rng(40 + q)
+    A = rng.standard_normal((300, 12)) @ rng.standard_normal((12, 200))
+    a = corutv(A, 15, 5, q, seed=3)
+    b = corutv(A, 15, 5, q, seed=3, core="approx")
+    nA = np.linalg.norm(A)
+    assert np.linalg.norm(a["D"] - b["D"]) <= 1e-10 * nA
+    assert np.linalg.norm(b["U"] @ b["T"] @ b["V"].T - A) <= 1e-10 * nA
+
+
+@pytest.mark.parametrize("q", [0, 1])
+def test_single_revisit_core_literal_equals_stabilized(q):
+    """The stabilized loop's Psi is the literal C2 times an upper triangular
+    factor G^-1, and C1 = A Psi carries the same factor, so Q1^T C1 (Q2^T
+    Psi)^+ is the same matrix in both modes (App. A.1 with R5's reading)."""
+    A = decaying(400, 300, 60, 1e-6, seed=11, kind="exp", tau=8.0)
+    a = corutv(A, 10, 5, q, seed=2, mode="literal", core="approx")
+    b = corutv(A, 10, 5, q, seed=2, core="approx")
+    assert np.linalg.norm(a["D"] - b["D"]) <= 1e-8 * np.linalg.norm(A)
+
+
+@pytest.mark.parametrize("q", [0, 1, 2])
+def test_single_revisit_core_equals_the_exact_core(q):
+    """Not only for low rank: Q2 spans the range of Z = A^T Q1 (Q2 R_Z = Z),
+    so Q1^T A = R_Z^T Q2^T exactly and Q1^T C1 = Q1^T A Psi = R_Z^T (Q2^T Psi).
+    Hence D_approx = R_Z^T (Q2^T Psi)(Q2^T Psi)^+ = R_Z^T = D for any A once
+    Q2^T Psi has full rank; full-rank noise beyond rank l included."""
+    A = decaying(500, 400, 200, 1e-3, seed=5 + q, kind="exp", tau=6.0)
+    a = corutv(A, 15, 5, q, seed=9)
+    b = corutv(A, 15, 5, q, seed=9, core="approx")
+    c = corutv(A, 15, 5, q, seed=9, core="rz")
+    nA = np.linalg.norm(A)
+    assert np.linalg.norm(b["D"] - a["D"]) <= 1e-10 * nA
+    assert np.linalg.norm(b["D"] - c["D"]) <= 1e-10 * nA
+    # a planted mistake: the C2 of the final iteration instead of the one
+    # that produced C1 (R5) breaks the identity
+    if q > 0:
+        wrong = a["Q1"].T @ (A @ b["Psi"]) @ np.linalg.pinv(a["Q2"].T @ (A.T @ a["Q1"]))
+        assert np.linalg.norm(wrong - a["D"]) > 1e-3 * nA
+
+
 @pytest.mark.parametrize("m,n,q,tri", [(300, 200, 1, "upper"), (300, 200, 0, "lower"), (150, 260, 2, "auto")])
 def test_core_from_rz_gives_the_same_factorization(m, n, q, tri):
     """core="rz" (D = R_Z^T, one product with A fewer) and core="pass" give the
