@@ -201,6 +201,60 @@ def serving_leg(cu, torch, n_req, pool_size, seed=5, load=0.8, slots=3):
                         "p=10, q in {1,2}" % pool_size}
 
 
+def achievable_peaks(torch):
+    """Achievable rates on this device with vendor kernels (torch's reduction
+    and hipBLASLt GEMMs), as context for the datasheet peaks."""
+    dev = torch.device("cuda", 0)
+    out = {}
+    x = torch.ones(1 << 30, dtype=torch.float32, device=dev)  # 4 GiB
+    for _ in range(2):
+        x.sum()
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for _ in range(5):
+        x.sum()
+    torch.cuda.synchronize()
+    out["hbm_read_GBps"] = round(5 * x.numel() * 4 / (time.perf_counter() - t0) / 1e9, 1)
+    del x
+    for name, dt, n in (("fp64", torch.float64, 8192), ("fp32", torch.float32, 8192),
+                        ("bf16", torch.bfloat16, 8192)):
+        a = torch.randn(n, n, device=dev).to(dt)
+        b = torch.randn(n, n, device=dev).to(dt)
+        for _ in range(2):
+            a @ b
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        reps = 10
+        for _ in range(reps):
+            a @ b
+        torch.cuda.synchronize()
+        out["gemm_%s_TFLOPs" % name] = round(reps * 2.0 * n ** 3 / (time.perf_counter() - t0) / 1e12, 1)
+        del a, b
+    # the pass shapes themselves: 20000 x 15000 A times a 112-column skinny
+    # operand, both orientations (the library's FP32/FP64 passes do the same
+    # flops; FP64 here is FP32 data widened, as the F64 form reads an F64 A)
+    for name, dt in (("fp32", torch.float32), ("fp64", torch.float64)):
+        A = torch.randn(M, N, device=dev).to(dt)
+        X = torch.randn(N, 112, device=dev).to(dt)
+        Y = torch.randn(M, 112, device=dev).to(dt)
+        for lbl, f in (("AX", lambda: A @ X), ("AtY", lambda: A.t() @ Y)):
+            for _ in range(2):
+                f()
+            torch.cuda.synchronize()
+            t0 = time.perf_counter()
+            reps = 10
+            for _ in range(reps):
+                f()
+            torch.cuda.synchronize()
+            out["pass_%s_%s_TFLOPs" % (lbl, name)] = round(reps * 2.0 * M * N * 112 / (time.perf_counter() - t0)
+                                                          / 1e12, 1)
+        del A, X, Y
+    torch.cuda.empty_cache()
+    out["note"] = ("torch.sum over 4 GiB float32; torch.matmul 8192^3 and the 20000x15000 by 112 pass "
+                   "shapes (hipBLASLt)")
+    return out
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -216,6 +270,8 @@ def main():
     ap.add_argument("--no-serving", action="store_true")
     ap.add_argument("--copy-calibration", action="store_true",
                     help="only run 4 plain 1 GiB device copies (calibrates the HBM byte counters)")
+    ap.add_argument("--peaks", action="store_true",
+                    help="only measure achievable peaks with library kernels (HBM read, GEMM rates)")
     args = ap.parse_args()
     if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) != 1:
         print("bench.py measures one GPU only: this build has no multi-GPU path "
@@ -223,6 +279,10 @@ def main():
         sys.exit(2)
 
     import torch
+
+    if args.peaks:
+        print(json.dumps(achievable_peaks(torch)), flush=True)
+        return
 
     if args.copy_calibration:
         # 2^27 doubles = 1 GiB read and 1 GiB written per copy launch
