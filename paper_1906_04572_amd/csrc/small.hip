@@ -209,7 +209,7 @@ __global__ void __launch_bounds__(1024) reduce_kernel(const double* __restrict__
 }
 
 // ---------------------------------------------------------------------------
-// Y = X B (or column gather).  Block: 64 rows x 64 columns, 4 x 4 per thread.
+// Output helpers and the column gather Y[:, j] = X[:, perm[j]].
 __device__ __forceinline__ void store_out(const MatOut& o, int64_t i, int c, double v) {
   const int64_t off = o.layout == CORUTV_COL_MAJOR ? (int64_t)c * o.ld + i : i * o.ld + c;
   if (o.dtype == CORUTV_F64)
@@ -230,75 +230,25 @@ __device__ __forceinline__ void store_out_nt(const MatOut& o, int64_t i, int c, 
     __builtin_nontemporal_store((float)v, (float*)o.ptr + off);
 }
 
-__global__ void __launch_bounds__(256) rowmat_kernel(const double* __restrict__ X, int64_t ldx,
-                                                     int64_t rows, int ell, const double* __restrict__ B,
-                                                     int64_t ldb, const int32_t* __restrict__ perm,
-                                                     MatOut o1, int pad1, MatOut o2, int pad2,
-                                                     const int* skip, int run_val) {
+// One thread per row, one block row per output column: loads and column-major
+// stores both run along rows.
+__global__ void __launch_bounds__(256) gather_cols_kernel(const double* __restrict__ X, int64_t ldx,
+                                                          int64_t rows, int ell,
+                                                          const int32_t* __restrict__ perm, MatOut o1,
+                                                          int pad1, MatOut o2, int pad2, const int* skip,
+                                                          int run_val) {
   if (skip && *skip != run_val) return;
-  constexpr int KB = 32;
-  __shared__ double sx[64][KB + 1];
-  __shared__ double sbm[KB][64 + 1];
-  const int tid = threadIdx.x, ta = tid >> 4, tb = tid & 15;
-  const int64_t i0 = (int64_t)blockIdx.x * 64;
-  const int c0 = blockIdx.y * 64;
-  const int ellp = pad_ell(ell);
-  double acc[4][4];
-#pragma unroll
-  for (int i = 0; i < 4; ++i)
-#pragma unroll
-    for (int j = 0; j < 4; ++j) acc[i][j] = 0.0;
-  if (perm) {
-#pragma unroll
-    for (int i = 0; i < 4; ++i)
-#pragma unroll
-      for (int j = 0; j < 4; ++j) {
-        const int64_t r = i0 + ta + 16 * i;
-        const int c = c0 + tb + 16 * j;
-        if (r < rows && c < ell) acc[i][j] = X[(int64_t)perm[c] * ldx + r];
-      }
+  const int c = blockIdx.y;
+  const int64_t r = (int64_t)blockIdx.x * 256 + threadIdx.x;
+  if (r >= rows) return;
+  if (c < ell) {
+    const double v = X[(int64_t)perm[c] * ldx + r];
+    if (o1.ptr) store_out(o1, r, c, v);
+    if (o2.ptr) store_out(o2, r, c, v);
   } else {
-    for (int k0 = 0; k0 < ell; k0 += KB) {
-      for (int e = tid; e < 64 * KB; e += 256) {
-        const int r = e % 64, k = e / 64;
-        const int64_t row = i0 + r;
-        sx[r][k] = (row < rows && k0 + k < ell) ? X[(int64_t)(k0 + k) * ldx + row] : 0.0;
-      }
-      for (int e = tid; e < 64 * KB; e += 256) {
-        const int k = e % KB, c = e / KB;
-        sbm[k][c] = (k0 + k < ell && c0 + c < ell) ? B[(int64_t)(c0 + c) * ldb + k0 + k] : 0.0;
-      }
-      __syncthreads();
-#pragma unroll 8
-      for (int k = 0; k < KB; ++k) {
-        double xv[4], bv[4];
-#pragma unroll
-        for (int i = 0; i < 4; ++i) xv[i] = sx[ta + 16 * i][k];
-#pragma unroll
-        for (int j = 0; j < 4; ++j) bv[j] = sbm[k][tb + 16 * j];
-#pragma unroll
-        for (int i = 0; i < 4; ++i)
-#pragma unroll
-          for (int j = 0; j < 4; ++j) acc[i][j] = fma(xv[i], bv[j], acc[i][j]);
-      }
-      __syncthreads();
-    }
+    if (o1.ptr && pad1) store_out(o1, r, c, 0.0);
+    if (o2.ptr && pad2) store_out(o2, r, c, 0.0);
   }
-#pragma unroll
-  for (int i = 0; i < 4; ++i)
-#pragma unroll
-    for (int j = 0; j < 4; ++j) {
-      const int64_t r = i0 + ta + 16 * i;
-      const int c = c0 + tb + 16 * j;
-      if (r >= rows) continue;
-      if (c < ell) {
-        if (o1.ptr) store_out(o1, r, c, acc[i][j]);
-        if (o2.ptr) store_out(o2, r, c, acc[i][j]);
-      } else if (c < ellp) {
-        if (o1.ptr && pad1) store_out(o1, r, c, 0.0);
-        if (o2.ptr && pad2) store_out(o2, r, c, 0.0);
-      }
-    }
 }
 
 // Y = X B on FP64 matrix cores, computed as Y^T = B^T X^T so that the
@@ -982,9 +932,9 @@ hipError_t launch_rowmat(const double* X, int64_t ldx, int64_t rows, int ell, co
   if (rows == 0) return hipSuccess;
   const int ellp = pad_ell(ell);
   if (perm) {
-    const dim3 grid((unsigned)((rows + 63) / 64), (unsigned)((ellp + 63) / 64));
-    rowmat_kernel<<<grid, dim3(256), 0, st>>>(X, ldx, rows, ell, B, ldb, perm, o1, pad1, o2, pad2, skip,
-                                              run_val);
+    const dim3 grid((unsigned)((rows + 255) / 256), (unsigned)ellp);
+    gather_cols_kernel<<<grid, dim3(256), 0, st>>>(X, ldx, rows, ell, perm, o1, pad1, o2, pad2, skip,
+                                                   run_val);
   } else {
     const dim3 grid((unsigned)((rows + 31) / 32), (unsigned)((ellp + 127) / 128));
     rowmat_mfma_kernel<<<grid, dim3(256), 0, st>>>(X, ldx, rows, ell, B, ldb, o1, pad1, o2, pad2,
