@@ -85,6 +85,9 @@ typedef struct corutv_opts {
   int32_t want_err;  /* nonzero: compute ||A - U T V^T||_F / ||A||_F (one    */
                      /* extra pass over A, not part of the method)           */
   int32_t flags;     /* CORUTV_FLAG_* bits; other bits must be 0             */
+  int32_t panel_rows; /* CORUTV_FLAG_A_HOST: storage rows of A per staged    */
+                      /* panel (rows if ROW_MAJOR, columns if COL_MAJOR);    */
+                      /* 0 selects 4096. Ignored otherwise                   */
 } corutv_opts;
 
 /* corutv_opts.flags: form the core from the R factor of the second sketch
@@ -96,6 +99,16 @@ typedef struct corutv_opts {
  * Algorithm 1): since Q1^T A = R_Z^T Q2^T, that expression equals R_Z^T
  * whenever Q2^T Psi has full rank. */
 #define CORUTV_FLAG_CORE_FROM_RZ 1
+/* corutv_opts.flags: A->ptr is a host pointer.  The method only reads A in
+ * whole passes (Sec. 3.1 counts its cost in passes over data stored
+ * externally), so each pass streams A through the device in panels of
+ * panel_rows storage rows, two staging panels in the workspace, the copy of
+ * one panel overlapping the products of the other.  Pinned host memory
+ * (hipHostMalloc) is needed for the overlap; pageable memory works, slower.
+ * F64 and F32 forms only, want_err must be 0, blocking corutv_decompose
+ * only (not the serving queue).  The workspace must hold the staging panels:
+ * size it with corutv_workspace_bytes_host. */
+#define CORUTV_FLAG_A_HOST 2
 
 typedef struct corutv_info {
   double rel_err;        /* relative Frobenius error if want_err, else -1       */
@@ -135,6 +148,12 @@ int corutv_destroy(corutv_ctx* ctx);
 /* Workspace bytes one decomposition of an m x n matrix needs (closed form,
  * independent of the data).  Returns 0 for invalid sizes. */
 uint64_t corutv_workspace_bytes(int64_t m, int64_t n, int32_t k, int32_t p, int32_t q, int32_t prec);
+/* Workspace for corutv_decompose with CORUTV_FLAG_A_HOST: the bytes of
+ * corutv_workspace_bytes plus two staging panels of panel_rows (0: 4096)
+ * storage rows of an m x n A of the given layout (enum corutv_layout) in the
+ * dtype of prec.  Returns 0 for invalid arguments or a BF16 form. */
+uint64_t corutv_workspace_bytes_host(int64_t m, int64_t n, int32_t k, int32_t p, int32_t q, int32_t prec,
+                                     int32_t layout, int32_t panel_rows);
 
 /* Rank-l CoR-UTV of A (Sec. 3.1, eqs. 4-9; Algorithm 1 with q power steps).
  *   A     m x n, F64 or F32 as opts->prec requires, either layout; read only.

@@ -16,6 +16,7 @@ LIB_PATH = os.path.join(_HERE, "libcorutv.so")
 OK, PENDING = 0, 1
 E_INVAL, E_NOMEM, E_BUSY, E_NUMERIC, E_DEVICE, E_NOTFOUND = -1, -2, -3, -4, -5, -6
 FLAG_CORE_FROM_RZ = 1  # core D = R_Z^T (2q + 2 passes)
+FLAG_A_HOST = 2  # A in host memory, streamed through the device in panels
 CORE = {"pass": 0, "rz": FLAG_CORE_FROM_RZ}
 F64, F32 = 0, 1
 COL_MAJOR, ROW_MAJOR = 0, 1
@@ -37,7 +38,7 @@ class Mat(ctypes.Structure):
 
 class Opts(ctypes.Structure):
     _fields_ = [("prec", ctypes.c_int32), ("tri", ctypes.c_int32), ("want_err", ctypes.c_int32),
-                ("flags", ctypes.c_int32)]
+                ("flags", ctypes.c_int32), ("panel_rows", ctypes.c_int32)]
 
 
 class Info(ctypes.Structure):
@@ -87,6 +88,7 @@ def _load():
         "corutv_create": (ctypes.c_int, [ctypes.POINTER(P), ctypes.POINTER(Config)]),
         "corutv_destroy": (ctypes.c_int, [P]),
         "corutv_workspace_bytes": (U64, [I64, I64, I32, I32, I32, I32]),
+        "corutv_workspace_bytes_host": (U64, [I64, I64, I32, I32, I32, I32, I32, I32]),
         "corutv_decompose": (ctypes.c_int, [P, MP, I32, I32, I32, U64, ctypes.POINTER(Opts), MP, P, I64,
                                             MP, P, ctypes.POINTER(Info)]),
         "corutv_rpca": (ctypes.c_int, [P, MP, D, I32, I32, I32, I32, D, U64, ctypes.POINTER(Opts), MP, MP,
@@ -124,11 +126,11 @@ def _check(rc, what=""):
     return rc
 
 
-def mat(t):
+def mat(t, host=False):
     """Descriptor of a 2-D CUDA tensor (row-major contiguous or a transposed
-    view of one, i.e. column-major)."""
-    if t.dim() != 2 or not t.is_cuda:
-        raise ValueError("expected a 2-D device tensor")
+    view of one, i.e. column-major); host=True takes a CPU tensor instead."""
+    if t.dim() != 2 or t.is_cuda == host:
+        raise ValueError("expected a 2-D %s tensor" % ("host" if host else "device"))
     dt = {torch.float64: F64, torch.float32: F32}.get(t.dtype)
     if dt is None:
         raise ValueError("dtype must be float64 or float32")
@@ -143,6 +145,12 @@ def mat(t):
 
 def workspace_bytes(m, n, k, p, q, prec="f64"):
     return int(lib.corutv_workspace_bytes(m, n, k, p, q, PREC[prec]))
+
+
+def workspace_bytes_host(m, n, k, p, q, prec="f64", layout="row", panel_rows=0):
+    """Workspace for a host-resident A (two staging panels included)."""
+    return int(lib.corutv_workspace_bytes_host(m, n, k, p, q, PREC[prec],
+                                               ROW_MAJOR if layout == "row" else COL_MAJOR, panel_rows))
 
 
 def rpca_workspace_bytes(m, n, k, p, q):
@@ -187,25 +195,31 @@ class Context:
         m, n = A.shape
         ell = k + p
         dt = dtype or A.dtype
+        dev = self.device
         if layout == "col":
-            U = torch.zeros((ell, m), dtype=dt, device=A.device).t()
-            V = torch.zeros((ell, n), dtype=dt, device=A.device).t()
+            U = torch.zeros((ell, m), dtype=dt, device=dev).t()
+            V = torch.zeros((ell, n), dtype=dt, device=dev).t()
         else:
-            U = torch.zeros((m, ell), dtype=dt, device=A.device)
-            V = torch.zeros((n, ell), dtype=dt, device=A.device)
-        T = torch.zeros((ell, ell), dtype=torch.float64, device=A.device).t()  # column-major
-        piv = torch.zeros(ell, dtype=torch.int32, device=A.device)
+            U = torch.zeros((m, ell), dtype=dt, device=dev)
+            V = torch.zeros((n, ell), dtype=dt, device=dev)
+        T = torch.zeros((ell, ell), dtype=torch.float64, device=dev).t()  # column-major
+        piv = torch.zeros(ell, dtype=torch.int32, device=dev)
         return U, T, V, piv
 
-    def decompose(self, A, k, p, q, seed, prec="f64", tri="auto", want_err=False, out=None, core="pass"):
+    def decompose(self, A, k, p, q, seed, prec="f64", tri="auto", want_err=False, out=None, core="pass",
+                  panel_rows=0):
         """Returns (U, T, V, piv, info dict).  core: "pass" (D = Q1^T (A Q2)) or
-        "rz" (D = R_Z^T from the QR of the second sketch, one pass fewer)."""
+        "rz" (D = R_Z^T from the QR of the second sketch, one pass fewer).
+        A CPU tensor A (pinned for overlap) is streamed through the device in
+        panels of panel_rows storage rows (0: the library default)."""
         U, T, V, piv = out if out is not None else self.alloc_outputs(A, k, p)
         ell = k + p
         info = Info()
-        opts = Opts(PREC[prec], TRI[tri], 1 if want_err else 0, CORE[core])
+        host = not A.is_cuda
+        opts = Opts(PREC[prec], TRI[tri], 1 if want_err else 0, CORE[core] | (FLAG_A_HOST if host else 0),
+                    panel_rows)
         mu, mv = mat(U), mat(V)
-        rc = lib.corutv_decompose(self.h, ctypes.byref(mat(A)), k, p, q, seed, ctypes.byref(opts),
+        rc = lib.corutv_decompose(self.h, ctypes.byref(mat(A, host)), k, p, q, seed, ctypes.byref(opts),
                                   ctypes.byref(mu), T.data_ptr(), ell, ctypes.byref(mv), piv.data_ptr(),
                                   ctypes.byref(info))
         _check(rc, "decompose")
@@ -213,13 +227,16 @@ class Context:
         d["tri"] = TRI_NAME.get(d["tri"], d["tri"])
         return U, T, V, piv, d
 
-    def decompose_rc(self, A, k, p, q, seed, prec="f64", tri="auto", want_err=False, out=None, core="pass"):
+    def decompose_rc(self, A, k, p, q, seed, prec="f64", tri="auto", want_err=False, out=None, core="pass",
+                     panel_rows=0):
         """Like decompose but returns the status code instead of raising."""
         U, T, V, piv = out if out is not None else self.alloc_outputs(A, k, p)
         info = Info()
-        opts = Opts(PREC[prec], TRI[tri], 1 if want_err else 0, CORE[core])
+        host = not A.is_cuda
+        opts = Opts(PREC[prec], TRI[tri], 1 if want_err else 0, CORE[core] | (FLAG_A_HOST if host else 0),
+                    panel_rows)
         mu, mv = mat(U), mat(V)
-        return lib.corutv_decompose(self.h, ctypes.byref(mat(A)), k, p, q, seed, ctypes.byref(opts),
+        return lib.corutv_decompose(self.h, ctypes.byref(mat(A, host)), k, p, q, seed, ctypes.byref(opts),
                                     ctypes.byref(mu), T.data_ptr(), k + p, ctypes.byref(mv),
                                     piv.data_ptr(), ctypes.byref(info))
 

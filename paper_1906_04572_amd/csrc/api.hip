@@ -41,7 +41,10 @@ struct Plan {
   // byte offsets
   size_t o_wop = 0, o_qop = 0, o_part = 0, o_x0 = 0, o_x1 = 0, o_q1 = 0, o_q2 = 0, o_xp = 0,
          o_g = 0, o_r = 0, o_rinv = 0, o_core = 0, o_qt = 0, o_rt = 0, o_qw = 0, o_tt = 0,
-         o_piv = 0, o_st = 0, o_res = 0, o_sum = 0, o_cw = 0, o_sbf = 0;
+         o_piv = 0, o_st = 0, o_res = 0, o_sum = 0, o_cw = 0, o_sbf = 0, o_stage = 0;
+  // host-resident A: panels of panel_rows storage rows, stage_ld elements each
+  int64_t panel_rows = 0, stage_ld = 0;
+  size_t stage_bytes = 0;  // one staging panel
   size_t total = 0;
 };
 
@@ -101,6 +104,21 @@ bool make_plan(int64_t m, int64_t n, int k, int p, int q, int prec, Plan* pl) {
   return true;
 }
 
+constexpr int kDefaultPanelRows = 4096;
+
+// Add two staging panels for a host-resident A (storage rows of srow_len
+// elements of es bytes; rows padded to 16 bytes so the passes can use vector
+// loads).
+bool plan_host_stages(int64_t nrows, int64_t srow_len, int es, int panel_rows, Plan* pl) {
+  if (panel_rows < 0 || nrows < 1 || srow_len < 1) return false;
+  pl->panel_rows = std::min<int64_t>(panel_rows ? panel_rows : kDefaultPanelRows, nrows);
+  pl->stage_ld = round_up(srow_len, 16 / es);
+  pl->stage_bytes = align256((size_t)pl->panel_rows * pl->stage_ld * es);
+  pl->o_stage = pl->total;
+  pl->total += 2 * pl->stage_bytes;
+  return true;
+}
+
 }  // namespace
 
 // ---------------------------------------------------------------------------
@@ -133,6 +151,9 @@ struct corutv_ctx {
   std::vector<hipEvent_t> ev_pool;
   int64_t t_passes = 0;
   double t_total = 0, t_min = 1e300, t_max = 0;
+  // host-resident A: copy stream and its events (created on first use)
+  hipStream_t copy_stream = nullptr;
+  hipEvent_t stage_ev[5] = {};  // ready[2], free[2], start
 };
 
 namespace {
@@ -185,7 +206,11 @@ int validate(const DecArgs& d) {
   if (prec == P_F64 && d.A.dtype != CORUTV_F64) return CORUTV_E_INVAL;
   if (prec != P_F64 && d.A.dtype != CORUTV_F32) return CORUTV_E_INVAL;
   if (d.opts.tri < CORUTV_TRI_AUTO || d.opts.tri > CORUTV_TRI_LOWER) return CORUTV_E_INVAL;
-  if ((uint32_t)d.opts.flags & ~(uint32_t)CORUTV_FLAG_CORE_FROM_RZ) return CORUTV_E_INVAL;
+  if ((uint32_t)d.opts.flags & ~(uint32_t)(CORUTV_FLAG_CORE_FROM_RZ | CORUTV_FLAG_A_HOST)) return CORUTV_E_INVAL;
+  if (d.opts.flags & CORUTV_FLAG_A_HOST) {
+    if (prec != P_F64 && prec != P_F32) return CORUTV_E_INVAL;
+    if (d.opts.want_err || d.opts.panel_rows < 0) return CORUTV_E_INVAL;
+  }
   return CORUTV_OK;
 }
 
@@ -201,13 +226,12 @@ struct Enqueued {
 // Thin QR of the sketch held in the stream-K partials `pp` (rows x ell):
 // CholeskyQR2 with FP64 Gram and Cholesky, Householder after a breakdown.
 // Outputs: q64 (FP64, may be scratch) and, for the F32 path, q32.
-// Thin QR of the sketch held as pass partials: CholeskyQR2 with FP64 Gram
-// matrices.  one_step: the first Cholesky may decide (status 4) that a
-// second step is not needed; then Q = X R1^-1 goes straight to the outputs
-// and the kernels of the second step return at once.
+// one_step: the first Cholesky may decide (status 4) that a second step is
+// not needed; then Q = X R1^-1 goes straight to the outputs and the kernels
+// of the second step return at once.
 hipError_t qr_from_partials(const Plan& pl, char* ws, const Partials& pp, int64_t rows, int64_t ld,
                             double* q64, float* q32, int* st, hipStream_t s, double* rfac = nullptr,
-                            bool one_step = false) {
+                            bool one_step = false, bool summed = false) {
   const int ell = pl.ell;
   double* x0 = (double*)(ws + pl.o_x0);
   double* x1 = (double*)(ws + pl.o_x1);
@@ -219,7 +243,8 @@ hipError_t qr_from_partials(const Plan& pl, char* ws, const Partials& pp, int64_
   const int64_t l2 = (int64_t)ell * ell;
   const int splits = xty_splits(rows, ell);
   hipError_t e;
-  if ((e = launch_sum_partials(pp, ell, pl.ellp, x0, nullptr, ld, s)) != hipSuccess) return e;
+  // summed: the sketch is already in x0 (passes over a host-resident A)
+  if (!summed && (e = launch_sum_partials(pp, ell, pl.ellp, x0, nullptr, ld, s)) != hipSuccess) return e;
   if ((e = launch_xty(x0, ld, x0, ld, rows, ell, xp, splits, nullptr, s)) != hipSuccess) return e;
   if ((e = launch_reduce(xp, splits, l2, G, nullptr, s)) != hipSuccess) return e;
   if ((e = launch_chol(G, ell, R, Ri, st, nullptr, cw, s, one_step ? kOneStepThr : 0.0)) != hipSuccess)
@@ -306,17 +331,61 @@ int enqueue_decompose(corutv_ctx* ctx, const Plan& pl, char* ws, const DecArgs& 
   auto mark = [&]() {
     if (pass_ev && evi < pass_ev->size()) hipEventRecord((*pass_ev)[evi++], s);
   };
+  // Host-resident A: the big row-major view (Rb x Cb, pitch d.A.ld) goes
+  // through two staging panels of pl.panel_rows rows.  A pass contracting
+  // over Cb (trans 0) yields the rows of each panel's output directly; one
+  // contracting over Rb (trans 1) adds the panels' products, in panel order.
+  // The result lands summed in x0 (ld ldout); x1 holds a panel's product.
+  const bool host_a = (d.opts.flags & CORUTV_FLAG_A_HOST) != 0;
+  auto stream_pass = [&](int trans, const void* opnd, int64_t ldo, int64_t ldout) -> hipError_t {
+    hipStream_t cs = ctx->copy_stream;
+    hipEvent_t* ev = ctx->stage_ev;
+    char* stage[2] = {ws + pl.o_stage, ws + pl.o_stage + pl.stage_bytes};
+    const int64_t pr = pl.panel_rows, np = (Rb + pr - 1) / pr;
+    hipError_t e;
+    // the staging panels are free once everything queued so far has run
+    if ((e = hipEventRecord(ev[4], s)) != hipSuccess || (e = hipStreamWaitEvent(cs, ev[4], 0)) != hipSuccess)
+      return e;
+    for (int64_t pi = 0; pi < np; ++pi) {
+      const int b = (int)(pi & 1);
+      const int64_t r0 = pi * pr, nr = std::min(pr, Rb - r0);
+      if (pi >= 2 && (e = hipStreamWaitEvent(cs, ev[2 + b], 0)) != hipSuccess) return e;
+      if ((e = hipMemcpy2DAsync(stage[b], (size_t)pl.stage_ld * es, (const char*)d.A.ptr + (size_t)r0 * d.A.ld * es,
+                                (size_t)d.A.ld * es, (size_t)Cb * es, (size_t)nr, hipMemcpyHostToDevice, cs)) !=
+          hipSuccess)
+        return e;
+      if ((e = hipEventRecord(ev[b], cs)) != hipSuccess || (e = hipStreamWaitEvent(s, ev[b], 0)) != hipSuccess)
+        return e;
+      if (trans == 0) {
+        if ((e = launch_sketch(prec, 0, stage[b], pl.stage_ld, nr, Cb, opnd, ldo, ellp, part, pl.part_elems, &pp,
+                               ctx->num_cu, s, nullptr)) != hipSuccess ||
+            (e = launch_sum_partials(pp, ell, ellp, x0 + r0, nullptr, ldout, s)) != hipSuccess)
+          return e;
+      } else {
+        const void* o = (const char*)opnd + (size_t)r0 * es;  // skinny rows r0..
+        if ((e = launch_sketch(prec, 1, stage[b], pl.stage_ld, nr, Cb, o, ldo, ellp, part, pl.part_elems, &pp,
+                               ctx->num_cu, s, nullptr)) != hipSuccess ||
+            (e = launch_sum_partials(pp, ell, ellp, pi == 0 ? x0 : x1, nullptr, ldout, s)) != hipSuccess)
+          return e;
+        if (pi > 0 && (e = launch_add_cols(x0, x1, Cb, ellp, ldout, s)) != hipSuccess) return e;
+      }
+      if ((e = hipEventRecord(ev[2 + b], s)) != hipSuccess) return e;
+    }
+    return hipSuccess;
+  };
   auto passA = [&](const void* opnd) {  // P X, X nn x ell -> mm x ell
     mark();
-    hipError_t e = launch_sketch(prec, tA, d.A.ptr, d.A.ld, Rb, Cb, opnd, ldn, ellp, part,
-                                 pl.part_elems, &pp, ctx->num_cu, s, ws + pl.o_sbf);
+    hipError_t e = host_a ? stream_pass(tA, opnd, ldn, ldm)
+                          : launch_sketch(prec, tA, d.A.ptr, d.A.ld, Rb, Cb, opnd, ldn, ellp, part,
+                                          pl.part_elems, &pp, ctx->num_cu, s, ws + pl.o_sbf);
     mark();
     return e;
   };
   auto passAt = [&](const void* opnd) {  // P^T Y, Y mm x ell -> nn x ell
     mark();
-    hipError_t e = launch_sketch(prec, tAt, d.A.ptr, d.A.ld, Rb, Cb, opnd, ldm, ellp, part,
-                                 pl.part_elems, &pp, ctx->num_cu, s, ws + pl.o_sbf);
+    hipError_t e = host_a ? stream_pass(tAt, opnd, ldm, ldn)
+                          : launch_sketch(prec, tAt, d.A.ptr, d.A.ld, Rb, Cb, opnd, ldm, ellp, part,
+                                          pl.part_elems, &pp, ctx->num_cu, s, ws + pl.o_sbf);
     mark();
     return e;
   };
@@ -324,19 +393,22 @@ int enqueue_decompose(corutv_ctx* ctx, const Plan& pl, char* ws, const DecArgs& 
   HIPOK(launch_omega(nn, ell, ellp, d.seed, d.sub, f64 ? (double*)wop : nullptr,
                      f64 ? nullptr : (float*)wop, ldn, s));
   HIPOK(passA(wop));
-  HIPOK(qr_from_partials(pl, ws, pp, mm, ldm, q1, f64 ? nullptr : (float*)qop, st + nqr++, s, nullptr, !f64));
+  HIPOK(qr_from_partials(pl, ws, pp, mm, ldm, q1, f64 ? nullptr : (float*)qop, st + nqr++, s, nullptr, !f64,
+                         host_a));
   for (int it = 0; it < d.q; ++it) {
     // W = qf(P^T Q1); Q1 = qf(P W)
     HIPOK(passAt(qsrc));
-    HIPOK(qr_from_partials(pl, ws, pp, nn, ldn, q2, f64 ? nullptr : (float*)wop, st + nqr++, s, nullptr, !f64));
+    HIPOK(qr_from_partials(pl, ws, pp, nn, ldn, q2, f64 ? nullptr : (float*)wop, st + nqr++, s, nullptr, !f64,
+                           host_a));
     HIPOK(passA(wsrc));
-    HIPOK(qr_from_partials(pl, ws, pp, mm, ldm, q1, f64 ? nullptr : (float*)qop, st + nqr++, s, nullptr, !f64));
+    HIPOK(qr_from_partials(pl, ws, pp, mm, ldm, q1, f64 ? nullptr : (float*)qop, st + nqr++, s, nullptr, !f64,
+                         host_a));
   }
   // Z = P^T Q1; Q2, R_Z = qf(Z)
   const bool core_rz = (d.opts.flags & CORUTV_FLAG_CORE_FROM_RZ) != 0;
   HIPOK(passAt(qsrc));
   HIPOK(qr_from_partials(pl, ws, pp, nn, ldn, q2, f64 ? nullptr : (float*)wop, st + nqr++, s,
-                         core_rz ? core : nullptr, !f64));
+                         core_rz ? core : nullptr, !f64, host_a));
   if (core_rz) {
     // D = Q1^T P Q2 = R_Z^T (Q2 R_Z = Z = P^T Q1): no pass over A; the
     // QRCP of D reads R_Z transposed, the QRCP of D^T reads R_Z as is
@@ -344,7 +416,7 @@ int enqueue_decompose(corutv_ctx* ctx, const Plan& pl, char* ws, const DecArgs& 
   } else {
     // core D = Q1^T (P Q2)
     HIPOK(passA(wsrc));
-    HIPOK(launch_sum_partials(pp, ell, ellp, x0, nullptr, ldm, s));
+    if (!host_a) HIPOK(launch_sum_partials(pp, ell, ellp, x0, nullptr, ldm, s));
     const int sp = xty_splits(mm, ell);
     HIPOK(launch_xty(q1, ldm, x0, ldm, mm, ell, xp, sp, nullptr, s));
     HIPOK(launch_reduce(xp, sp, (int64_t)ell * ell, core, nullptr, s));
@@ -473,6 +545,17 @@ uint64_t corutv_workspace_bytes(int64_t m, int64_t n, int32_t k, int32_t p, int3
   return pl.total;
 }
 
+uint64_t corutv_workspace_bytes_host(int64_t m, int64_t n, int32_t k, int32_t p, int32_t q, int32_t prec,
+                                     int32_t layout, int32_t panel_rows) {
+  if (prec != P_F64 && prec != P_F32) return 0;
+  if (layout != CORUTV_COL_MAJOR && layout != CORUTV_ROW_MAJOR) return 0;
+  Plan pl;
+  if (!make_plan(m, n, k, p, q, prec, &pl)) return 0;
+  const bool col = layout == CORUTV_COL_MAJOR;
+  if (!plan_host_stages(col ? n : m, col ? m : n, prec == P_F64 ? 8 : 4, panel_rows, &pl)) return 0;
+  return pl.total;
+}
+
 int corutv_create(corutv_ctx** out, const corutv_config* cfg) {
   if (!out || !cfg) return CORUTV_E_INVAL;
   *out = nullptr;
@@ -524,9 +607,21 @@ int corutv_decompose(corutv_ctx* ctx, const corutv_mat* A, int32_t k, int32_t p,
   if ((rc = validate(d)) != CORUTV_OK) return rc;
   Plan pl;
   if (!make_plan(A->rows, A->cols, k, p, q, opts->prec, &pl)) return CORUTV_E_INVAL;
+  const bool host_a = (opts->flags & CORUTV_FLAG_A_HOST) != 0;
+  if (host_a) {
+    const bool col = A->layout == CORUTV_COL_MAJOR;
+    if (!plan_host_stages(col ? A->cols : A->rows, col ? A->rows : A->cols, opts->prec == P_F64 ? 8 : 4,
+                          opts->panel_rows, &pl))
+      return CORUTV_E_INVAL;
+  }
   if (pl.total > ctx->ws_bytes) return CORUTV_E_NOMEM;
   std::lock_guard<std::mutex> lk(ctx->run_mu);
   hipStream_t s = ctx->streams[0];
+  if (host_a && !ctx->copy_stream) {
+    if (hipStreamCreateWithFlags(&ctx->copy_stream, hipStreamNonBlocking) != hipSuccess) return poison(ctx);
+    for (hipEvent_t& e : ctx->stage_ev)
+      if (hipEventCreateWithFlags(&e, hipEventDisableTiming) != hipSuccess) return poison(ctx);
+  }
   hipEvent_t e0, e1;
   if (hipEventCreate(&e0) != hipSuccess || hipEventCreate(&e1) != hipSuccess) return poison(ctx);
   hipEventRecord(e0, s);
@@ -889,6 +984,10 @@ int corutv_submit(corutv_ctx* ctx, const corutv_request* req, uint64_t* ticket) 
   j->d.q = req->q;
   j->d.seed = req->seed;
   j->d.opts = req->opts;
+  if (req->opts.flags & CORUTV_FLAG_A_HOST) {  // blocking corutv_decompose only
+    delete j;
+    return CORUTV_E_INVAL;
+  }
   if ((rc = validate(j->d)) != CORUTV_OK ||
       !make_plan(req->A.rows, req->A.cols, req->k, req->p, req->q, req->opts.prec, &j->pl)) {
     delete j;
@@ -993,6 +1092,12 @@ int corutv_destroy(corutv_ctx* ctx) {
   ctx->jobs.clear();
   if (ctx->host_status) hipHostFree(ctx->host_status);
   for (hipEvent_t e : ctx->ev_pool) hipEventDestroy(e);
+  if (ctx->copy_stream) {
+    hipStreamSynchronize(ctx->copy_stream);
+    for (hipEvent_t e : ctx->stage_ev)
+      if (e) hipEventDestroy(e);
+    hipStreamDestroy(ctx->copy_stream);
+  }
   delete ctx;
   return CORUTV_OK;
 }

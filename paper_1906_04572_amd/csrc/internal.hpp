@@ -55,6 +55,9 @@ inline size_t sketch_bf16_bytes(int ellp, int64_t lds) { return 2 * (size_t)ellp
 // 256-CU device.
 int64_t partials_capacity(int64_t n_out, int64_t k_len, int ellp, int prec);
 
+// y[c*ld + i] += x[c*ld + i] for i < rows, c < cols (FP64, column-major).
+hipError_t launch_add_cols(double* y, const double* x, int64_t rows, int cols, int64_t ld, hipStream_t st);
+
 // out64[c*ld + i] = sum of the partial tiles for row i (i < n, c < ell); zero for
 // ell <= c < ncols.  Optionally also out32 (float copy).
 hipError_t launch_sum_partials(const Partials& p, int ell, int ncols, double* out64, float* out32,

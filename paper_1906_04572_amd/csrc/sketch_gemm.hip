@@ -158,8 +158,8 @@ __global__ void __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(sizeof
 #pragma unroll
               for (int e = 0; e < 4; ++e) mask |= (uint32_t)(nok && k + e < a.K) << (base + e);
               if constexpr (VEC) {
-                // rows are 16-byte aligned and lda is a multiple of 4, so the
-                // 4-vector at k < K stays inside the row's allocation
+                // rows are 16-byte aligned and K (the row length) is a
+                // multiple of 4, so the 4-vector at k < K stays in the row
                 const T* src = A + nc * a.lda + (k < a.K ? k : 0);
                 if constexpr (sizeof(T) == 4) {
                   const f4 vv = *(const f4*)src;
@@ -189,8 +189,8 @@ __global__ void __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(sizeof
 #pragma unroll
               for (int e = 0; e < NB; ++e) mask |= (uint32_t)(kok && n0 + e < a.N) << (base + e);
               if constexpr (NB == 2 && VEC) {
-                // n0 is even and lda a multiple of 4: the pair at n0 < N is
-                // inside the row's allocation
+                // n0 is even and N (the row length) a multiple of 4: the
+                // pair at n0 < N stays in the row
                 const T* src = A + kc * a.lda + (n0 < a.N ? n0 : 0);
                 if constexpr (sizeof(T) == 4) {
                   const f2 vv = *(const f2*)src;
@@ -385,7 +385,7 @@ __global__ void __launch_bounds__(256) sketch_bf16_kernel(SketchArgs a) {
 #pragma unroll
               for (int e = 0; e < 8; ++e) mask |= (uint32_t)(nok && k + e < a.K) << (base + e);
               if constexpr (VEC) {
-                // lda is a multiple of 4; the second 4-vector is clamped
+                // K is a multiple of 4: both 4-vectors at k < K stay in the row
                 const float* src = A + nc * a.lda + (k < a.K ? k : 0);
                 const f4 v0 = *(const f4*)src;
                 const int64_t k2 = k + 4 < a.K ? k + 4 : (k < a.K ? k : 0);
@@ -626,7 +626,10 @@ hipError_t launch_sketch(int prec, int trans, const void* A, int64_t lda, int64_
   const bool f64 = prec == P_F64;
   const int mb = ellp / 16;
   const int elem = f64 ? 8 : 4;
-  const bool vec = (((uintptr_t)A) % 16 == 0) && ((lda * elem) % 16 == 0);
+  // Vector loads read whole 16-byte groups (4 floats, or 2 + 2 doubles) from
+  // a clamped start inside the row: a row length that is a multiple of 4
+  // keeps the last group of the last row inside the matrix.
+  const bool vec = (((uintptr_t)A) % 16 == 0) && ((lda * elem) % 16 == 0) && (C % 4 == 0);
   void* fn = nullptr;
   if (prec == P_F64)
     fn = vec ? (trans ? pick<double, true, true>(mb) : pick<double, false, true>(mb))

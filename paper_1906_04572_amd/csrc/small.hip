@@ -6,6 +6,7 @@
 // All arithmetic here is FP64.  Skinny matrices (rows x l) are column-major.
 // Reductions over rows are split into a fixed number of row blocks whose
 // partial sums are added in block order, so results are deterministic.
+#include <algorithm>
 #include <cmath>
 
 #include "internal.hpp"
@@ -854,6 +855,14 @@ __global__ void __launch_bounds__(256) residual_kernel(const TA* __restrict__ A,
   }
 }
 
+// y[c * ld + i] += x[c * ld + i] for i < rows, c < cols
+__global__ void add_cols_kernel(double* __restrict__ y, const double* __restrict__ x, int64_t rows, int cols,
+                                int64_t ld) {
+  const int c = blockIdx.y;
+  for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < rows; i += (int64_t)gridDim.x * blockDim.x)
+    y[(int64_t)c * ld + i] += x[(int64_t)c * ld + i];
+}
+
 __global__ void fill_int_kernel(int* p, int n, int v) {
   const int i = blockIdx.x * blockDim.x + threadIdx.x;
   if (i < n) p[i] = v;
@@ -881,6 +890,13 @@ __global__ void __launch_bounds__(256) trprod_kernel(const double* __restrict__ 
 }
 
 }  // namespace
+
+hipError_t launch_add_cols(double* y, const double* x, int64_t rows, int cols, int64_t ld, hipStream_t st) {
+  if (rows == 0 || cols == 0) return hipSuccess;
+  const int64_t bx = std::min<int64_t>((rows + 255) / 256, 64);
+  add_cols_kernel<<<dim3((unsigned)bx, (unsigned)cols), dim3(256), 0, st>>>(y, x, rows, cols, ld);
+  return hipGetLastError();
+}
 
 hipError_t launch_trprod(const double* R2, const double* R1, int ell, double* R, const int* status,
                          hipStream_t st) {

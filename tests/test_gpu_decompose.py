@@ -329,6 +329,63 @@ def test_single_revisit_core_against_oracle(ctx, q, prec):
         assert abs(info["rel_err"] - e_ref) <= 1e-5
 
 
+def _host(A, layout):
+    """Pinned host copy of A in the given storage order."""
+    if layout == "row":
+        return torch.from_numpy(np.ascontiguousarray(A)).pin_memory()
+    return torch.from_numpy(np.ascontiguousarray(A.T)).pin_memory().t()
+
+
+@pytest.mark.parametrize("m,n,layout,prec,q,panel", [
+    (1200, 900, "row", "f64", 1, 257),   # five panels, the last one ragged
+    (1200, 900, "col", "f64", 1, 200),   # column-major storage: panels of columns
+    (900, 1200, "row", "f64", 2, 300),   # wide: the method runs on A^T
+    (1037, 613, "col", "f64", 0, 613),   # one panel
+    (1500, 1100, "row", "f32", 1, 400),
+    (1100, 1500, "col", "f32", 1, 256),
+])
+def test_host_resident_a_against_oracle(ctx, m, n, layout, prec, q, panel):
+    """A in pinned host memory, streamed through the device panel by panel
+    in every pass: the factors match the oracle (F64: e and A_hat to 1e-10,
+    leading pivots; F32: |de| <= 1e-5) and the device-resident run."""
+    _say("host A", m, n, layout, prec, q, panel)
+    k, p = 20, 10
+    dt = np.float64 if prec == "f64" else np.float32
+    A = decaying(m, n, min(m, n) // 2, 1e-4, seed=m + n + q, kind="exp", tau=8.0).astype(dt)
+    A64 = A.astype(np.float64)
+    U, T, V, piv, info = ctx.decompose(_host(A, layout), k, p, q, 5, prec=prec, panel_rows=panel)
+    U, T, V, piv = (U.cpu().numpy().astype(np.float64), T.cpu().numpy(), V.cpu().numpy().astype(np.float64),
+                    piv.cpu().numpy())
+    assert info["passes"] == 2 * q + 3
+    ref = corutv(A64, k, p, q, seed=5)
+    e_ref = rel_err(A64, ref["U"], ref["T"], ref["V"])
+    e_gpu = rel_err(A64, U, T, V)
+    Ad = ctx.decompose(_dev(A, layout), k, p, q, 5, prec=prec)
+    Ah_dev = Ad[0].cpu().numpy().astype(np.float64) @ Ad[1].cpu().numpy() @ Ad[2].cpu().numpy().astype(np.float64).T
+    nA = np.linalg.norm(A64)
+    if prec == "f64":
+        assert abs(e_gpu - e_ref) <= 1e-10
+        assert np.linalg.norm(U @ T @ V.T - ref["U"] @ ref["T"] @ ref["V"].T) <= 1e-10 * nA
+        np.testing.assert_array_equal(piv[:k], ref["piv"][:k])
+        assert np.linalg.norm(U @ T @ V.T - Ah_dev) <= 1e-12 * nA
+    else:
+        assert abs(e_gpu - e_ref) <= 1e-5
+        assert np.linalg.norm(U @ T @ V.T - Ah_dev) <= 1e-5 * nA
+
+
+def test_host_resident_a_rejects_what_it_does_not_support(ctx):
+    import paper_1906_04572_amd as cu
+
+    A = decaying(600, 400, 100, 1e-4, seed=3, kind="exp", tau=8.0).astype(np.float32)
+    Ah = _host(A, "row")
+    assert ctx.decompose_rc(Ah, 10, 5, 1, 1, prec="bf16x3") == cu.E_INVAL
+    assert ctx.decompose_rc(Ah, 10, 5, 1, 1, prec="f32", want_err=True) == cu.E_INVAL
+    assert ctx.decompose_rc(Ah, 10, 5, 1, 1, prec="f32", panel_rows=-1) == cu.E_INVAL
+    assert cu.workspace_bytes_host(600, 400, 10, 5, 1, "bf16") == 0
+    assert cu.workspace_bytes_host(600, 400, 10, 5, 1, "f32", "row", 100) > cu.workspace_bytes(600, 400, 10, 5, 1,
+                                                                                                 "f32")
+
+
 def test_core_from_rz_after_cholesky_breakdown(ctx):
     """Exactly low-rank A: the QR of Z falls back to Householder, whose R
     then gives the core; the factorization is still exact."""
@@ -353,7 +410,7 @@ def test_unknown_flag_bits_are_rejected(ctx):
     A = torch.from_numpy(decaying(300, 200, 20, 1e-3, seed=1)).cuda()
     U, T, V, piv = ctx.alloc_outputs(A, 10, 5)
     info = cu.Info()
-    opts = cu.Opts(cu.PREC["f64"], 0, 0, 2)
+    opts = cu.Opts(cu.PREC["f64"], 0, 0, 4)  # not a defined CORUTV_FLAG_* bit
     rc = cu.lib.corutv_decompose(ctx.h, ctypes.byref(cu.mat(A)), 10, 5, 1, 3, ctypes.byref(opts),
                                  ctypes.byref(cu.mat(U)), T.data_ptr(), 15, ctypes.byref(cu.mat(V)),
                                  piv.data_ptr(), ctypes.byref(info))
