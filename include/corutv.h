@@ -198,6 +198,8 @@ typedef struct corutv_rpca_info {
   double mu0;
   double mu;            /* mu after the last update                           */
   double gpu_ms;
+  double step_ms;       /* summed duration of the fused elementwise kernel over
+                           the iterations when pass timing is on, else 0     */
 } corutv_rpca_info;
 int corutv_rpca(corutv_ctx* ctx, const corutv_mat* M, double lambda, int32_t k, int32_t p,
                 int32_t q, int32_t max_iter, double tol, uint64_t seed, const corutv_opts* opts,

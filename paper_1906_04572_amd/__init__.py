@@ -53,7 +53,8 @@ class Info(ctypes.Structure):
 
 class RpcaInfo(ctypes.Structure):
     _fields_ = [("iters", ctypes.c_int32), ("final_rank", ctypes.c_int32), ("zeta", ctypes.c_double),
-                ("mu0", ctypes.c_double), ("mu", ctypes.c_double), ("gpu_ms", ctypes.c_double)]
+                ("mu0", ctypes.c_double), ("mu", ctypes.c_double), ("gpu_ms", ctypes.c_double),
+                ("step_ms", ctypes.c_double)]
 
     def as_dict(self):
         return {f: getattr(self, f) for f, _ in self._fields_}

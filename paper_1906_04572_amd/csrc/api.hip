@@ -41,7 +41,7 @@ struct Plan {
   // byte offsets
   size_t o_wop = 0, o_qop = 0, o_part = 0, o_x0 = 0, o_x1 = 0, o_q1 = 0, o_q2 = 0, o_xp = 0,
          o_g = 0, o_r = 0, o_rinv = 0, o_core = 0, o_qt = 0, o_rt = 0, o_qw = 0, o_tt = 0,
-         o_piv = 0, o_st = 0, o_res = 0, o_sum = 0, o_cw = 0, o_sbf = 0, o_stage = 0;
+         o_piv = 0, o_st = 0, o_res = 0, o_sum = 0, o_cw = 0, o_sbf = 0, o_stage = 0, o_hh = 0;
   // host-resident A: panels of panel_rows storage rows, stage_ld elements each
   int64_t panel_rows = 0, stage_ld = 0;
   size_t stage_bytes = 0;  // one staging panel
@@ -99,6 +99,7 @@ bool make_plan(int64_t m, int64_t n, int k, int p, int q, int prec, Plan* pl) {
   pl->o_res = take((size_t)residual_blocks(pl->mm) * 2 * 8);
   pl->o_sum = take(2 * 8);
   pl->o_cw = take(chol_work_bytes((int)ell));
+  pl->o_hh = take(hh_work_bytes(pl->mm, (int)ell));
   if (prec == P_BF16 || prec == P_BF16X3) pl->o_sbf = take(sketch_bf16_bytes(pl->ellp, pl->ldx));
   pl->total = off;
   return true;
@@ -274,7 +275,8 @@ hipError_t qr_from_partials(const Plan& pl, char* ws, const Partials& pp, int64_
   // optional R factor: R2 R1 on the Cholesky route, the Householder R after a
   // breakdown (each kernel checks the status word)
   if (rfac && (e = launch_trprod(R2, R, ell, rfac, st, s)) != hipSuccess) return e;
-  return launch_householder_qr(x0, ld, rows, ell, x1, ld, q64, ld, q32, ld, rfac, st, s);
+  return launch_householder_qr(x0, ld, rows, ell, x1, ld, q64, ld, q32, ld, rfac, st,
+                               (double*)(ws + pl.o_hh), s);
 }
 
 // Enqueue a whole decomposition on stream s using the workspace at ws.
@@ -749,7 +751,7 @@ int corutv_tsqr(corutv_ctx* ctx, const double* X, int64_t rows, int32_t ell, int
   const size_t o_x0 = take((size_t)ellp * ld * 8), o_x1 = take((size_t)ellp * ld * 8),
                o_q = take((size_t)ellp * ld * 8), o_xp = take(splits * l2), o_g = take(l2),
                o_r1 = take(2 * l2), o_r2 = take(2 * l2), o_ri = take(l2), o_rh = take(l2),
-               o_st = take(64), o_cw = take(chol_work_bytes(ell));
+               o_st = take(64), o_cw = take(chol_work_bytes(ell)), o_hh = take(hh_work_bytes(rows, ell));
   if (off > ctx->ws_bytes) return CORUTV_E_NOMEM;
   std::lock_guard<std::mutex> lk(ctx->run_mu);
   hipStream_t s = ctx->streams[0];
@@ -776,7 +778,7 @@ int corutv_tsqr(corutv_ctx* ctx, const double* X, int64_t rows, int32_t ell, int
   oq.ptr = qq;
   oq.ld = ld;
   HIPOK(launch_rowmat(x1, ld, rows, ell, Ri, ell, nullptr, oq, 1, MatOut(), 0, st, s, true));
-  HIPOK(launch_householder_qr(x0, ld, rows, ell, x1, ld, qq, ld, nullptr, 0, Rh, st, s));
+  HIPOK(launch_householder_qr(x0, ld, rows, ell, x1, ld, qq, ld, nullptr, 0, Rh, st, (double*)(w + o_hh), s));
   int hst = 0;
   HIPOK(hipMemcpyAsync(&hst, st, 4, hipMemcpyDeviceToHost, s));
   if (hipStreamSynchronize(s) != hipSuccess) return poison(ctx);
@@ -1183,6 +1185,13 @@ extern "C" int corutv_rpca(corutv_ctx* ctx, const corutv_mat* M, double lambda, 
   // Y and B share M's layout, packed
   const int lay = M->layout;
   const int64_t ldi = lay == CORUTV_COL_MAJOR ? m : n;
+  if (ctx->timing) {
+    while ((int)ctx->ev_pool.size() < 2 * max_iter) {
+      hipEvent_t e;
+      if (hipEventCreate(&e) != hipSuccess) return poison(ctx);
+      ctx->ev_pool.push_back(e);
+    }
+  }
   hipEvent_t e0, e1;
   if (hipEventCreate(&e0) != hipSuccess || hipEventCreate(&e1) != hipSuccess) return poison(ctx);
   hipEventRecord(e0, s);
@@ -1244,10 +1253,14 @@ extern "C" int corutv_rpca(corutv_ctx* ctx, const corutv_mat* M, double lambda, 
     const double* Q = lower ? V : Qm;
     const double mu_next = std::min(rho * mu, mu_bar);
     const bool last = j + 1 == max_iter;
+    // L is an output only: written when this iteration may be the last
+    const bool want_l = L && (last || tol > 0);
+    if (ctx->timing) hipEventRecord(ctx->ev_pool[2 * j], s);
     HIPOK(launch_rpca_elementwise((const float*)M->ptr, lay, M->ld, (float*)S->ptr, S->layout, S->ld, Y,
-                                  ldi, last ? nullptr : B, ldi, L ? (float*)L->ptr : nullptr,
+                                  ldi, last ? nullptr : B, ldi, want_l ? (float*)L->ptr : nullptr,
                                   L ? L->layout : CORUTV_COL_MAJOR, L ? L->ld : 1, m, n, P, m, Q, n, T,
                                   ell, ell, mu, mu_next, lambda, part, s));
+    if (ctx->timing) hipEventRecord(ctx->ev_pool[2 * j + 1], s);
     HIPOK(launch_reduce(part, nb, 1, sum, nullptr, s));
     iters = j + 1;
     mu_last = mu;
@@ -1270,9 +1283,17 @@ extern "C" int corutv_rpca(corutv_ctx* ctx, const corutv_mat* M, double lambda, 
   hipEventElapsedTime(&ms, e0, e1);
   hipEventDestroy(e0);
   hipEventDestroy(e1);
+  double step_ms = 0;
+  if (ctx->timing) {
+    for (int j = 0; j < iters; ++j) {
+      float em = 0.f;
+      if (hipEventElapsedTime(&em, ctx->ev_pool[2 * j], ctx->ev_pool[2 * j + 1]) == hipSuccess) step_ms += em;
+    }
+  }
   int r = 0;
   while (r < ell && Th[(size_t)r * ell + r] > 1.0 / mu_last) ++r;
   if (info) {
+    info->step_ms = step_ms;
     info->iters = iters;
     info->final_rank = r;
     info->zeta = zeta;

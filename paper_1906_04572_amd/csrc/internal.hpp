@@ -109,10 +109,14 @@ hipError_t launch_trprod(const double* R2, const double* R1, int ell, double* R,
 
 // Householder thin QR of X (rows x ell, column-major FP64) -> Q (diag R >= 0,
 // FP64 and optionally a float copy), R (nullable); runs only when
-// (*status & 3) == 1 (a Cholesky breakdown on finite data).  work: rows x ell.
+// (*status & 3) == 1 (a Cholesky breakdown on finite data).  work: rows x ell
+// (must not overlap X or Q); hw: hh_work_bytes(rows, ell) bytes for the
+// two-level tree of a tall X (nullable when that is 0).
 hipError_t launch_householder_qr(const double* X, int64_t ldx, int64_t rows, int ell, double* work,
                                  int64_t ldw, double* Q, int64_t ldq, float* Q32, int64_t ldq32,
-                                 double* R, const int* status, hipStream_t st);
+                                 double* R, const int* status, double* hw, hipStream_t st);
+int hh_panels(int64_t rows, int ell);
+size_t hh_work_bytes(int64_t rows, int ell);
 hipError_t launch_fill_int(int* p, int n, int v, hipStream_t st);
 
 // Column-pivoted QR of an ell x ell FP64 matrix (column-major, ldd; trans

@@ -48,39 +48,72 @@ __device__ __forceinline__ int64_t at(int lay, int64_t ld, int64_t i, int64_t j)
   return lay == CORUTV_COL_MAJOR ? j * ld + i : i * ld + j;
 }
 
+// One block of the grid handles tiles of 256 consecutive elements of a storage
+// line of M (a column when M is column-major, a row otherwise) times kLines
+// neighbouring lines, so each thread reads its entry of the along-line factor
+// (P for columns, Q for rows) once per rank-one term and reuses it for kLines
+// elements.  Every element is loaded and computed at a clamped in-range index;
+// only stores and the Z^2 sum are masked.
+constexpr int kLines = 4;
+
 __global__ void __launch_bounds__(256) rpca_step_kernel(RpcaArgs a) {
   __shared__ int rs;
   __shared__ double red[256];
-  if (threadIdx.x == 0) {
-    int r = 0;
-    while (r < a.ell && a.T[(int64_t)r * a.ldt + r] > a.inv_mu) ++r;
-    rs = r;
-  }
+  if (threadIdx.x == 0) rs = a.ell;
+  __syncthreads();
+  // r: the first diagonal entry of T not above 1/mu (diag(T) is a prefix)
+  if ((int)threadIdx.x < a.ell && !(a.T[(int64_t)threadIdx.x * a.ldt + threadIdx.x] > a.inv_mu))
+    atomicMin(&rs, (int)threadIdx.x);
   __syncthreads();
   const int r = rs;
   const bool colmaj = a.lay_m == CORUTV_COL_MAJOR;
-  const int64_t total = a.m * a.n;
+  const int64_t len = colmaj ? a.m : a.n;     // elements along a storage line
+  const int64_t nlines = colmaj ? a.n : a.m;
+  const double* Fa = colmaj ? a.P : a.Q;      // factor indexed along the line
+  const int64_t ldfa = colmaj ? a.ldp : a.ldq;
+  const double* Fb = colmaj ? a.Q : a.P;      // factor indexed by the line
+  const int64_t ldfb = colmaj ? a.ldq : a.ldp;
+  const int64_t ta = (len + 255) / 256, tb = (nlines + kLines - 1) / kLines;
   double z2 = 0.0;
-  for (int64_t e = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; e < total;
-       e += (int64_t)gridDim.x * blockDim.x) {
-    // walk the data in its own storage order (coalesced)
-    const int64_t i = colmaj ? e % a.m : e / a.n;
-    const int64_t j = colmaj ? e / a.m : e % a.n;
-    double l = 0.0;
-    for (int c = 0; c < r; ++c) l = fma(a.P[(int64_t)c * a.ldp + i], a.Q[(int64_t)c * a.ldq + j], l);
-    const int64_t om = at(a.lay_m, a.ldm, i, j);
-    const double mv = (double)a.M[om];
-    const double yv = a.Y ? (double)a.Y[at(a.lay_m, a.ldy, i, j)] : 0.0;
-    const double x = mv - l + yv / a.mu;
-    const double ax = fabs(x) - a.thresh;
-    const double sv = ax > 0.0 ? copysign(ax, x) : 0.0;
-    const double z = mv - l - sv;
-    const double yn = yv + a.mu * z;
-    a.S[at(a.lay_s, a.lds, i, j)] = (float)sv;
-    a.Y[at(a.lay_m, a.ldy, i, j)] = yn;
-    if (a.B) a.B[at(a.lay_m, a.ldb, i, j)] = mv - sv + yn / a.mu_next;
-    if (a.L) a.L[at(a.lay_l, a.ldl, i, j)] = (float)l;
-    z2 += z * z;
+  for (int64_t t = blockIdx.x; t < ta * tb; t += gridDim.x) {
+    const int64_t p0 = (t % ta) * 256 + threadIdx.x;
+    const int64_t b0 = (t / ta) * kLines;
+    const bool pin = p0 < len;
+    const int64_t pc = pin ? p0 : len - 1;
+    int64_t bl[kLines];
+    double l[kLines], mv[kLines], yv[kLines];
+#pragma unroll
+    for (int u = 0; u < kLines; ++u) {
+      bl[u] = b0 + u < nlines ? b0 + u : nlines - 1;
+      l[u] = 0.0;
+    }
+#pragma unroll
+    for (int u = 0; u < kLines; ++u) {
+      mv[u] = (double)a.M[bl[u] * a.ldm + pc];
+      yv[u] = a.Y[bl[u] * a.ldy + pc];
+    }
+    for (int c = 0; c < r; ++c) {
+      const double fa = Fa[(int64_t)c * ldfa + pc];
+#pragma unroll
+      for (int u = 0; u < kLines; ++u) l[u] = fma(fa, Fb[(int64_t)c * ldfb + bl[u]], l[u]);
+    }
+#pragma unroll
+    for (int u = 0; u < kLines; ++u) {
+      const double x = mv[u] - l[u] + yv[u] / a.mu;
+      const double ax = fabs(x) - a.thresh;
+      const double sv = ax > 0.0 ? copysign(ax, x) : 0.0;
+      const double z = mv[u] - l[u] - sv;
+      const double yn = yv[u] + a.mu * z;
+      if (pin && b0 + u < nlines) {
+        const int64_t i = colmaj ? p0 : b0 + u;
+        const int64_t j = colmaj ? b0 + u : p0;
+        a.S[at(a.lay_s, a.lds, i, j)] = (float)sv;
+        a.Y[bl[u] * a.ldy + p0] = yn;
+        if (a.B) a.B[bl[u] * a.ldb + p0] = mv[u] - sv + yn / a.mu_next;
+        if (a.L) a.L[at(a.lay_l, a.ldl, i, j)] = (float)l[u];
+        z2 += z * z;
+      }
+    }
   }
   red[threadIdx.x] = z2;
   __syncthreads();

@@ -15,60 +15,77 @@ namespace corutv {
 namespace {
 
 // ---------------------------------------------------------------------------
-// Sum of the stream-K partial tiles.  One block per (output tile, column
-// group): the tile's contributing partial slots are listed once in LDS in the
-// fixed order (chunk x ascending, workgroup ascending), then every thread sums
-// its (column, row) entries over that list.
+// Sum of the stream-K partial tiles.  The workgroups of every K chunk split
+// the units identically, so a tile's contributing partial slots are chunk x
+// (0..7) times the same list of workgroups; the list is built once in LDS and
+// the slots are taken in the fixed order (chunk x ascending, workgroup
+// ascending).  A block covers 256 / tpe entries of one output tile; with
+// tpe > 1 (a tile fed by many slots: a short output, a long contraction) tpe
+// threads share an entry, each summing a contiguous part of the slot list,
+// and the parts are added in order.
 constexpr int kSegMax = 2048;
-constexpr int kSumCols = 16;  // columns per block
 
 template <typename T>
 __global__ void __launch_bounds__(256) sum_partials_kernel(Partials p, const T* __restrict__ P, int ell,
                                                            int ncols, double* __restrict__ out64,
-                                                           float* __restrict__ out32, int64_t ld) {
-  __shared__ int seg[kSegMax];
-  __shared__ int nseg;
+                                                           float* __restrict__ out32, int64_t ld, int tpe) {
+  __shared__ int wg[kSegMax / 8], wslot[kSegMax / 8];
+  __shared__ int nwg;
+  __shared__ double acc[256];
   const int t = blockIdx.x;
-  const int c0 = blockIdx.y * kSumCols;
   if (threadIdx.x == 0) {
     const int64_t U = (int64_t)p.tiles * p.nkx;
     const int64_t lo = (int64_t)t * p.nkx, hi = lo + p.nkx;
     int n = 0;
-    for (int x = 0; x < 8; ++x) {
-      for (int j = (int)(lo * p.gx / U); j < p.gx; ++j) {
-        const int64_t u0 = (int64_t)j * U / p.gx;
-        if (u0 >= hi) break;
-        const int64_t u1 = (int64_t)(j + 1) * U / p.gx;
-        if ((u0 > lo ? u0 : lo) >= (u1 < hi ? u1 : hi)) continue;
-        if (n < kSegMax) seg[n] = (x * p.gx + j) * p.maxslot + (t - (int)(u0 / p.nkx));
-        ++n;
+    for (int j = (int)(lo * p.gx / U); j < p.gx; ++j) {
+      const int64_t u0 = (int64_t)j * U / p.gx;
+      if (u0 >= hi) break;
+      const int64_t u1 = (int64_t)(j + 1) * U / p.gx;
+      if ((u0 > lo ? u0 : lo) >= (u1 < hi ? u1 : hi)) continue;
+      if (n < kSegMax / 8) {
+        wg[n] = j;
+        wslot[n] = t - (int)(u0 / p.nkx);
       }
+      ++n;
     }
-    nseg = n;
+    nwg = n < kSegMax / 8 ? n : kSegMax / 8;
   }
   __syncthreads();
-  const int ns = nseg < kSegMax ? nseg : kSegMax;
+  const int nw = nwg, ns = 8 * nw;
+  const int epb = 256 / tpe;
+  const int el = threadIdx.x % epb, part = threadIdx.x / epb;
+  const int e = blockIdx.y * epb + el;  // entry of the tile: column e / tw, row e % tw
+  const int nl = e % p.tw;
+  const int c = e / p.tw;
+  const int64_t n = (int64_t)t * p.tw + nl;
   const int64_t tile_elems = (int64_t)p.ellp * p.tw;
-  for (int e = threadIdx.x; e < kSumCols * p.tw; e += blockDim.x) {
-    const int nl = e % p.tw;
-    const int c = c0 + e / p.tw;
-    const int64_t n = (int64_t)t * p.tw + nl;
-    if (c >= ncols || n >= p.n) continue;
-    double v = 0.0;
-    if (c < ell) {
-      const T* src = P + (int64_t)c * p.tw + nl;
-      // loads in groups of eight so their latencies overlap; the sum still
-      // runs over the slots in list order
-      int k = 0;
-      for (; k + 8 <= ns; k += 8) {
-        T l[8];
+  double v = 0.0;
+  if (c < ell && n < p.n) {
+    const T* src = P + (int64_t)c * p.tw + nl;
+    const int k0 = part * ns / tpe, k1 = (part + 1) * ns / tpe;
+    auto slot = [&](int k) {
+      const int x = k / nw, q = k - x * nw;
+      return (int64_t)(x * p.gx + wg[q]) * p.maxslot + wslot[q];
+    };
+    // loads in groups of eight so their latencies overlap; the sum still
+    // runs over the slots in list order
+    int k = k0;
+    for (; k + 8 <= k1; k += 8) {
+      T l[8];
 #pragma unroll
-        for (int j = 0; j < 8; ++j) l[j] = src[(int64_t)seg[k + j] * tile_elems];
+      for (int j = 0; j < 8; ++j) l[j] = src[slot(k + j) * tile_elems];
 #pragma unroll
-        for (int j = 0; j < 8; ++j) v += (double)l[j];
-      }
-      for (; k < ns; ++k) v += (double)src[(int64_t)seg[k] * tile_elems];
+      for (int j = 0; j < 8; ++j) v += (double)l[j];
     }
+    for (; k < k1; ++k) v += (double)src[slot(k) * tile_elems];
+  }
+  if (tpe > 1) {
+    acc[threadIdx.x] = v;
+    __syncthreads();
+    if (part == 0)
+      for (int q = 1; q < tpe; ++q) v += acc[q * epb + el];
+  }
+  if (part == 0 && c < ncols && n < p.n) {
     if (out64) out64[(int64_t)c * ld + n] = v;
     if (out32) out32[(int64_t)c * ld + n] = (float)v;
   }
@@ -651,35 +668,32 @@ __global__ void __launch_bounds__(1024) chol_kernel(const double* __restrict__ G
 }
 
 // ---------------------------------------------------------------------------
-// Householder thin QR (fallback).  One workgroup of 1024 threads; each wave
-// owns columns j = wave (mod 16) for the dot products and updates.
+// Householder thin QR (fallback after a Cholesky breakdown).  A tall X is
+// factored as a two-level tree (TSQR, Demmel, Grigori, Hoemmen and Langou):
+// each of P row panels is reduced by Householder reflections in its own
+// workgroup, the P stacked ell x ell triangles are reduced by one workgroup,
+// and each panel's reflectors are applied to its ell x ell block of the root
+// Q.  The product is X = Q R with Q orthonormal for any X, rank-deficient
+// ones included.  A short X (fewer than two panels) is one workgroup's job.
 __device__ __forceinline__ double wave_sum(double v) {
 #pragma unroll
   for (int off = 32; off > 0; off >>= 1) v += __shfl_xor(v, off, 64);
   return v;
 }
 
-__global__ void __launch_bounds__(1024) householder_kernel(const double* __restrict__ X,
-                                                           int64_t ldx, int64_t rows, int ell,
-                                                           double* __restrict__ W, int64_t ldw,
-                                                           double* __restrict__ Q, int64_t ldq,
-                                                           float* __restrict__ Q32, int64_t ldq32,
-                                                           double* __restrict__ R,
-                                                           const int* status) {
-  if ((*status & 3) != 1) return;  // only after a Cholesky breakdown
-  __shared__ double tau[256], alpha[256], vhead[256];
-  __shared__ double red[16];
-  const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6, nw = 16;
-  for (int64_t e = tid; e < rows * ell; e += 1024) {
-    const int64_t i = e % rows;
-    const int j = (int)(e / rows);
-    W[(int64_t)j * ldw + i] = X[(int64_t)j * ldx + i];
-  }
-  __syncthreads();
+// Householder reduction of the rows x ell column-major W in place (NT
+// threads; waves own columns j = wave mod NT/64).  On return the part of
+// column s below row s holds the tail of reflector s (its head is vhead[s]),
+// the strict upper part holds R's off-diagonal entries, R[s,s] = alpha[s] and
+// H_s = I - tau[s] v v^T (tau = 0 for a zero column).
+template <int NT>
+__device__ void hh_factor(double* __restrict__ W, int64_t ldw, int64_t rows, int ell, double* tau,
+                          double* alpha, double* vhead, double* red) {
+  constexpr int nw = NT / 64;
+  const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
   for (int s = 0; s < ell; ++s) {
-    // norm of W[s:, s]
     double part = 0.0;
-    for (int64_t i = s + tid; i < rows; i += 1024) {
+    for (int64_t i = s + tid; i < rows; i += NT) {
       const double v = W[(int64_t)s * ldw + i];
       part += v * v;
     }
@@ -722,27 +736,21 @@ __global__ void __launch_bounds__(1024) householder_kernel(const double* __restr
     }
     __syncthreads();
   }
-  // R (upper, ell x ell, column-major ld ell) with diag >= 0
-  if (R) {
-    for (int e = tid; e < ell * ell; e += 1024) {
-      const int i = e % ell, j = e / ell;
-      double v = i < j ? W[(int64_t)j * ldw + i] : (i == j ? alpha[i] : 0.0);
-      if (alpha[i] < 0.0) v = -v;
-      R[e] = v;
-    }
-  }
-  __syncthreads();
-  // Q = H_0 ... H_{ell-1} [I; 0], accumulated backwards into Q's columns.
-  for (int64_t e = tid; e < rows * ell; e += 1024) {
-    const int64_t i = e % rows;
-    const int j = (int)(e / rows);
-    Q[(int64_t)j * ldq + i] = i == j ? 1.0 : 0.0;
-  }
-  __syncthreads();
+}
+
+// Q <- H_0 ... H_{ell-1} Q for the rows x ell Q, with the reflectors left in W
+// by hh_factor.  Columns below jmin are not touched (Q = [I; 0] needs only
+// j >= s at step s: earlier columns are unit vectors zero from row s on).
+template <int NT>
+__device__ void hh_apply(const double* __restrict__ W, int64_t ldw, int64_t rows, int ell,
+                         const double* tau, const double* vhead, double* __restrict__ Q, int64_t ldq,
+                         bool identity) {
+  constexpr int nw = NT / 64;
+  const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
   for (int s = ell - 1; s >= 0; --s) {
     const double ts = tau[s], v0 = vhead[s];
     if (ts != 0.0) {
-      for (int j = s + wave; j < ell; j += nw) {
+      for (int j = (identity ? s : 0) + wave; j < ell; j += nw) {
         double d = 0.0;
         for (int64_t i = s + lane; i < rows; i += 64) {
           const double vi = i == s ? v0 : W[(int64_t)s * ldw + i];
@@ -757,6 +765,44 @@ __global__ void __launch_bounds__(1024) householder_kernel(const double* __restr
     }
     __syncthreads();
   }
+}
+
+// One workgroup: X (rows x ell) -> Q (diag R >= 0), R (nullable, ld ell).
+__global__ void __launch_bounds__(1024) householder_kernel(const double* __restrict__ X,
+                                                           int64_t ldx, int64_t rows, int ell,
+                                                           double* __restrict__ W, int64_t ldw,
+                                                           double* __restrict__ Q, int64_t ldq,
+                                                           float* __restrict__ Q32, int64_t ldq32,
+                                                           double* __restrict__ R,
+                                                           const int* status) {
+  if ((*status & 3) != 1) return;  // only after a Cholesky breakdown
+  __shared__ double tau[256], alpha[256], vhead[256];
+  __shared__ double red[16];
+  const int tid = threadIdx.x;
+  for (int64_t e = tid; e < rows * ell; e += 1024) {
+    const int64_t i = e % rows;
+    const int j = (int)(e / rows);
+    W[(int64_t)j * ldw + i] = X[(int64_t)j * ldx + i];
+  }
+  __syncthreads();
+  hh_factor<1024>(W, ldw, rows, ell, tau, alpha, vhead, red);
+  // R (upper, ell x ell, column-major ld ell) with diag >= 0
+  if (R) {
+    for (int e = tid; e < ell * ell; e += 1024) {
+      const int i = e % ell, j = e / ell;
+      double v = i < j ? W[(int64_t)j * ldw + i] : (i == j ? alpha[i] : 0.0);
+      if (alpha[i] < 0.0) v = -v;
+      R[e] = v;
+    }
+  }
+  // Q = H_0 ... H_{ell-1} [I; 0]
+  for (int64_t e = tid; e < rows * ell; e += 1024) {
+    const int64_t i = e % rows;
+    const int j = (int)(e / rows);
+    Q[(int64_t)j * ldq + i] = i == j ? 1.0 : 0.0;
+  }
+  __syncthreads();
+  hh_apply<1024>(W, ldw, rows, ell, tau, vhead, Q, ldq, true);
   // sign normalisation diag(R) >= 0: flip the columns of Q with alpha < 0
   for (int64_t e = tid; e < rows * ell; e += 1024) {
     const int64_t i = e % rows;
@@ -767,6 +813,73 @@ __global__ void __launch_bounds__(1024) householder_kernel(const double* __restr
       Q[(int64_t)j * ldq + i] = v;
     }
     if (Q32) Q32[(int64_t)j * ldq32 + i] = (float)v;
+  }
+}
+
+// Tree level 1: panel b (rows [b h, b h + hb), the last panel takes the
+// remainder) is copied to W and reduced there; its triangle goes to rows
+// [b ell, (b + 1) ell) of the stacked Rs (ld P ell), its tau and reflector
+// heads to tv[b * 2 ell ...].
+__global__ void __launch_bounds__(256) hh_panel_kernel(const double* __restrict__ X, int64_t ldx,
+                                                       int64_t rows, int ell, int64_t h, int P,
+                                                       double* __restrict__ W, int64_t ldw,
+                                                       double* __restrict__ Rs, double* __restrict__ tv,
+                                                       const int* status) {
+  if ((*status & 3) != 1) return;
+  __shared__ double tau[256], alpha[256], vhead[256];
+  __shared__ double red[4];
+  const int tid = threadIdx.x, b = blockIdx.x;
+  const int64_t r0 = (int64_t)b * h, hb = b == P - 1 ? rows - r0 : h;
+  for (int64_t e = tid; e < hb * ell; e += 256) {
+    const int64_t i = e % hb;
+    const int j = (int)(e / hb);
+    W[(int64_t)j * ldw + r0 + i] = X[(int64_t)j * ldx + r0 + i];
+  }
+  __syncthreads();
+  hh_factor<256>(W + r0, ldw, hb, ell, tau, alpha, vhead, red);
+  const int64_t ldr = (int64_t)P * ell;
+  for (int e = tid; e < ell * ell; e += 256) {
+    const int i = e % ell, j = e / ell;
+    Rs[(int64_t)j * ldr + (int64_t)b * ell + i] =
+        i < j ? W[(int64_t)j * ldw + r0 + i] : (i == j ? alpha[i] : 0.0);
+  }
+  for (int s = tid; s < ell; s += 256) {
+    tv[(int64_t)b * 2 * ell + s] = tau[s];
+    tv[(int64_t)b * 2 * ell + ell + s] = vhead[s];
+  }
+}
+
+// Tree level 2 (after the root's Householder QR of Rs gave Qr, ld P ell):
+// panel b of Q is its reflectors applied to [Qr rows b ell ... ; 0].
+__global__ void __launch_bounds__(256) hh_expand_kernel(const double* __restrict__ W, int64_t ldw,
+                                                        int64_t rows, int ell, int64_t h, int P,
+                                                        const double* __restrict__ Qr,
+                                                        const double* __restrict__ tv,
+                                                        double* __restrict__ Q, int64_t ldq,
+                                                        float* __restrict__ Q32, int64_t ldq32,
+                                                        const int* status) {
+  if ((*status & 3) != 1) return;
+  __shared__ double tau[256], vhead[256];
+  const int tid = threadIdx.x, b = blockIdx.x;
+  const int64_t r0 = (int64_t)b * h, hb = b == P - 1 ? rows - r0 : h;
+  const int64_t ldr = (int64_t)P * ell;
+  for (int s = tid; s < ell; s += 256) {
+    tau[s] = tv[(int64_t)b * 2 * ell + s];
+    vhead[s] = tv[(int64_t)b * 2 * ell + ell + s];
+  }
+  for (int64_t e = tid; e < hb * ell; e += 256) {
+    const int64_t i = e % hb;
+    const int j = (int)(e / hb);
+    Q[(int64_t)j * ldq + r0 + i] = i < ell ? Qr[(int64_t)j * ldr + (int64_t)b * ell + i] : 0.0;
+  }
+  __syncthreads();
+  hh_apply<256>(W + r0, ldw, hb, ell, tau, vhead, Q + r0, ldq, false);
+  if (Q32) {
+    for (int64_t e = tid; e < hb * ell; e += 256) {
+      const int64_t i = e % hb;
+      const int j = (int)(e / hb);
+      Q32[(int64_t)j * ldq32 + r0 + i] = (float)Q[(int64_t)j * ldq + r0 + i];
+    }
   }
 }
 
@@ -910,13 +1023,18 @@ hipError_t launch_sum_partials(const Partials& p, int ell, int ncols, double* ou
   if (p.n == 0 || ncols == 0) return hipSuccess;
   // every segment list must fit: at most 8 * (gx + 1) entries per tile
   if (8 * (p.gx + 1) > kSegMax) return hipErrorInvalidValue;
-  dim3 grid((unsigned)p.tiles, (unsigned)((ncols + kSumCols - 1) / kSumCols));
+  // about 8 (gx / tiles + 1) slots feed a tile; give each thread at least 8
+  const int64_t slots = 8 * ((int64_t)p.gx / p.tiles + 1);
+  int tpe = 1;
+  while (tpe < 16 && slots / (2 * tpe) >= 8) tpe *= 2;
+  const int epb = 256 / tpe;
+  dim3 grid((unsigned)p.tiles, (unsigned)(((int64_t)ncols * p.tw + epb - 1) / epb));
   if (p.elem == 8)
     sum_partials_kernel<double><<<grid, dim3(256), 0, st>>>(p, (const double*)p.ptr, ell, ncols, out64,
-                                                            out32, ld);
+                                                            out32, ld, tpe);
   else
     sum_partials_kernel<float><<<grid, dim3(256), 0, st>>>(p, (const float*)p.ptr, ell, ncols, out64,
-                                                           out32, ld);
+                                                           out32, ld, tpe);
   return hipGetLastError();
 }
 
@@ -973,11 +1091,43 @@ hipError_t launch_chol(const double* G, int ell, double* R, double* Rinv, int* s
   return hipGetLastError();
 }
 
+// Panel height of the Householder tree: at least four triangles' worth of
+// rows, so the stacked triangles are at most a quarter of X.
+static int64_t hh_panel_rows(int ell) { return std::max<int64_t>(256, 4 * (int64_t)ell); }
+
+int hh_panels(int64_t rows, int ell) {
+  const int64_t P = rows / hh_panel_rows(ell);
+  return P >= 2 ? (int)P : 1;
+}
+
+size_t hh_work_bytes(int64_t rows, int ell) {
+  const int P = hh_panels(rows, ell);
+  if (P < 2) return 0;
+  const size_t pe = (size_t)P * ell;
+  return (3 * pe * ell + 2 * pe) * 8;
+}
+
 hipError_t launch_householder_qr(const double* X, int64_t ldx, int64_t rows, int ell, double* work,
                                  int64_t ldw, double* Q, int64_t ldq, float* Q32, int64_t ldq32,
-                                 double* R, const int* status, hipStream_t st) {
-  householder_kernel<<<dim3(1), dim3(1024), 0, st>>>(X, ldx, rows, ell, work, ldw, Q, ldq, Q32, ldq32,
-                                                     R, status);
+                                 double* R, const int* status, double* hw, hipStream_t st) {
+  const int P = hh_panels(rows, ell);
+  if (P < 2) {
+    householder_kernel<<<dim3(1), dim3(1024), 0, st>>>(X, ldx, rows, ell, work, ldw, Q, ldq, Q32, ldq32,
+                                                       R, status);
+    return hipGetLastError();
+  }
+  if (!hw) return hipErrorInvalidValue;
+  const int64_t h = hh_panel_rows(ell);
+  const int64_t pe = (int64_t)P * ell;
+  double* Rs = hw;             // stacked triangles, pe x ell
+  double* Rw = Rs + pe * ell;  // the root's working copy
+  double* Qr = Rw + pe * ell;  // the root's Q
+  double* tv = Qr + pe * ell;  // per panel: tau[ell], vhead[ell]
+  hh_panel_kernel<<<dim3(P), dim3(256), 0, st>>>(X, ldx, rows, ell, h, P, work, ldw, Rs, tv, status);
+  householder_kernel<<<dim3(1), dim3(1024), 0, st>>>(Rs, pe, pe, ell, Rw, pe, Qr, pe, nullptr, 0, R,
+                                                     status);
+  hh_expand_kernel<<<dim3(P), dim3(256), 0, st>>>(work, ldw, rows, ell, h, P, Qr, tv, Q, ldq, Q32, ldq32,
+                                                  status);
   return hipGetLastError();
 }
 
