@@ -54,7 +54,7 @@ __device__ __forceinline__ int64_t at(int lay, int64_t ld, int64_t i, int64_t j)
 // (P for columns, Q for rows) once per rank-one term and reuses it for kLines
 // elements.  Every element is loaded and computed at a clamped in-range index;
 // only stores and the Z^2 sum are masked.
-constexpr int kLines = 4;
+constexpr int kLines = 8;
 
 __global__ void __launch_bounds__(256) rpca_step_kernel(RpcaArgs a) {
   __shared__ int rs;

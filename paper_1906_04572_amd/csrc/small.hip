@@ -19,8 +19,8 @@ namespace {
 // the units identically, so a tile's contributing partial slots are chunk x
 // (0..7) times the same list of workgroups; the list is built once in LDS and
 // the slots are taken in the fixed order (chunk x ascending, workgroup
-// ascending).  A block covers 256 / tpe entries of one output tile; with
-// tpe > 1 (a tile fed by many slots: a short output, a long contraction) tpe
+// ascending).  A block covers reps x 256 / tpe entries of one output tile;
+// with tpe > 1 (a tile fed by many slots: a short output, a long contraction) tpe
 // threads share an entry, each summing a contiguous part of the slot list,
 // and the parts are added in order.
 constexpr int kSegMax = 2048;
@@ -28,8 +28,9 @@ constexpr int kSegMax = 2048;
 template <typename T>
 __global__ void __launch_bounds__(256) sum_partials_kernel(Partials p, const T* __restrict__ P, int ell,
                                                            int ncols, double* __restrict__ out64,
-                                                           float* __restrict__ out32, int64_t ld, int tpe) {
-  __shared__ int wg[kSegMax / 8], wslot[kSegMax / 8];
+                                                           float* __restrict__ out32, int64_t ld, int tpe,
+                                                           int reps) {
+  __shared__ int wg[kSegMax / 8], wslot[kSegMax / 8], seg[kSegMax];
   __shared__ int nwg;
   __shared__ double acc[256];
   const int t = blockIdx.x;
@@ -52,42 +53,47 @@ __global__ void __launch_bounds__(256) sum_partials_kernel(Partials p, const T* 
   }
   __syncthreads();
   const int nw = nwg, ns = 8 * nw;
+  for (int k = threadIdx.x; k < ns; k += blockDim.x) {
+    const int x = k / nw, q = k - x * nw;
+    seg[k] = (x * p.gx + wg[q]) * p.maxslot + wslot[q];
+  }
+  __syncthreads();
   const int epb = 256 / tpe;
   const int el = threadIdx.x % epb, part = threadIdx.x / epb;
-  const int e = blockIdx.y * epb + el;  // entry of the tile: column e / tw, row e % tw
-  const int nl = e % p.tw;
-  const int c = e / p.tw;
-  const int64_t n = (int64_t)t * p.tw + nl;
   const int64_t tile_elems = (int64_t)p.ellp * p.tw;
-  double v = 0.0;
-  if (c < ell && n < p.n) {
-    const T* src = P + (int64_t)c * p.tw + nl;
-    const int k0 = part * ns / tpe, k1 = (part + 1) * ns / tpe;
-    auto slot = [&](int k) {
-      const int x = k / nw, q = k - x * nw;
-      return (int64_t)(x * p.gx + wg[q]) * p.maxslot + wslot[q];
-    };
-    // loads in groups of eight so their latencies overlap; the sum still
-    // runs over the slots in list order
-    int k = k0;
-    for (; k + 8 <= k1; k += 8) {
-      T l[8];
+  const int k0 = part * ns / tpe, k1 = (part + 1) * ns / tpe;
+  for (int r = 0; r < reps; ++r) {
+    // entry of the tile: column e / tw, row e % tw
+    const int e = (blockIdx.y * reps + r) * epb + el;
+    const int nl = e % p.tw;
+    const int c = e / p.tw;
+    const int64_t n = (int64_t)t * p.tw + nl;
+    double v = 0.0;
+    if (c < ell && n < p.n) {
+      const T* src = P + (int64_t)c * p.tw + nl;
+      // loads in groups of eight so their latencies overlap; the sum still
+      // runs over the slots in list order
+      int k = k0;
+      for (; k + 8 <= k1; k += 8) {
+        T l[8];
 #pragma unroll
-      for (int j = 0; j < 8; ++j) l[j] = src[slot(k + j) * tile_elems];
+        for (int j = 0; j < 8; ++j) l[j] = src[(int64_t)seg[k + j] * tile_elems];
 #pragma unroll
-      for (int j = 0; j < 8; ++j) v += (double)l[j];
+        for (int j = 0; j < 8; ++j) v += (double)l[j];
+      }
+      for (; k < k1; ++k) v += (double)src[(int64_t)seg[k] * tile_elems];
     }
-    for (; k < k1; ++k) v += (double)src[slot(k) * tile_elems];
-  }
-  if (tpe > 1) {
-    acc[threadIdx.x] = v;
-    __syncthreads();
-    if (part == 0)
-      for (int q = 1; q < tpe; ++q) v += acc[q * epb + el];
-  }
-  if (part == 0 && c < ncols && n < p.n) {
-    if (out64) out64[(int64_t)c * ld + n] = v;
-    if (out32) out32[(int64_t)c * ld + n] = (float)v;
+    if (tpe > 1) {
+      acc[threadIdx.x] = v;
+      __syncthreads();
+      if (part == 0)
+        for (int q = 1; q < tpe; ++q) v += acc[q * epb + el];
+      __syncthreads();
+    }
+    if (part == 0 && c < ncols && n < p.n) {
+      if (out64) out64[(int64_t)c * ld + n] = v;
+      if (out32) out32[(int64_t)c * ld + n] = (float)v;
+    }
   }
 }
 
@@ -1027,14 +1033,17 @@ hipError_t launch_sum_partials(const Partials& p, int ell, int ncols, double* ou
   const int64_t slots = 8 * ((int64_t)p.gx / p.tiles + 1);
   int tpe = 1;
   while (tpe < 16 && slots / (2 * tpe) >= 8) tpe *= 2;
+  // a block covers reps x 256 / tpe entries (16 columns when one thread sums
+  // each entry: the slot list is built once per block)
   const int epb = 256 / tpe;
-  dim3 grid((unsigned)p.tiles, (unsigned)(((int64_t)ncols * p.tw + epb - 1) / epb));
+  const int reps = tpe == 1 ? 16 * p.tw / 256 : 1;
+  dim3 grid((unsigned)p.tiles, (unsigned)(((int64_t)ncols * p.tw + epb * reps - 1) / (epb * reps)));
   if (p.elem == 8)
     sum_partials_kernel<double><<<grid, dim3(256), 0, st>>>(p, (const double*)p.ptr, ell, ncols, out64,
-                                                            out32, ld, tpe);
+                                                            out32, ld, tpe, reps);
   else
     sum_partials_kernel<float><<<grid, dim3(256), 0, st>>>(p, (const float*)p.ptr, ell, ncols, out64,
-                                                           out32, ld, tpe);
+                                                           out32, ld, tpe, reps);
   return hipGetLastError();
 }
 
