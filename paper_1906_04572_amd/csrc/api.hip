@@ -99,7 +99,7 @@ bool make_plan(int64_t m, int64_t n, int k, int p, int q, int prec, Plan* pl) {
   pl->o_res = take((size_t)residual_blocks(pl->mm) * 2 * 8);
   pl->o_sum = take(2 * 8);
   pl->o_cw = take(chol_work_bytes((int)ell));
-  pl->o_hh = take(hh_work_bytes(pl->mm, (int)ell));
+  pl->o_hh = take(std::max(hh_work_bytes(pl->mm, (int)ell), hh_work_bytes(pl->nn, (int)ell)));
   if (prec == P_BF16 || prec == P_BF16X3) pl->o_sbf = take(sketch_bf16_bytes(pl->ellp, pl->ldx));
   pl->total = off;
   return true;

@@ -687,6 +687,42 @@ __device__ __forceinline__ double wave_sum(double v) {
   return v;
 }
 
+// sum over i = s, s + 64, ... < rows (lane offsets added by the caller) of
+// v_i w_i, with v_s replaced by v0; four loads of each column in flight, the
+// terms still added in ascending i
+__device__ __forceinline__ double hh_dot(const double* __restrict__ v, const double* __restrict__ w,
+                                         int64_t i, int64_t s, int64_t rows, double v0) {
+  double d = 0.0;
+  for (; i + 192 < rows; i += 256) {
+    double a[4], b[4];
+#pragma unroll
+    for (int u = 0; u < 4; ++u) {
+      a[u] = v[i + 64 * u];
+      b[u] = w[i + 64 * u];
+    }
+#pragma unroll
+    for (int u = 0; u < 4; ++u) d += (i + 64 * u == s ? v0 : a[u]) * b[u];
+  }
+  for (; i < rows; i += 64) d += (i == s ? v0 : v[i]) * w[i];
+  return d;
+}
+
+// w_i -= d v_i over the same index set
+__device__ __forceinline__ void hh_axpy(const double* __restrict__ v, double* __restrict__ w, int64_t i,
+                                        int64_t s, int64_t rows, double v0, double d) {
+  for (; i + 192 < rows; i += 256) {
+    double a[4], b[4];
+#pragma unroll
+    for (int u = 0; u < 4; ++u) {
+      a[u] = v[i + 64 * u];
+      b[u] = w[i + 64 * u];
+    }
+#pragma unroll
+    for (int u = 0; u < 4; ++u) w[i + 64 * u] = b[u] - d * (i + 64 * u == s ? v0 : a[u]);
+  }
+  for (; i < rows; i += 64) w[i] -= d * (i == s ? v0 : v[i]);
+}
+
 // Householder reduction of the rows x ell column-major W in place (NT
 // threads; waves own columns j = wave mod NT/64).  On return the part of
 // column s below row s holds the tail of reflector s (its head is vhead[s]),
@@ -727,17 +763,11 @@ __device__ void hh_factor(double* __restrict__ W, int64_t ldw, int64_t rows, int
     __syncthreads();
     const double ts = tau[s], v0 = vhead[s];
     if (ts != 0.0) {
+      const double* vs = W + (int64_t)s * ldw;
       for (int j = s + 1 + wave; j < ell; j += nw) {
-        double d = 0.0;
-        for (int64_t i = s + lane; i < rows; i += 64) {
-          const double vi = i == s ? v0 : W[(int64_t)s * ldw + i];
-          d += vi * W[(int64_t)j * ldw + i];
-        }
-        d = wave_sum(d) * ts;
-        for (int64_t i = s + lane; i < rows; i += 64) {
-          const double vi = i == s ? v0 : W[(int64_t)s * ldw + i];
-          W[(int64_t)j * ldw + i] -= d * vi;
-        }
+        double* wj = W + (int64_t)j * ldw;
+        const double d = wave_sum(hh_dot(vs, wj, s + lane, s, rows, v0)) * ts;
+        hh_axpy(vs, wj, s + lane, s, rows, v0, d);
       }
     }
     __syncthreads();
@@ -756,17 +786,11 @@ __device__ void hh_apply(const double* __restrict__ W, int64_t ldw, int64_t rows
   for (int s = ell - 1; s >= 0; --s) {
     const double ts = tau[s], v0 = vhead[s];
     if (ts != 0.0) {
+      const double* vs = W + (int64_t)s * ldw;
       for (int j = (identity ? s : 0) + wave; j < ell; j += nw) {
-        double d = 0.0;
-        for (int64_t i = s + lane; i < rows; i += 64) {
-          const double vi = i == s ? v0 : W[(int64_t)s * ldw + i];
-          d += vi * Q[(int64_t)j * ldq + i];
-        }
-        d = wave_sum(d) * ts;
-        for (int64_t i = s + lane; i < rows; i += 64) {
-          const double vi = i == s ? v0 : W[(int64_t)s * ldw + i];
-          Q[(int64_t)j * ldq + i] -= d * vi;
-        }
+        double* qj = Q + (int64_t)j * ldq;
+        const double d = wave_sum(hh_dot(vs, qj, s + lane, s, rows, v0)) * ts;
+        hh_axpy(vs, qj, s + lane, s, rows, v0, d);
       }
     }
     __syncthreads();
@@ -1100,12 +1124,16 @@ hipError_t launch_chol(const double* G, int ell, double* R, double* Rinv, int* s
   return hipGetLastError();
 }
 
-// Panel height of the Householder tree: at least four triangles' worth of
-// rows, so the stacked triangles are at most a quarter of X.
-static int64_t hh_panel_rows(int ell) { return std::max<int64_t>(256, 4 * (int64_t)ell); }
+// Panel height of the Householder tree: about sqrt(rows ell), so a panel and
+// the stacked triangles (P ell rows) are of similar height; at least four
+// triangles' worth of rows and at least 256.
+static int64_t hh_panel_rows(int64_t rows, int ell) {
+  const int64_t bal = (int64_t)std::sqrt((double)rows * ell);
+  return std::max<int64_t>(std::max<int64_t>(256, 4 * (int64_t)ell), bal);
+}
 
 int hh_panels(int64_t rows, int ell) {
-  const int64_t P = rows / hh_panel_rows(ell);
+  const int64_t P = rows / hh_panel_rows(rows, ell);
   return P >= 2 ? (int)P : 1;
 }
 
@@ -1126,7 +1154,7 @@ hipError_t launch_householder_qr(const double* X, int64_t ldx, int64_t rows, int
     return hipGetLastError();
   }
   if (!hw) return hipErrorInvalidValue;
-  const int64_t h = hh_panel_rows(ell);
+  const int64_t h = hh_panel_rows(rows, ell);
   const int64_t pe = (int64_t)P * ell;
   double* Rs = hw;             // stacked triangles, pe x ell
   double* Rw = Rs + pe * ell;  // the root's working copy
