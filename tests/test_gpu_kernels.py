@@ -50,6 +50,9 @@ CASES = [
     (1000, 777, 37, "col", "f32"), (513, 2050, 16, "row", "f32"), (4096, 1024, 112, "row", "f32"),
     (4096, 1024, 112, "col", "f64"), (3000, 700, 256, "row", "f32"), (1537, 1201, 1, "row", "f64"),
     (64, 64, 64, "col", "f32"), (300, 20000, 10, "row", "f32"), (2048, 1000, 200, "row", "f64"),
+    # short output, long contraction: many partial slots per output tile, so
+    # several threads share each entry of the partial sum
+    (300, 40000, 10, "col", "f64"), (40000, 200, 20, "row", "f32"),
 ]
 
 
