@@ -347,9 +347,16 @@ qrcp_reg_kernel(const double* __restrict__ D, int64_t ldd, int trans, int ell, d
 #pragma unroll
           for (int q = g * kSeg; q < g * kSeg + kSeg && q < NR; ++q) vv[q] = mp[4 * q + k];
         } else if (g == gs) {
+          // All loads first, each made opaque before the masking: a select
+          // between a loaded value and a constant is otherwise turned into a
+          // branch around the load, which then waits for every load in turn.
+          double xs[kSeg];
+#pragma unroll
+          for (int q = g * kSeg; q < g * kSeg + kSeg && q < NR; ++q) xs[q - g * kSeg] = mp[4 * q + k];
 #pragma unroll
           for (int q = g * kSeg; q < g * kSeg + kSeg && q < NR; ++q) {
-            const double x = mp[4 * q + k];
+            double x = xs[q - g * kSeg];
+            asm volatile("" : "+v"(x));
             const int row = 4 * q + k;
             vv[q] = row < s ? 0.0 : (row == s ? v0 : x);
           }
