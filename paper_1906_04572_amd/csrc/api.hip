@@ -317,12 +317,22 @@ int enqueue_decompose(corutv_ctx* ctx, const Plan& pl, char* ws, const DecArgs& 
   const int64_t ldm = pl.ldm, ldn = pl.ldn;
   const int es = f64 ? 8 : 4;
 
-  HIPOK(launch_fill_int(st, kMaxQr, 0, s));
-  // padding columns of the pass operands must read as zero
-  HIPOK(hipMemsetAsync(wop, 0, (size_t)ellp * ldn * es, s));
-  if (!f64) HIPOK(hipMemsetAsync(qop, 0, (size_t)ellp * ldm * es, s));
-  HIPOK(hipMemsetAsync(q1, 0, (size_t)ellp * ldm * 8, s));
-  HIPOK(hipMemsetAsync(q2, 0, (size_t)ellp * ldn * 8, s));
+  // status words, and the pass operands, whose padding columns and rows must
+  // read as zero (one launch)
+  // (every size is a whole number of 16-byte words: ld is a multiple of 64)
+  static_assert(kMaxQr * sizeof(int) % 16 == 0, "status words fill 16-byte words");
+  ZeroRanges z{};
+  auto zero = [&](void* p, size_t bytes) {
+    z.ptr[z.count] = p;
+    z.words[z.count] = (int64_t)(bytes / 16);
+    ++z.count;
+  };
+  zero(st, kMaxQr * sizeof(int));
+  zero(wop, (size_t)ellp * ldn * es);
+  if (!f64) zero(qop, (size_t)ellp * ldm * es);
+  zero(q1, (size_t)ellp * ldm * 8);
+  zero(q2, (size_t)ellp * ldn * 8);
+  HIPOK(launch_zero_ranges(z, s));
   // F64 path: the FP64 bases are the pass operands themselves
   const void* qsrc = f64 ? (const void*)q1 : qop;
   const void* wsrc = f64 ? (const void*)q2 : wop;

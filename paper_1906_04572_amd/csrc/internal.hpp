@@ -119,6 +119,17 @@ int hh_panels(int64_t rows, int ell);
 size_t hh_work_bytes(int64_t rows, int ell);
 hipError_t launch_fill_int(int* p, int n, int v, hipStream_t st);
 
+// Up to kZeroRanges device ranges to clear in one launch: ptr[r] 16-byte
+// aligned, words[r] 16-byte words (bytes / 16).  A fill kernel rather than
+// hipMemsetAsync: one launch for all ranges, and safe under graph capture.
+constexpr int kZeroRanges = 6;
+struct ZeroRanges {
+  void* ptr[kZeroRanges];
+  int64_t words[kZeroRanges];
+  int count;
+};
+hipError_t launch_zero_ranges(const ZeroRanges& z, hipStream_t st);
+
 // Column-pivoted QR of an ell x ell FP64 matrix (column-major, ldd; trans
 // reads D^T).  Qt, R column-major ld ell; piv int32.  work: 2*ell*ell + 2*ell doubles.
 hipError_t launch_qrcp(const double* D, int64_t ldd, int trans, int ell, double* Qt, double* R,

@@ -1011,6 +1011,18 @@ __global__ void fill_int_kernel(int* p, int n, int v) {
   if (i < n) p[i] = v;
 }
 
+// Zero up to kZeroRanges device ranges (16-byte aligned, whole 16-byte
+// words) in one launch.
+__global__ void __launch_bounds__(256) zero_ranges_kernel(ZeroRanges z) {
+  const int64_t stride = (int64_t)gridDim.x * blockDim.x;
+  for (int r = 0; r < z.count; ++r) {
+    uint4* p = (uint4*)z.ptr[r];
+    const int64_t n = z.words[r];
+    for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < n; i += stride)
+      p[i] = uint4{0u, 0u, 0u, 0u};
+  }
+}
+
 // R = R2 R1 for two upper triangular l x l factors (column-major, ld l):
 // the R factor of CholeskyQR2 (X = Q' R1, Q' = Q R2); R = R1 when the QR
 // stopped after one step (status 4).  After a breakdown the Householder
@@ -1194,6 +1206,19 @@ hipError_t launch_residual(const void* A, int dtype, int64_t lda, int64_t R, int
 
 hipError_t launch_fill_int(int* p, int n, int v, hipStream_t st) {
   fill_int_kernel<<<dim3((n + 255) / 256), dim3(256), 0, st>>>(p, n, v);
+  return hipGetLastError();
+}
+
+hipError_t launch_zero_ranges(const ZeroRanges& z, hipStream_t st) {
+  if (z.count < 0 || z.count > kZeroRanges) return hipErrorInvalidValue;
+  int64_t most = 0;
+  for (int r = 0; r < z.count; ++r) {
+    if (((uintptr_t)z.ptr[r] & 15) != 0 || z.words[r] < 0) return hipErrorInvalidValue;
+    most = std::max(most, z.words[r]);
+  }
+  if (most == 0) return hipSuccess;
+  const int64_t blocks = std::min<int64_t>(1024, (most + 255) / 256);
+  zero_ranges_kernel<<<dim3((unsigned)blocks), dim3(256), 0, st>>>(z);
   return hipGetLastError();
 }
 
