@@ -155,6 +155,8 @@ struct corutv_ctx {
   // host-resident A: copy stream and its events (created on first use)
   hipStream_t copy_stream = nullptr;
   hipEvent_t stage_ev[5] = {};  // ready[2], free[2], start
+  // start / end of a blocking decomposition (created on first use)
+  hipEvent_t dec_ev[2] = {};
 };
 
 namespace {
@@ -253,8 +255,6 @@ hipError_t qr_from_partials(const Plan& pl, char* ws, const Partials& pp, int64_
   MatOut ox1;
   ox1.ptr = x1;
   ox1.ld = ld;
-  if ((e = launch_rowmat(x0, ld, rows, ell, Ri, ell, nullptr, ox1, 1, MatOut(), 0, st, s, true)) != hipSuccess)
-    return e;
   MatOut o1, o2;
   o1.ptr = q64;
   o1.ld = ld;
@@ -263,9 +263,13 @@ hipError_t qr_from_partials(const Plan& pl, char* ws, const Partials& pp, int64_
     o2.ld = ld;
     o2.dtype = CORUTV_F32;
   }
-  if (one_step &&
-      (e = launch_rowmat(x0, ld, rows, ell, Ri, ell, nullptr, o1, 1, o2, 1, st, s, true, 4)) != hipSuccess)
-    return e;
+  // X R1^{-1}: the basis itself when one step is enough (status 4), else the
+  // input of the second step (status 0); one launch either way
+  if (one_step)
+    e = launch_rowmat(x0, ld, rows, ell, Ri, ell, nullptr, o1, 1, o2, 1, st, s, true, 4, ox1, 1, 0);
+  else
+    e = launch_rowmat(x0, ld, rows, ell, Ri, ell, nullptr, ox1, 1, MatOut(), 0, st, s, true);
+  if (e != hipSuccess) return e;
   if ((e = launch_xty(x1, ld, x1, ld, rows, ell, xp, splits, st, s)) != hipSuccess) return e;
   if ((e = launch_reduce(xp, splits, l2, G, st, s)) != hipSuccess) return e;
   double* R2 = R + l2;  // the second factor goes beside the first
@@ -634,8 +638,10 @@ int corutv_decompose(corutv_ctx* ctx, const corutv_mat* A, int32_t k, int32_t p,
     for (hipEvent_t& e : ctx->stage_ev)
       if (hipEventCreateWithFlags(&e, hipEventDisableTiming) != hipSuccess) return poison(ctx);
   }
-  hipEvent_t e0, e1;
-  if (hipEventCreate(&e0) != hipSuccess || hipEventCreate(&e1) != hipSuccess) return poison(ctx);
+  if (!ctx->dec_ev[0] &&
+      (hipEventCreate(&ctx->dec_ev[0]) != hipSuccess || hipEventCreate(&ctx->dec_ev[1]) != hipSuccess))
+    return poison(ctx);
+  hipEvent_t e0 = ctx->dec_ev[0], e1 = ctx->dec_ev[1];
   hipEventRecord(e0, s);
   Enqueued eq;
   const int npass = 2 * q + ((opts->flags & CORUTV_FLAG_CORE_FROM_RZ) ? 2 : 3);
@@ -649,16 +655,8 @@ int corutv_decompose(corutv_ctx* ctx, const corutv_mat* A, int32_t k, int32_t p,
   std::vector<hipEvent_t> pev;
   if (ctx->timing) pev.assign(ctx->ev_pool.begin(), ctx->ev_pool.begin() + 2 * npass);
   rc = enqueue_decompose(ctx, pl, ctx->ws, d, s, &eq, ctx->timing ? &pev : nullptr);
-  if (rc == CORUTV_E_DEVICE) {
-    hipEventDestroy(e0);
-    hipEventDestroy(e1);
-    return poison(ctx);
-  }
-  if (rc != CORUTV_OK) {
-    hipEventDestroy(e0);
-    hipEventDestroy(e1);
-    return rc;
-  }
+  if (rc == CORUTV_E_DEVICE) return poison(ctx);
+  if (rc != CORUTV_OK) return rc;
   hipEventRecord(e1, s);
   int* hst = ctx->host_status;
   double hsum[2] = {0, 0};
@@ -669,8 +667,6 @@ int corutv_decompose(corutv_ctx* ctx, const corutv_mat* A, int32_t k, int32_t p,
   if (hipStreamSynchronize(s) != hipSuccess) return poison(ctx);
   float ms = 0.f;
   hipEventElapsedTime(&ms, e0, e1);
-  hipEventDestroy(e0);
-  hipEventDestroy(e1);
   if (ctx->timing) {
     for (int i = 0; i < npass; ++i) {
       float pm = 0.f;
@@ -1104,6 +1100,8 @@ int corutv_destroy(corutv_ctx* ctx) {
   ctx->jobs.clear();
   if (ctx->host_status) hipHostFree(ctx->host_status);
   for (hipEvent_t e : ctx->ev_pool) hipEventDestroy(e);
+  for (hipEvent_t e : ctx->dec_ev)
+    if (e) hipEventDestroy(e);
   if (ctx->copy_stream) {
     hipStreamSynchronize(ctx->copy_stream);
     for (hipEvent_t e : ctx->stage_ev)

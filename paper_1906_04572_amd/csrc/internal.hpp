@@ -85,10 +85,13 @@ struct MatOut {
 // >= rows are not written; columns ell..ellp-1 of FP64 skinny destinations
 // (dtype F64/F32 column-major with pad = 1) are zero-filled.  b_upper: B is
 // upper triangular (entries below the diagonal are zero and are skipped).
-// Runs only when *skip == run_val (skip may be null).
+// Runs only when *skip == run_val (skip may be null); when *skip == alt_val
+// instead (product only, no perm) it writes the single destination oa (pad
+// pada) in place of o1 and o2: one launch for the two outcomes of a status.
 hipError_t launch_rowmat(const double* X, int64_t ldx, int64_t rows, int ell, const double* B,
                          int64_t ldb, const int32_t* perm, MatOut o1, int pad1, MatOut o2, int pad2,
-                         const int* skip, hipStream_t st, bool b_upper = false, int run_val = 0);
+                         const int* skip, hipStream_t st, bool b_upper = false, int run_val = 0,
+                         MatOut oa = MatOut(), int pada = 0, int alt_val = -1);
 
 // Cholesky G = R^T R of an SPD ell x ell FP64 matrix (column-major, ld ell)
 // and the inverse of R, both written column-major (ld ell).  status gets

@@ -292,8 +292,19 @@ __global__ void __launch_bounds__(256) rowmat_mfma_kernel(const double* __restri
                                                           int64_t rows, int ell,
                                                           const double* __restrict__ B, int64_t ldb,
                                                           MatOut o1, int pad1, MatOut o2, int pad2,
-                                                          int b_upper, const int* skip, int run_val) {
-  if (skip && *skip != run_val) return;
+                                                          int b_upper, const int* skip, int run_val,
+                                                          MatOut oa, int pada, int alt_val) {
+  if (skip) {
+    const int sv = *skip;
+    if (sv == alt_val) {
+      o1 = oa;
+      pad1 = pada;
+      o2 = MatOut();
+      pad2 = 0;
+    } else if (sv != run_val) {
+      return;
+    }
+  }
   constexpr int KB = 32, SP = KB + 1, KS = KB / 4, NT = 4, CW = 128;
   constexpr int BPT = KB * CW / 256;  // B values staged per thread and chunk
   __shared__ double sbt[2][CW * SP];  // sbt[buf][c * SP + k] = B[k0 + k][c0 + c]
@@ -1107,9 +1118,12 @@ hipError_t launch_reduce(const double* part, int splits, int64_t elems, double* 
 
 hipError_t launch_rowmat(const double* X, int64_t ldx, int64_t rows, int ell, const double* B,
                          int64_t ldb, const int32_t* perm, MatOut o1, int pad1, MatOut o2, int pad2,
-                         const int* skip, hipStream_t st, bool b_upper, int run_val) {
+                         const int* skip, hipStream_t st, bool b_upper, int run_val, MatOut oa, int pada,
+                         int alt_val) {
   if (rows == 0) return hipSuccess;
   const int ellp = pad_ell(ell);
+  if (oa.ptr && (perm || !skip || alt_val == run_val)) return hipErrorInvalidValue;
+  if (!oa.ptr) alt_val = -1;
   if (perm) {
     const dim3 grid((unsigned)((rows + 255) / 256), (unsigned)ellp);
     gather_cols_kernel<<<grid, dim3(256), 0, st>>>(X, ldx, rows, ell, perm, o1, pad1, o2, pad2, skip,
@@ -1117,7 +1131,7 @@ hipError_t launch_rowmat(const double* X, int64_t ldx, int64_t rows, int ell, co
   } else {
     const dim3 grid((unsigned)((rows + 31) / 32), (unsigned)((ellp + 127) / 128));
     rowmat_mfma_kernel<<<grid, dim3(256), 0, st>>>(X, ldx, rows, ell, B, ldb, o1, pad1, o2, pad2,
-                                                   b_upper ? 1 : 0, skip, run_val);
+                                                   b_upper ? 1 : 0, skip, run_val, oa, pada, alt_val);
   }
   return hipGetLastError();
 }
