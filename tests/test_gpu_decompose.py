@@ -189,6 +189,8 @@ def test_bad_arguments_leave_outputs_untouched(ctx):
     assert ctx.decompose_rc(A, 0, 5, 1, 3, out=out) == cu.E_INVAL
     assert ctx.decompose_rc(A, 10, 5, -1, 3, out=out) == cu.E_INVAL
     assert ctx.decompose_rc(A, 10, 5, 1, 3, prec="f32", out=out) == cu.E_INVAL  # f64 data
+    empty = torch.empty((0, 200), dtype=torch.float64, device="cuda")
+    assert ctx.decompose_rc(empty, 10, 5, 1, 3, out=out) == cu.E_INVAL  # no rows
     torch.cuda.synchronize()
     for t in out:
         assert torch.all(t == 7)
@@ -415,3 +417,35 @@ def test_unknown_flag_bits_are_rejected(ctx):
                                  ctypes.byref(cu.mat(U)), T.data_ptr(), 15, ctypes.byref(cu.mat(V)),
                                  piv.data_ptr(), ctypes.byref(info))
     assert rc == cu.E_INVAL
+
+
+@pytest.mark.parametrize("m,n,k,p,q", [(1, 1, 1, 0, 0), (7, 3, 1, 0, 2), (300, 40, 30, 10, 1), (40, 300, 25, 15, 2)])
+def test_degenerate_shapes(ctx, m, n, k, p, q):
+    """A 1 x 1 matrix, k = 1 with no oversampling, and l = min(m, n) (the
+    factorization is then exact: A = U T V^T to rounding)."""
+    _say("degenerate", m, n, k, p, q)
+    A = np.random.default_rng(m * 31 + n).standard_normal((m, n))
+    got = _run(ctx, A, k, p, q, 11, "f64", "auto")
+    ref = corutv(A, k, p, q, seed=11)
+    _check_f64(A, k, p, q, 11, "auto", got, ref)
+    if k + p == min(m, n):
+        assert got[4]["rel_err"] <= 1e-13
+
+
+@pytest.mark.parametrize("prec", ["f64", "f32"])
+def test_zero_matrix(ctx, prec):
+    """A = 0: every sketch is zero, every thin QR breaks down and the
+    Householder fallback returns an orthonormal basis; the core is zero, no
+    column is ever preferred (pivots in natural order, as the oracle's) and
+    T = 0, so U T V^T = A exactly."""
+    _say("zero", prec)
+    A = np.zeros((50, 30), dtype=np.float64 if prec == "f64" else np.float32)
+    U, T, V, piv, info = _run(ctx, A, 5, 3, 1, 1, prec, "auto")
+    ref = corutv(A.astype(np.float64), 5, 3, 1, seed=1)
+    assert info["qr_fallbacks"] >= 1
+    assert info["rel_err"] == 0.0
+    assert np.all(T == 0)
+    np.testing.assert_array_equal(piv, ref["piv"])
+    tol = 1e-13 if prec == "f64" else 1e-6
+    assert np.max(np.abs(U.T @ U - np.eye(8))) <= tol
+    assert np.max(np.abs(V.T @ V - np.eye(8))) <= tol
