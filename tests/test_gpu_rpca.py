@@ -55,6 +55,24 @@ def test_frames_shape_reduced_matches_oracle(ctx):
     assert info["iters"] == 50
 
 
+@pytest.mark.parametrize("m,n,layout", [(7680, 300, "row"), (300, 7680, "col"), (301, 2999, "row")])
+def test_layouts_and_wide_inputs(ctx, m, n, layout):
+    """Row-major M (the elementwise kernel walks rows: the along-line factor
+    is Q), a wide M (lower T: P = U T, Q = V) and ragged sizes; the same
+    endpoints as the oracle's."""
+    _say("rpca", m, n, layout)
+    M, L, S = low_rank_plus_sparse(m, n, 5, 0.05, 50.0, seed=m + n, grid=GRID)
+    Md = torch.from_numpy(np.ascontiguousarray(M, dtype=np.float32)).cuda() if layout == "row" else _col(M)
+    Lg, Sg, info = ctx.rpca(Md, 5, 5, 1, seed=9, max_iter=50)
+    Lg, Sg = Lg.cpu().numpy().astype(np.float64), Sg.cpu().numpy().astype(np.float64)
+    Lo, So, oinfo = alm_corutv(M, 5, 5, 1, seed=9, max_iter=50)
+    assert info["final_rank"] == 5 == oinfo["ranks"][-1]
+    assert np.array_equal(Sg != 0, S != 0)
+    assert np.array_equal(Sg != 0, So != 0)
+    assert np.linalg.norm(Lg - L) / np.linalg.norm(L) <= 1e-5
+    assert info["iters"] == 50
+
+
 def test_table1_n1000_row(ctx):
     _say("rpca table-1 n=1000")
     M, L, S = low_rank_plus_sparse(1000, 1000, 50, 0.05, 80.0, seed=1000, values="pm", grid=GRID)
