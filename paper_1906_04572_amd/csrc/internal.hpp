@@ -29,6 +29,7 @@ struct Partials {
   int ellp = 0;
   int tw = 0;             // output rows per tile
   int tiles = 0;
+  int nchunk = 8;         // K chunks: 8 (chunk x on XCD x) or 1 (short K)
   int nkx = 0;            // k-blocks per chunk
   int gx = 0;             // workgroups per chunk
   int maxslot = 0;

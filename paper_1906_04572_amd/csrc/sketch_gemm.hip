@@ -19,6 +19,9 @@
 //    XCD (workgroup w runs on XCD w mod 8), so each XCD's L2 holds only its
 //    1/8 of the skinny operand; inside a chunk the (tile, k-block) units are
 //    divided evenly over a persistent grid, so every CU gets the same work.
+//    A skinny operand of at most 1 MB fits every L2 whole: the reduction is
+//    then one chunk over the whole grid, and an output tile gathers about
+//    8 g / tiles + 1 partial tiles instead of 8 (g / tiles + 1).
 //    Each workgroup writes one partial tile per output tile it touches; the
 //    consumer kernel sums them in a fixed order, so results are
 //    deterministic (no atomics).
@@ -63,7 +66,7 @@ struct SketchArgs {
   const void* S2;  // bf16 forms: the lo parts of the pre-split skinny operand
   int64_t lds;
   void* P;
-  int tiles, nk, nkx, gx, maxslot;
+  int tiles, nk, nkx, gx, maxslot, nchunk;
 };
 
 // VEC: A rows 16-byte aligned (address and leading dimension), so vector
@@ -88,8 +91,8 @@ __global__ void __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(sizeof
   const int tid = threadIdx.x;
   const int lane = tid & 63, wave = tid >> 6;
   const int g = lane >> 4, qd = lane & 15;
-  const int x = blockIdx.x & 7;
-  const int jw = blockIdx.x >> 3;
+  const int x = blockIdx.x % a.nchunk;  // K chunk (chunk x on XCD x when there are 8)
+  const int jw = blockIdx.x / a.nchunk;
   const T* __restrict__ A = (const T*)a.A;
   const T* __restrict__ S = (const T*)a.S;
   T* __restrict__ P = (T*)a.P;
@@ -320,8 +323,8 @@ __global__ void __launch_bounds__(256) sketch_bf16_kernel(SketchArgs a) {
   const int tid = threadIdx.x;
   const int lane = tid & 63, wave = tid >> 6;
   const int g = lane >> 4, qd = lane & 15;
-  const int x = blockIdx.x & 7;
-  const int jw = blockIdx.x >> 3;
+  const int x = blockIdx.x % a.nchunk;  // K chunk (chunk x on XCD x when there are 8)
+  const int jw = blockIdx.x / a.nchunk;
   const float* __restrict__ A = (const float*)a.A;
   const __bf16* __restrict__ Sp[2] = {(const __bf16*)a.S, (const __bf16*)a.S2};
   float* __restrict__ P = (float*)a.P;
@@ -575,6 +578,9 @@ int occupancy_of(void* fn) {
 // k values per stage of each kernel family
 int kc_of(int prec) { return prec == P_F64 ? 16 : (prec == P_BF16 ? 64 : 32); }
 
+constexpr int64_t kOneChunkBytes = 1 << 20;
+
+// gx: workgroups per XCD (the grid is 8 gx)
 void geometry(int64_t N, int64_t K, int ellp, int elem, int kc, int gx, Partials* p) {
   const int mb = ellp / 16;
   const int nb = mb <= 8 ? 2 : 1;
@@ -585,8 +591,11 @@ void geometry(int64_t N, int64_t K, int ellp, int elem, int kc, int gx, Partials
   p->n = N;
   p->tiles = (int)((N + tw - 1) / tw);
   const int64_t nk = (K + kc - 1) / kc;
-  p->nkx = (int)((nk + 7) / 8);
+  // a skinny operand that fits every XCD's L2 whole needs no split by XCD
+  p->nchunk = K * ellp * elem <= kOneChunkBytes ? 1 : 8;
+  p->nkx = (int)((nk + p->nchunk - 1) / p->nchunk);
   if (p->nkx < 1) p->nkx = 1;
+  gx = gx * 8 / p->nchunk;  // workgroups per chunk (the grid is 8 gx either way)
   p->gx = gx;
   const int64_t U = (int64_t)p->tiles * p->nkx;
   int ms = 1;
@@ -602,7 +611,7 @@ void geometry(int64_t N, int64_t K, int ellp, int elem, int kc, int gx, Partials
 }  // namespace
 
 static int64_t need_elems(const Partials& p) {
-  return 8ll * p.gx * p.maxslot * (int64_t)p.ellp * p.tw;
+  return (int64_t)p.nchunk * p.gx * p.maxslot * (int64_t)p.ellp * p.tw;
 }
 
 int64_t partials_capacity(int64_t n_out, int64_t k_len, int ellp, int prec) {
@@ -680,6 +689,7 @@ hipError_t launch_sketch(int prec, int trans, const void* A, int64_t lda, int64_
   a.tiles = part->tiles;
   a.nk = (int)((K + kc - 1) / kc);
   a.nkx = part->nkx;
+  a.nchunk = part->nchunk;
   a.gx = part->gx;
   a.maxslot = part->maxslot;
   void* args[] = {&a};

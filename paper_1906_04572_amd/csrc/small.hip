@@ -17,7 +17,7 @@ namespace {
 // ---------------------------------------------------------------------------
 // Sum of the stream-K partial tiles.  The workgroups of every K chunk split
 // the units identically, so a tile's contributing partial slots are chunk x
-// (0..7) times the same list of workgroups; the list is built once in LDS and
+// (0..nchunk-1) times the same list of workgroups; the list is built once in LDS and
 // the slots are taken in the fixed order (chunk x ascending, workgroup
 // ascending).  A block covers reps x 256 / tpe entries of one output tile;
 // with tpe > 1 (a tile fed by many slots: a short output, a long contraction) tpe
@@ -30,7 +30,7 @@ __global__ void __launch_bounds__(256) sum_partials_kernel(Partials p, const T* 
                                                            int ncols, double* __restrict__ out64,
                                                            float* __restrict__ out32, int64_t ld, int tpe,
                                                            int reps) {
-  __shared__ int wg[kSegMax / 8], wslot[kSegMax / 8], seg[kSegMax];
+  __shared__ int wg[kSegMax], wslot[kSegMax], seg[kSegMax];
   __shared__ int nwg;
   __shared__ double acc[256];
   const int t = blockIdx.x;
@@ -43,16 +43,16 @@ __global__ void __launch_bounds__(256) sum_partials_kernel(Partials p, const T* 
       if (u0 >= hi) break;
       const int64_t u1 = (int64_t)(j + 1) * U / p.gx;
       if ((u0 > lo ? u0 : lo) >= (u1 < hi ? u1 : hi)) continue;
-      if (n < kSegMax / 8) {
+      if (n < kSegMax) {
         wg[n] = j;
         wslot[n] = t - (int)(u0 / p.nkx);
       }
       ++n;
     }
-    nwg = n < kSegMax / 8 ? n : kSegMax / 8;
+    nwg = n < kSegMax ? n : kSegMax;
   }
   __syncthreads();
-  const int nw = nwg, ns = 8 * nw;
+  const int nw = nwg, ns = p.nchunk * nw;
   for (int k = threadIdx.x; k < ns; k += blockDim.x) {
     const int x = k / nw, q = k - x * nw;
     seg[k] = (x * p.gx + wg[q]) * p.maxslot + wslot[q];
@@ -1075,9 +1075,9 @@ hipError_t launch_sum_partials(const Partials& p, int ell, int ncols, double* ou
                                int64_t ld, hipStream_t st) {
   if (p.n == 0 || ncols == 0) return hipSuccess;
   // every segment list must fit: at most 8 * (gx + 1) entries per tile
-  if (8 * (p.gx + 1) > kSegMax) return hipErrorInvalidValue;
-  // about 8 (gx / tiles + 1) slots feed a tile; give each thread at least 8
-  const int64_t slots = 8 * ((int64_t)p.gx / p.tiles + 1);
+  if (p.nchunk < 1 || (int64_t)p.nchunk * (p.gx + 1) > kSegMax) return hipErrorInvalidValue;
+  // about nchunk (gx / tiles + 1) slots feed a tile; give each thread at least 8
+  const int64_t slots = p.nchunk * ((int64_t)p.gx / p.tiles + 1);
   int tpe = 1;
   while (tpe < 16 && slots / (2 * tpe) >= 8) tpe *= 2;
   // a block covers reps x 256 / tpe entries (16 columns when one thread sums
