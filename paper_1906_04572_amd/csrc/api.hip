@@ -1200,10 +1200,22 @@ extern "C" int corutv_rpca(corutv_ctx* ctx, const corutv_mat* M, double lambda, 
       ctx->ev_pool.push_back(e);
     }
   }
-  hipEvent_t e0, e1;
-  if (hipEventCreate(&e0) != hipSuccess || hipEventCreate(&e1) != hipSuccess) return poison(ctx);
+  // the context's start / end events (calls on one context are serialised)
+  if (!ctx->dec_ev[0] &&
+      (hipEventCreate(&ctx->dec_ev[0]) != hipSuccess || hipEventCreate(&ctx->dec_ev[1]) != hipSuccess))
+    return poison(ctx);
+  hipEvent_t e0 = ctx->dec_ev[0], e1 = ctx->dec_ev[1];
   hipEventRecord(e0, s);
-  HIPOK(hipMemsetAsync(Y, 0, (size_t)m * n * 8, s));
+  // Y = 0 (m n doubles: a whole number of 16-byte words when m n is even)
+  if ((size_t)m * n % 2 == 0) {
+    ZeroRanges zy{};
+    zy.ptr[0] = Y;
+    zy.words[0] = (int64_t)((size_t)m * n / 2);
+    zy.count = 1;
+    HIPOK(launch_zero_ranges(zy, s));
+  } else {
+    HIPOK(hipMemsetAsync(Y, 0, (size_t)m * n * 8, s));
+  }
   HIPOK(launch_widen((const float*)M->ptr, lay, M->ld, m, n, B, ldi, s));
   // ||M||_F
   HIPOK(launch_sumsq((const float*)M->ptr, lay, M->ld, m, n, part, s));
@@ -1289,8 +1301,6 @@ extern "C" int corutv_rpca(corutv_ctx* ctx, const corutv_mat* M, double lambda, 
   if (hipStreamSynchronize(s) != hipSuccess) return poison(ctx);
   float ms = 0;
   hipEventElapsedTime(&ms, e0, e1);
-  hipEventDestroy(e0);
-  hipEventDestroy(e1);
   double step_ms = 0;
   if (ctx->timing) {
     for (int j = 0; j < iters; ++j) {
