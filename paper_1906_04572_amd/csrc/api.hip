@@ -13,6 +13,7 @@
 #include <deque>
 #include <map>
 #include <mutex>
+#include <tuple>
 #include <new>
 #include <thread>
 #include <vector>
@@ -50,6 +51,26 @@ struct Plan {
 
 size_t align256(size_t x) { return (x + 255) / 256 * 256; }
 
+// The partial-tile capacity of a shape takes tens of microseconds of host
+// time (geometry scans over every grid size); every blocking call and every
+// admitted request needs it, so it is kept per shape.
+std::mutex g_cap_mu;
+std::map<std::tuple<int64_t, int64_t, int, int>, int64_t> g_cap;
+
+int64_t partials_capacity_cached(int64_t n_out, int64_t k_len, int ellp, int prec) {
+  const auto key = std::make_tuple(n_out, k_len, ellp, prec);
+  {
+    std::lock_guard<std::mutex> lk(g_cap_mu);
+    auto it = g_cap.find(key);
+    if (it != g_cap.end()) return it->second;
+  }
+  const int64_t cap = partials_capacity(n_out, k_len, ellp, prec);
+  std::lock_guard<std::mutex> lk(g_cap_mu);
+  if (g_cap.size() > 4096) g_cap.clear();  // bounded for streams of many shapes
+  g_cap[key] = cap;
+  return cap;
+}
+
 bool make_plan(int64_t m, int64_t n, int k, int p, int q, int prec, Plan* pl) {
   (void)q;
   if (m < 1 || n < 1 || k < 1 || p < 0) return false;
@@ -68,8 +89,8 @@ bool make_plan(int64_t m, int64_t n, int k, int p, int q, int prec, Plan* pl) {
   // partial tiles: the larger of the two pass orientations (gemm prec for
   // partial element size: BF16 forms accumulate in FP32 like F32)
   const int gp = prec == P_F64 ? P_F64 : P_F32;
-  pl->part_elems = std::max(partials_capacity(pl->mm, pl->nn, pl->ellp, gp),
-                            partials_capacity(pl->nn, pl->mm, pl->ellp, gp));
+  pl->part_elems = std::max(partials_capacity_cached(pl->mm, pl->nn, pl->ellp, gp),
+                            partials_capacity_cached(pl->nn, pl->mm, pl->ellp, gp));
   pl->xsplits = std::max(xty_splits(pl->mm, pl->ell), xty_splits(pl->nn, pl->ell));
   const size_t l2 = (size_t)ell * ell * 8;
   size_t off = 0;
@@ -716,7 +737,7 @@ int corutv_sketch(corutv_ctx* ctx, const corutv_mat* A, int32_t trans, int32_t p
   const bool a_col = A->layout == CORUTV_COL_MAJOR;
   const int64_t Rb = a_col ? n : m, Cb = a_col ? m : n;
   const int t = (a_col ? 1 : 0) ^ trans;
-  const int64_t cap = partials_capacity(nout, klen, ellp, prec);
+  const int64_t cap = partials_capacity_cached(nout, klen, ellp, prec);
   const bool bf = prec == P_BF16 || prec == P_BF16X3;
   const size_t need = align256((size_t)ellp * ldk * es) + align256((size_t)cap * es) +
                       (bf ? align256(sketch_bf16_bytes(ellp, ldk)) : 0);
