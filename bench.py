@@ -432,6 +432,29 @@ def main():
             "corutv_per_s": round(1 / hdt, 2), "ms_per_step": round(hdt * 1e3, 2), "passes_per_step": 5,
             "host_to_device_GBps": round(5 * M * N * 4 / hdt / 1e9, 1), "panel_rows": HOST_PANEL_ROWS}
         del A_host, out
+        # the same decompositions as a stream through the serving queue with
+        # two slots: one request's small steps (thin QRs, QRCP: a few
+        # workgroups) overlap the next one's passes
+        slots = 2
+        pstreams = [torch.cuda.current_stream()] + [torch.cuda.Stream() for _ in range(slots)]
+        pctx = cu.Context(workspace_bytes=slots * cu.workspace_bytes(M, N, K_RANK, P_OVER, 1, "f32"),
+                          streams=pstreams)
+        nreq = 20
+        outs = [pctx.alloc_outputs(A32, K_RANK, P_OVER) for _ in range(nreq)]
+        for t in [pctx.submit(A32, K_RANK, P_OVER, 1, seed=900 + i, prec="f32", out=outs[i]) for i in range(2)]:
+            pctx.wait(t)
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        tickets = [pctx.submit(A32, K_RANK, P_OVER, 1, seed=i + 1, prec="f32", out=outs[i]) for i in range(nreq)]
+        for t in tickets:
+            pctx.wait(t)
+        torch.cuda.synchronize()
+        pdt = (time.perf_counter() - t0) / nreq
+        variants["f32_q1_queue_2slots"] = {
+            "corutv_per_s": round(1 / pdt, 2), "ms_per_step": round(pdt * 1e3, 3), "passes_per_step": 5,
+            "requests": nreq, "slots": slots}
+        pctx.close()
+        del outs
     ctx.close()
     del A_main, A32
     torch.cuda.empty_cache()
