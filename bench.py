@@ -319,7 +319,7 @@ def main():
                     help="only measure achievable peaks with library kernels (HBM read, GEMM rates)")
     args = ap.parse_args()
     if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) != 1:
-        print("bench.py measures one GPU only: this build has no multi-GPU path "
+        print("bench.py measures one GPU only: the library has no multi-GPU path "
               "(requested --gpus %d)" % args.gpus, flush=True)
         sys.exit(2)
 
