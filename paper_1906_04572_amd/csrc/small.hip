@@ -857,52 +857,82 @@ __global__ void __launch_bounds__(1024) householder_kernel(const double* __restr
   }
 }
 
-// Tree level 1: panel b (rows [b h, b h + hb), the last panel takes the
-// remainder) is copied to W and reduced there; its triangle goes to rows
-// [b ell, (b + 1) ell) of the stacked Rs (ld P ell), its tau and reflector
-// heads to tv[b * 2 ell ...].
+// Panels of the tree.  A panel of at most kHhLds entries is factored in LDS
+// (panels then split the rows evenly: panel b is rows [b rows / P,
+// (b + 1) rows / P)); otherwise panel b is rows [b h, b h + h) of the
+// workspace copy, the last one taking the remainder.  Either way the
+// reflectors end in W (rows of the panel), where the expand step reads them.
+constexpr int kHhLds = 7168;  // doubles (56 KB)
+
+__device__ __forceinline__ void hh_panel_range(int b, int64_t rows, int64_t h, int P, int lds, int64_t& r0,
+                                               int64_t& hb) {
+  if (lds) {
+    r0 = (int64_t)b * rows / P;
+    hb = (int64_t)(b + 1) * rows / P - r0;
+  } else {
+    r0 = (int64_t)b * h;
+    hb = b == P - 1 ? rows - r0 : h;
+  }
+}
+
+// Tree level 1: panel b is reduced (in LDS or in W); its triangle goes to
+// rows [b ell, (b + 1) ell) of the stacked Rs (ld P ell), its tau and
+// reflector heads to tv[b * 2 ell ...].
 __global__ void __launch_bounds__(256) hh_panel_kernel(const double* __restrict__ X, int64_t ldx,
-                                                       int64_t rows, int ell, int64_t h, int P,
+                                                       int64_t rows, int ell, int64_t h, int P, int lds,
                                                        double* __restrict__ W, int64_t ldw,
                                                        double* __restrict__ Rs, double* __restrict__ tv,
                                                        const int* status) {
   if ((*status & 3) != 1) return;
+  __shared__ double sw[kHhLds];
   __shared__ double tau[256], alpha[256], vhead[256];
   __shared__ double red[4];
   const int tid = threadIdx.x, b = blockIdx.x;
-  const int64_t r0 = (int64_t)b * h, hb = b == P - 1 ? rows - r0 : h;
+  int64_t r0, hb;
+  hh_panel_range(b, rows, h, P, lds, r0, hb);
+  double* Wp = lds ? sw : W + r0;
+  const int64_t ldp = lds ? hb : ldw;
   for (int64_t e = tid; e < hb * ell; e += 256) {
     const int64_t i = e % hb;
     const int j = (int)(e / hb);
-    W[(int64_t)j * ldw + r0 + i] = X[(int64_t)j * ldx + r0 + i];
+    Wp[(int64_t)j * ldp + i] = X[(int64_t)j * ldx + r0 + i];
   }
   __syncthreads();
-  hh_factor<256>(W + r0, ldw, hb, ell, tau, alpha, vhead, red);
+  hh_factor<256>(Wp, ldp, hb, ell, tau, alpha, vhead, red);
   const int64_t ldr = (int64_t)P * ell;
   for (int e = tid; e < ell * ell; e += 256) {
     const int i = e % ell, j = e / ell;
     Rs[(int64_t)j * ldr + (int64_t)b * ell + i] =
-        i < j ? W[(int64_t)j * ldw + r0 + i] : (i == j ? alpha[i] : 0.0);
+        i < j ? Wp[(int64_t)j * ldp + i] : (i == j ? alpha[i] : 0.0);
   }
   for (int s = tid; s < ell; s += 256) {
     tv[(int64_t)b * 2 * ell + s] = tau[s];
     tv[(int64_t)b * 2 * ell + ell + s] = vhead[s];
+  }
+  if (lds) {
+    for (int64_t e = tid; e < hb * ell; e += 256) {
+      const int64_t i = e % hb;
+      const int j = (int)(e / hb);
+      W[(int64_t)j * ldw + r0 + i] = sw[(int64_t)j * hb + i];
+    }
   }
 }
 
 // Tree level 2 (after the root's Householder QR of Rs gave Qr, ld P ell):
 // panel b of Q is its reflectors applied to [Qr rows b ell ... ; 0].
 __global__ void __launch_bounds__(256) hh_expand_kernel(const double* __restrict__ W, int64_t ldw,
-                                                        int64_t rows, int ell, int64_t h, int P,
+                                                        int64_t rows, int ell, int64_t h, int P, int lds,
                                                         const double* __restrict__ Qr,
                                                         const double* __restrict__ tv,
                                                         double* __restrict__ Q, int64_t ldq,
                                                         float* __restrict__ Q32, int64_t ldq32,
                                                         const int* status) {
   if ((*status & 3) != 1) return;
+  __shared__ double sw[kHhLds];
   __shared__ double tau[256], vhead[256];
   const int tid = threadIdx.x, b = blockIdx.x;
-  const int64_t r0 = (int64_t)b * h, hb = b == P - 1 ? rows - r0 : h;
+  int64_t r0, hb;
+  hh_panel_range(b, rows, h, P, lds, r0, hb);
   const int64_t ldr = (int64_t)P * ell;
   for (int s = tid; s < ell; s += 256) {
     tau[s] = tv[(int64_t)b * 2 * ell + s];
@@ -912,9 +942,13 @@ __global__ void __launch_bounds__(256) hh_expand_kernel(const double* __restrict
     const int64_t i = e % hb;
     const int j = (int)(e / hb);
     Q[(int64_t)j * ldq + r0 + i] = i < ell ? Qr[(int64_t)j * ldr + (int64_t)b * ell + i] : 0.0;
+    if (lds) sw[(int64_t)j * hb + i] = W[(int64_t)j * ldw + r0 + i];
   }
   __syncthreads();
-  hh_apply<256>(W + r0, ldw, hb, ell, tau, vhead, Q + r0, ldq, false);
+  if (lds)
+    hh_apply<256>(sw, hb, hb, ell, tau, vhead, Q + r0, ldq, false);
+  else
+    hh_apply<256>(W + r0, ldw, hb, ell, tau, vhead, Q + r0, ldq, false);
   if (Q32) {
     for (int64_t e = tid; e < hb * ell; e += 256) {
       const int64_t i = e % hb;
@@ -1150,18 +1184,44 @@ hipError_t launch_chol(const double* G, int ell, double* R, double* Rinv, int* s
   return hipGetLastError();
 }
 
-// Panel height of the Householder tree: about sqrt(rows ell), so a panel and
-// the stacked triangles (P ell rows) are of similar height; at least four
-// triangles' worth of rows and at least 256.
+// Panel height of the Householder tree when panels do not fit LDS: about
+// sqrt(rows ell), so a panel and the stacked triangles (P ell rows) are of
+// similar height; at least four triangles' worth of rows and at least 256.
 static int64_t hh_panel_rows(int64_t rows, int ell) {
   const int64_t bal = (int64_t)std::sqrt((double)rows * ell);
   return std::max<int64_t>(std::max<int64_t>(256, 4 * (int64_t)ell), bal);
 }
 
-int hh_panels(int64_t rows, int ell) {
-  const int64_t P = rows / hh_panel_rows(rows, ell);
-  return P >= 2 ? (int)P : 1;
+struct HhTree {
+  int P = 1;       // panels (1: one workgroup does the whole QR)
+  int64_t h = 0;   // panel height (device-memory panels)
+  int lds = 0;     // panels in LDS, rows split evenly
+};
+
+// LDS panels when a panel of at least 2 ell rows fits and the stacked
+// triangles stay at most 4096 rows; else the device-memory tree.
+static HhTree hh_tree(int64_t rows, int ell) {
+  HhTree t;
+  const int64_t hl = kHhLds / ell;
+  if (hl >= 2 * (int64_t)ell && hl >= 64) {
+    const int64_t P = (rows + hl - 1) / hl;
+    if (P < 2) return t;
+    if (P * ell <= 4096) {
+      t.P = (int)P;
+      t.lds = 1;
+      return t;
+    }
+  }
+  const int64_t h = hh_panel_rows(rows, ell);
+  const int64_t P = rows / h;
+  if (P >= 2) {
+    t.P = (int)P;
+    t.h = h;
+  }
+  return t;
 }
+
+int hh_panels(int64_t rows, int ell) { return hh_tree(rows, ell).P; }
 
 size_t hh_work_bytes(int64_t rows, int ell) {
   const int P = hh_panels(rows, ell);
@@ -1173,24 +1233,25 @@ size_t hh_work_bytes(int64_t rows, int ell) {
 hipError_t launch_householder_qr(const double* X, int64_t ldx, int64_t rows, int ell, double* work,
                                  int64_t ldw, double* Q, int64_t ldq, float* Q32, int64_t ldq32,
                                  double* R, const int* status, double* hw, hipStream_t st) {
-  const int P = hh_panels(rows, ell);
+  const HhTree tr = hh_tree(rows, ell);
+  const int P = tr.P;
   if (P < 2) {
     householder_kernel<<<dim3(1), dim3(1024), 0, st>>>(X, ldx, rows, ell, work, ldw, Q, ldq, Q32, ldq32,
                                                        R, status);
     return hipGetLastError();
   }
   if (!hw) return hipErrorInvalidValue;
-  const int64_t h = hh_panel_rows(rows, ell);
   const int64_t pe = (int64_t)P * ell;
   double* Rs = hw;             // stacked triangles, pe x ell
   double* Rw = Rs + pe * ell;  // the root's working copy
   double* Qr = Rw + pe * ell;  // the root's Q
   double* tv = Qr + pe * ell;  // per panel: tau[ell], vhead[ell]
-  hh_panel_kernel<<<dim3(P), dim3(256), 0, st>>>(X, ldx, rows, ell, h, P, work, ldw, Rs, tv, status);
+  hh_panel_kernel<<<dim3(P), dim3(256), 0, st>>>(X, ldx, rows, ell, tr.h, P, tr.lds, work, ldw, Rs, tv,
+                                                 status);
   householder_kernel<<<dim3(1), dim3(1024), 0, st>>>(Rs, pe, pe, ell, Rw, pe, Qr, pe, nullptr, 0, R,
                                                      status);
-  hh_expand_kernel<<<dim3(P), dim3(256), 0, st>>>(work, ldw, rows, ell, h, P, Qr, tv, Q, ldq, Q32, ldq32,
-                                                  status);
+  hh_expand_kernel<<<dim3(P), dim3(256), 0, st>>>(work, ldw, rows, ell, tr.h, P, tr.lds, Qr, tv, Q, ldq,
+                                                  Q32, ldq32, status);
   return hipGetLastError();
 }
 
