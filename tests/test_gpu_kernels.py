@@ -94,9 +94,10 @@ def test_tsqr_matches_householder(ctx, rows, ell):
 @pytest.mark.parametrize("rows,ell,rank", [(3000, 30, 12), (2000, 64, 1), (500, 17, 16), (76800, 10, 5),
                                            (20037, 110, 60)])
 def test_tsqr_rank_deficient_falls_back(ctx, rows, ell, rank):
-    """Cholesky breaks down; the Householder tree (panels of max(256, 4 ell)
-    rows, the last one ragged; a single workgroup below two panels) gives an
-    orthonormal Q with X = QR.  The first `rank` columns of X are independent,
+    """Cholesky breaks down; the Householder tree (panels in LDS with the rows
+    split evenly: 3000x30, 500x17, 76800x10; device-memory panels of
+    max(256, 4 ell, sqrt(rows ell)) rows, the last one ragged: 2000x64,
+    20037x110) gives an orthonormal Q with X = QR.  The first `rank` columns of X are independent,
     so Q[:, :rank] and R[:rank] are unique and equal the oracle's."""
     _say("tsqr-deficient", rows, ell, rank)
     rng = np.random.default_rng(rows)
