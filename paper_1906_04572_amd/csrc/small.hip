@@ -808,7 +808,10 @@ __device__ void hh_apply(const double* __restrict__ W, int64_t ldw, int64_t rows
   }
 }
 
+constexpr int kHhLds = 7168;  // doubles of a matrix reduced in LDS (56 KB)
+
 // One workgroup: X (rows x ell) -> Q (diag R >= 0), R (nullable, ld ell).
+// X is reduced in LDS when it fits, else in the workspace W.
 __global__ void __launch_bounds__(1024) householder_kernel(const double* __restrict__ X,
                                                            int64_t ldx, int64_t rows, int ell,
                                                            double* __restrict__ W, int64_t ldw,
@@ -817,21 +820,25 @@ __global__ void __launch_bounds__(1024) householder_kernel(const double* __restr
                                                            double* __restrict__ R,
                                                            const int* status) {
   if ((*status & 3) != 1) return;  // only after a Cholesky breakdown
+  __shared__ double sw[kHhLds];
   __shared__ double tau[256], alpha[256], vhead[256];
   __shared__ double red[16];
   const int tid = threadIdx.x;
+  const bool lds = rows * ell <= kHhLds;
+  double* Wp = lds ? sw : W;
+  const int64_t ldp = lds ? rows : ldw;
   for (int64_t e = tid; e < rows * ell; e += 1024) {
     const int64_t i = e % rows;
     const int j = (int)(e / rows);
-    W[(int64_t)j * ldw + i] = X[(int64_t)j * ldx + i];
+    Wp[(int64_t)j * ldp + i] = X[(int64_t)j * ldx + i];
   }
   __syncthreads();
-  hh_factor<1024>(W, ldw, rows, ell, tau, alpha, vhead, red);
+  hh_factor<1024>(Wp, ldp, rows, ell, tau, alpha, vhead, red);
   // R (upper, ell x ell, column-major ld ell) with diag >= 0
   if (R) {
     for (int e = tid; e < ell * ell; e += 1024) {
       const int i = e % ell, j = e / ell;
-      double v = i < j ? W[(int64_t)j * ldw + i] : (i == j ? alpha[i] : 0.0);
+      double v = i < j ? Wp[(int64_t)j * ldp + i] : (i == j ? alpha[i] : 0.0);
       if (alpha[i] < 0.0) v = -v;
       R[e] = v;
     }
@@ -843,7 +850,7 @@ __global__ void __launch_bounds__(1024) householder_kernel(const double* __restr
     Q[(int64_t)j * ldq + i] = i == j ? 1.0 : 0.0;
   }
   __syncthreads();
-  hh_apply<1024>(W, ldw, rows, ell, tau, vhead, Q, ldq, true);
+  hh_apply<1024>(Wp, ldp, rows, ell, tau, vhead, Q, ldq, true);
   // sign normalisation diag(R) >= 0: flip the columns of Q with alpha < 0
   for (int64_t e = tid; e < rows * ell; e += 1024) {
     const int64_t i = e % rows;
@@ -862,8 +869,6 @@ __global__ void __launch_bounds__(1024) householder_kernel(const double* __restr
 // (b + 1) rows / P)); otherwise panel b is rows [b h, b h + h) of the
 // workspace copy, the last one taking the remainder.  Either way the
 // reflectors end in W (rows of the panel), where the expand step reads them.
-constexpr int kHhLds = 7168;  // doubles (56 KB)
-
 __device__ __forceinline__ void hh_panel_range(int b, int64_t rows, int64_t h, int P, int lds, int64_t& r0,
                                                int64_t& hb) {
   if (lds) {
