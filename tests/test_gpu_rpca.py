@@ -86,6 +86,27 @@ def test_table1_n1000_row(ctx):
     assert 8 <= info["iters"] <= 16
 
 
+def test_sparse_only_output_and_explicit_lambda(ctx):
+    """L is an output only: without it S, the residual and the iteration are
+    bit-identical.  An explicit lambda equal to the default 1/sqrt(max(m, n))
+    gives the same run; early stopping (tol) writes L at every iteration."""
+    _say("rpca without L, explicit lambda")
+    M, L, S = low_rank_plus_sparse(3000, 200, 5, 0.05, 50.0, seed=21, grid=GRID)
+    Md = _col(M)
+    L1, S1, i1 = ctx.rpca(Md, 5, 5, 1, seed=3, max_iter=30)
+    L2, S2, i2 = ctx.rpca(Md, 5, 5, 1, seed=3, max_iter=30, want_L=False)
+    L3, S3, i3 = ctx.rpca(Md, 5, 5, 1, seed=3, max_iter=30, lam=1.0 / np.sqrt(3000.0))
+    assert L2 is None
+    assert torch.equal(S1, S2) and torch.equal(S1, S3) and torch.equal(L1, L3)
+    assert i1["zeta"] == i2["zeta"] == i3["zeta"] and i1["final_rank"] == i2["final_rank"] == 5
+    # early stop: the L of the stopping iteration
+    L4, S4, i4 = ctx.rpca(Md, 5, 5, 1, seed=3, max_iter=60, tol=1e-9)
+    assert i4["iters"] < 60 and i4["zeta"] < 1e-9
+    L4, S4 = L4.cpu().numpy().astype(np.float64), S4.cpu().numpy().astype(np.float64)
+    assert np.array_equal(S4 != 0, S != 0)
+    assert np.linalg.norm(L4 - L) / np.linalg.norm(L) <= 1e-5
+
+
 def test_frames_full_76800x300(ctx):
     _say("rpca 76800x300 50 iterations")
     M, L, S = low_rank_plus_sparse(76800, 300, 5, 0.05, 50.0, seed=4, grid=GRID)
