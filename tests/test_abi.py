@@ -52,3 +52,20 @@ def test_null_arguments_are_rejected(lib):
     assert lib.corutv_create(None, None) == -1
     lib.corutv_destroy.argtypes = [ctypes.c_void_p]
     assert lib.corutv_destroy(None) == -1
+
+
+def test_binding_refuses_to_run_without_the_library(tmp_path):
+    """The product path has no CPU fallback: a copy of the binding with no
+    libcorutv.so beside it fails at import with a message naming the build."""
+    import shutil
+    import subprocess
+    import sys
+
+    pkg = tmp_path / "paper_1906_04572_amd"
+    pkg.mkdir()
+    shutil.copy(os.path.join(ROOT, "paper_1906_04572_amd", "__init__.py"), pkg / "__init__.py")
+    code = ("import sys; sys.path.insert(0, %r)\n"
+            "try:\n    import paper_1906_04572_amd\nexcept ImportError as e:\n    print('refused:', e)\n"
+            "else:\n    print('loaded')\n") % str(tmp_path)
+    out = subprocess.run([sys.executable, "-c", code], capture_output=True, text=True, timeout=300)
+    assert "refused:" in out.stdout and "not built" in out.stdout, (out.stdout, out.stderr)
