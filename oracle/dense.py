@@ -11,7 +11,10 @@
   downdating), ties go to the lowest current column position, and diag(R) is
   made non-negative at the end.  Every reduction is a sequential sum in row
   order of separately rounded products, so that the pivot sequence is a
-  deterministic function of the input bits.
+  deterministic function of the input bits.  An implementation that sums in
+  another order sees norms that differ by rounding; its pivots are compared
+  with these by replaying them (``follow``) and bounding, at every step, how
+  far its choice falls short of the largest norm.
 * ``jacobi_svd`` -- one-sided (Hestenes) Jacobi SVD, used only by the pins to
   get singular values (Eckart-Young optimum of eq. 3, interlacing checks).
 """
@@ -60,47 +63,53 @@ def householder_qr(X):
     return Q, R
 
 
-def _sum4(terms, size):
-    """Four interleaved sequential partial sums of an ordered list of equally
-    shaped terms, combined as (a0 + a1) + (a2 + a3)."""
-    acc = [np.zeros(size) for _ in range(4)]
-    for k, t in enumerate(terms):
-        acc[k % 4] = acc[k % 4] + t
-    return (acc[0] + acc[1]) + (acc[2] + acc[3])
-
-
-def qrcp(D):
-    """Column-pivoted QR of a square matrix: D[:, piv] = Qt @ R.
+def qrcp(D, follow=None, trace=None):
+    """Column-pivoted QR of a square matrix: D[:, piv] = Qt @ R (eq. 8).
 
     Returns (Qt orthogonal, R upper triangular with diag >= 0 and
     |R[0,0]| >= |R[1,1]| >= ..., piv int32 with D[:, piv] = Qt R).
 
-    Arithmetic order (fixed, so pivots depend only on the input bits; every
-    product and sum separately rounded).  sum4 over an ordered list of terms
-    means: a_k = sequential sum (from 0) of the terms at positions k, k+4,
-    k+8, ... (k = 0..3), result (a_0 + a_1) + (a_2 + a_3).
-      tails:  t_j = sum4 of W[i,j]*W[i,j] over i = s+1..l-1
-      norms:  acc_j = W[s,j]*W[s,j] + t_j
-      pivot:  first j >= s with the largest acc_j
-      reflector on x = W[s:, s] (after the swap):  nrm = sqrt(acc_p);
+    Businger-Golub: at step s the trailing column of largest Euclidean norm
+    is swapped to position s and a Householder reflector annihilates it below
+    the diagonal.  The arithmetic is the plain one, in a fixed order:
+      norms:  acc_j = 0; for i = s..l-1: acc_j = acc_j + W[i,j]*W[i,j]
+      pivot:  first j >= s with the largest acc_j (ties: lowest position)
+      reflector on x = W[s:, s] (after the swap): nrm = sqrt(acc_p);
               alpha = -nrm if x0 >= 0 else nrm; v = x with v0 = x0 - alpha;
-              vtv = v0*v0 + t_p; tau = 2 / vtv
-      update: d_j = sum4 of v_i*W[s+i,j] over i = 0..l-s-1;  f_j = d_j*tau;
+              vtv = sequential sum of v_i*v_i; tau = 2 / vtv
+      update: d_j = sequential sum over i of v_i*W[s+i,j]; f_j = d_j*tau;
               W[s+i,j] = W[s+i,j] - f_j*v_i
     Qt = H_0 H_1 ... H_{l-1} (H_s = I - tau_s v_s v_s^T) is formed after the
     loop; it does not influence the pivots.
+
+    follow: optional sequence of original column indices.  At step s the
+    column D[:, follow[s]] is taken instead of the argmax (every other step
+    of the arithmetic is unchanged).  This replays another implementation's
+    pivot sequence so that, at every step, its choice can be compared with
+    the largest norm this arithmetic sees.
+    trace: optional list; for every step the tuple (acc, chosen position - s)
+    is appended, acc being the squared norms of the trailing columns
+    (positions s..l-1) before the swap.
     """
     W = np.array(D, dtype=np.float64, copy=True)
     l = W.shape[0]
     if W.shape != (l, l):
         raise ValueError("qrcp expects a square matrix")
     piv = np.arange(l, dtype=np.int32)
-    Qt = np.eye(l)
     reflectors = []
     for s in range(l):
-        tail = _sum4([W[i, s:] * W[i, s:] for i in range(s + 1, l)], l - s)
-        acc = W[s, s:] * W[s, s:] + tail
-        p = s + int(np.argmax(acc))
+        acc = np.zeros(l - s)
+        for i in range(s, l):
+            acc = acc + W[i, s:] * W[i, s:]
+        if follow is None:
+            p = s + int(np.argmax(acc))
+        else:
+            where = np.nonzero(piv[s:] == int(follow[s]))[0]
+            if where.size != 1:
+                raise ValueError("follow is not a permutation of the column indices")
+            p = s + int(where[0])
+        if trace is not None:
+            trace.append((acc.copy(), p - s))
         if p != s:
             W[:, [s, p]] = W[:, [p, s]]
             piv[[s, p]] = piv[[p, s]]
@@ -111,16 +120,21 @@ def qrcp(D):
         alpha = -nrm if x0 >= 0 else nrm
         v = W[s:, s].copy()
         v[0] = x0 - alpha
-        vtv = v[0] * v[0] + tail[p - s]
+        vtv = 0.0
+        for vi in v:
+            vtv = vtv + vi * vi
         tau = 2.0 / vtv
         if s + 1 < l:
-            d = _sum4([v[i] * W[s + i, s + 1:] for i in range(l - s)], l - s - 1)
+            d = np.zeros(l - s - 1)
+            for i in range(l - s):
+                d = d + v[i] * W[s + i, s + 1:]
             f = d * tau
             for i in range(l - s):
                 W[s + i, s + 1:] = W[s + i, s + 1:] - f * v[i]
         W[s, s] = alpha
         W[s + 1:, s] = 0.0
         reflectors.append((s, v, tau))
+    Qt = np.eye(l)
     for s, v, tau in reversed(reflectors):  # Qt = H_0 (H_1 (... H_{l-1}))
         Qt[s:, :] -= np.outer(v, tau * (v @ Qt[s:, :]))
     R = np.triu(W)

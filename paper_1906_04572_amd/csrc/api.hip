@@ -1329,8 +1329,8 @@ extern "C" int corutv_rpca(corutv_ctx* ctx, const corutv_mat* M, double lambda, 
       if (hipEventElapsedTime(&em, ctx->ev_pool[2 * j], ctx->ev_pool[2 * j + 1]) == hipSuccess) step_ms += em;
     }
   }
-  int r = 0;
-  while (r < ell && Th[(size_t)r * ell + r] > 1.0 / mu_last) ++r;
+  int r = 0;  // diagonal entries above the last threshold (eq. 12)
+  for (int i = 0; i < ell; ++i) r += Th[(size_t)i * ell + i] > 1.0 / mu_last ? 1 : 0;
   if (info) {
     info->step_ms = step_ms;
     info->iters = iters;

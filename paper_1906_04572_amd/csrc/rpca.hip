@@ -1,8 +1,8 @@
 // ALM-CoRUTV robust PCA, elementwise part (Sec. 4, Algorithm 2; eq. 12 and
 // the shrinkage operator).  One pass over the m x n data per iteration j:
 //
-//   r   = number of diagonal entries of T above 1/mu_j (a prefix: diag(T) is
-//         non-negative and non-increasing)
+//   r   = number of diagonal entries of T above 1/mu_j (for the non-negative,
+//         non-increasing diagonal of a QRCP these are the first r)
 //   L   = sum_{a < r} P[i, a] Q[j, a]   (P = U, Q = V T^T for an upper T;
 //         P = U T, Q = V for a lower T -- the rank-r CoR-UTV thresholding)
 //   x   = M - L + Y / mu_j
@@ -59,11 +59,11 @@ constexpr int kLines = 8;
 __global__ void __launch_bounds__(256) rpca_step_kernel(RpcaArgs a) {
   __shared__ int rs;
   __shared__ double red[256];
-  if (threadIdx.x == 0) rs = a.ell;
+  if (threadIdx.x == 0) rs = 0;
   __syncthreads();
-  // r: the first diagonal entry of T not above 1/mu (diag(T) is a prefix)
-  if ((int)threadIdx.x < a.ell && !(a.T[(int64_t)threadIdx.x * a.ldt + threadIdx.x] > a.inv_mu))
-    atomicMin(&rs, (int)threadIdx.x);
+  // r: how many diagonal entries of T exceed 1/mu (eq. 12)
+  if ((int)threadIdx.x < a.ell && a.T[(int64_t)threadIdx.x * a.ldt + threadIdx.x] > a.inv_mu)
+    atomicAdd(&rs, 1);
   __syncthreads();
   const int r = rs;
   const bool colmaj = a.lay_m == CORUTV_COL_MAJOR;

@@ -6,7 +6,9 @@
   the FP32 accumulation bound, both layouts, ragged and misaligned sizes.
 * Thin QR (CholeskyQR2 / Householder fallback): equal to the oracle's
   Householder Q (unique with diag R > 0) within 1e-12; orthonormal to 1e-13.
-* QRCP of the core: identical pivots when fed the oracle's input bits.
+* QRCP of the core, fed the oracle's input bits: the kernel's pivots are the
+  oracle's at every step not decided by a near tie (margin rule), and its
+  factorization is exact to rounding.
 """
 import numpy as np
 import pytest
@@ -131,14 +133,35 @@ def _cores():
 
 
 @pytest.mark.parametrize("name,D", _cores(), ids=[c[0] for c in _cores()])
-def test_qrcp_pivots_bit_exact(ctx, name, D):
+def test_qrcp_pivots_margin_rule(ctx, name, D):
+    """Identical input bits: the kernel sums column norms in four interleaved
+    partial sums, the oracle sequentially, so norms differ by rounding.  The
+    kernel's pivot sequence is replayed in the oracle's arithmetic; at every
+    step its choice must be the oracle's largest norm unless the two norms are
+    within tau = 8 l u max_j ||D_j|| (near ties are listed, not failed).
+    When the sequences agree, R and Qt agree to the rounding of the
+    factorization."""
+    from tests.pivots import margin_tau, pivot_margins
+
     _say("qrcp", name, D.shape)
     Qt, R, piv = ctx.qrcp(torch.from_numpy(np.ascontiguousarray(D)).cuda())
+    Qt, R, piv = Qt.cpu().numpy(), R.cpu().numpy(), piv.cpu().numpy()
+    tau = margin_tau(D)
+    near = pivot_margins(D, piv, tau)
+    print("near-tie steps (step, norm gap):", near, "tau %.3e" % tau)
     Qto, Ro, pivo = qrcp(D)
-    np.testing.assert_array_equal(piv.cpu().numpy(), pivo)
-    # same arithmetic order: R and Qt agree to the last bits
-    np.testing.assert_allclose(R.cpu().numpy(), Ro, rtol=0, atol=1e-13 * max(1.0, np.abs(D).max()))
-    np.testing.assert_allclose(Qt.cpu().numpy(), Qto, rtol=0, atol=1e-12)
+    ell = D.shape[0]
+    scale = max(1.0, np.abs(D).max())
+    # the kernel's own factorization is exact to rounding whatever the pivots
+    assert np.max(np.abs(Qt @ R - D[:, piv])) <= 1e-13 * ell * scale
+    assert np.max(np.abs(Qt.T @ Qt - np.eye(ell))) <= 1e-14 * ell
+    assert np.all(np.tril(R, -1) == 0) and np.all(np.diag(R) >= 0)
+    if np.array_equal(piv, pivo):
+        np.testing.assert_allclose(R, Ro, rtol=0, atol=1e-13 * ell * scale)
+        if name != "rank6" and name != "ties":  # trailing reflectors of a zero block are arbitrary
+            np.testing.assert_allclose(Qt, Qto, rtol=0, atol=1e-10)
+    else:
+        assert near, "pivots differ although no step is a near tie"
 
 
 BF_CASES = [

@@ -258,3 +258,44 @@ def test_core_from_rz_gives_the_same_factorization(m, n, q, tri):
     np.testing.assert_array_equal(a["piv"][:10], b["piv"][:10])
     with pytest.raises(ValueError):
         corutv(A, 15, 5, q, seed=7, mode="literal", core="rz")
+
+
+@pytest.mark.parametrize("m,n,tri", [(150, 260, "auto"), (260, 150, "lower"), (260, 150, "upper")])
+def test_truncation_is_a_projection_of_the_approximation(m, n, tri):
+    """Rank-r truncation (Sec. 5.2, eq. 12).  Upper T keeps the first r rows
+    of T, which is the projection U_r U_r^T A_hat onto the leading left
+    vectors; lower T (the transposed problem) keeps the first r columns, the
+    projection A_hat V_r V_r^T.  Both follow from U, V orthonormal and T
+    triangular, independently of how truncate() is written; a row truncation
+    applied to a lower T is a different matrix and must not pass."""
+    A = decaying(m, n, 80, 1e-3, seed=m + 2 * n, kind="exp", tau=6.0)
+    res = corutv(A, 15, 5, 1, seed=4, tri=tri)
+    U, T, V = res["U"], res["T"], res["V"]
+    lower = bool(np.all(np.triu(T, 1) == 0))
+    assert lower == (tri == "lower" or (tri == "auto" and m < n))
+    Ah = U @ T @ V.T
+    nA = np.linalg.norm(A)
+    for r in (1, 7, 20):
+        got = truncate(U, T, V, r, "lower" if lower else "upper")
+        if lower:
+            want = Ah @ V[:, :r] @ V[:, :r].T
+            wrong = U[:, :r] @ T[:r, :] @ V.T
+        else:
+            want = U[:, :r] @ (U[:, :r].T @ Ah)
+            wrong = U @ T[:, :r] @ V[:, :r].T
+        assert np.linalg.norm(got - want) <= 1e-13 * nA
+        if r < 20:
+            assert np.linalg.norm(wrong - want) > 1e-6 * nA
+    assert np.linalg.norm(truncate(U, T, V, 20, "lower" if lower else "upper") - Ah) <= 1e-14 * nA
+
+
+def test_truncation_of_the_wide_problem_is_the_transposed_tall_one():
+    """The lower-T truncation of a wide A equals the upper-T truncation of
+    the tall A^T, transposed (P13 carried through eq. 12)."""
+    A = decaying(120, 300, 40, 1e-4, seed=8)
+    a = corutv(A, 10, 5, 1, seed=9)
+    b = corutv(A.T.copy(), 10, 5, 1, seed=9, tri="upper")
+    for r in (1, 6, 15):
+        x = truncate(a["U"], a["T"], a["V"], r, "lower")
+        y = truncate(b["U"], b["T"], b["V"], r, "upper")
+        assert np.linalg.norm(x - y.T) <= 1e-14 * np.linalg.norm(A)

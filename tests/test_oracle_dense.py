@@ -93,3 +93,57 @@ def test_jacobi_svd_vs_numpy(m, n):
     ref = np.linalg.svd(A, compute_uv=False)
     np.testing.assert_allclose(s, ref, rtol=1e-12, atol=1e-13 * ref[0])
     np.testing.assert_allclose(U @ np.diag(s) @ V.T, A, atol=1e-12 * ref[0])
+
+
+def test_qrcp_replay_of_its_own_pivots_is_bit_identical():
+    """follow= with the oracle's own pivots changes nothing, and the trace
+    shows the argmax chosen at every step."""
+    D = np.random.default_rng(13).standard_normal((37, 37)) * np.logspace(0, -5, 37)
+    a = qrcp(D)
+    trace = []
+    b = qrcp(D, follow=a[2], trace=trace)
+    for x, y in zip(a, b):
+        np.testing.assert_array_equal(x, y)
+    assert len(trace) == 37
+    assert all(int(np.argmax(acc)) == c for acc, c in trace)
+    with pytest.raises(ValueError):
+        qrcp(D, follow=np.zeros(37, dtype=np.int32))
+
+
+def test_qrcp_replay_of_other_pivots_is_still_a_factorization():
+    """Any pivot sequence gives D[:, piv] = Qt R with orthogonal Qt."""
+    rng = np.random.default_rng(14)
+    D = rng.standard_normal((20, 20))
+    order = rng.permutation(20).astype(np.int32)
+    Qt, R, piv = qrcp(D, follow=order)
+    np.testing.assert_array_equal(piv, order)
+    assert np.max(np.abs(Qt @ R - D[:, piv])) < 1e-13
+    assert np.max(np.abs(Qt.T @ Qt - np.eye(20))) < 1e-14
+
+
+def test_pivot_margin_rule_accepts_rounding_and_catches_wrong_pivots():
+    """The margin rule used to compare QRCP implementations: a QRCP whose
+    norms are summed in another order (here: reversed row order, the same
+    factorization otherwise) passes, listing at most a few near-tie steps; a
+    sequence with two decided pivots exchanged, or ordered by smallest norm,
+    fails."""
+    from tests.pivots import margin_tau, pivot_margins
+
+    rng = np.random.default_rng(15)
+    l = 60
+    D = rng.standard_normal((l, l)) * np.logspace(0, -8, l)[rng.permutation(l)]
+    tau = margin_tau(D)
+    # reversed summation order: the oracle on the row-reversed matrix sums
+    # every column norm in the opposite order and has the same pivots up to
+    # rounding (a row permutation leaves column norms unchanged)
+    piv_rev = qrcp(D[::-1].copy())[2]
+    near = pivot_margins(D, piv_rev, tau)
+    assert len(near) <= 2
+    piv = qrcp(D)[2]
+    bad = piv.copy()
+    bad[[3, 4]] = bad[[4, 3]]
+    with pytest.raises(AssertionError):
+        pivot_margins(D, bad, tau)
+    worst = np.argsort(np.linalg.norm(D, axis=0)).astype(np.int32)
+    with pytest.raises(AssertionError):
+        pivot_margins(D, worst, tau)

@@ -26,11 +26,16 @@ def test_shrink_closed_form():
     assert np.all(shrink(x, 0.0) == x)
 
 
-def test_threshold_rank_is_strict_prefix_count():
+def test_threshold_rank_counts_diagonal_entries_above_delta():
+    """eq. 12 keeps the diagonal entries of T greater than delta (strictly);
+    the count is taken over the whole diagonal, which for the non-increasing
+    diagonal of a QRCP is a prefix."""
     T = np.diag([5.0, 3.0, 1.0, 1.0, 0.5])
     assert threshold_rank(T, 1.0) == 2
     assert threshold_rank(T, 0.4) == 5
     assert threshold_rank(T, 9.0) == 0
+    # a diagonal that rounding left out of order: every entry above delta counts
+    assert threshold_rank(np.diag([5.0, 1.0, 3.0]), 2.0) == 2
 
 
 def _rows():
@@ -63,3 +68,20 @@ def test_frames_shaped_rpca_recovers_support():
     # support: the exact nonzeros of S* equal the planted ones
     assert np.array_equal(Sh != 0, S != 0)
     assert info["ranks"][-1] == 5
+
+
+@pytest.mark.parametrize("m,n", [(120, 3000), (900, 1300)])
+def test_wide_input_is_the_transposed_problem(m, n):
+    """A wide M runs CoR-UTV on the transposed problem (lower T, Sec. 3), and
+    its thresholding keeps the columns of T (eq. 12 on the transposed
+    problem).  Every operator of Algorithm 2 commutes with transposition, so
+    the run on M^T equals the transposed run on M, up to the rounding of
+    associating the rank-r products differently."""
+    Mw, L, S = low_rank_plus_sparse(m, n, 4, 0.05, 20.0, seed=m + n)
+    a_L, a_S, a = alm_corutv(Mw, 4, 4, 1, seed=3, max_iter=25)
+    b_L, b_S, b = alm_corutv(Mw.T.copy(), 4, 4, 1, seed=3, max_iter=25)
+    assert a["ranks"] == b["ranks"]
+    assert np.array_equal(a_S != 0, b_S.T != 0)
+    nL = np.linalg.norm(b_L)
+    assert np.linalg.norm(a_L - b_L.T) <= 1e-12 * nL
+    assert np.linalg.norm(a_S - b_S.T) <= 1e-12 * nL
