@@ -26,6 +26,11 @@
  *     are unspecified.  CORUTV_E_DEVICE poisons the context (destroy it).
  *   - Blocking calls enqueue on the context's first stream and synchronize it
  *     before returning.
+ *   - Workspace: blocking calls and serving requests take their scratch
+ *     ranges from one first-fit arena over the workspace, under the context's
+ *     lock, so they never overlap.  A blocking call made while requests are
+ *     in flight waits until its range is free (new admissions pause until
+ *     it has one) and then runs beside them.
  */
 #ifndef CORUTV_H
 #define CORUTV_H
@@ -53,8 +58,11 @@ enum corutv_layout { CORUTV_COL_MAJOR = 0, CORUTV_ROW_MAJOR = 1 };
 /* Arithmetic of the passes over A (sketches, power products, core pass).
  * F64: double operands on FP64 matrix cores.  F32: float operands on FP32
  * matrix cores.  BF16: float A and operands rounded to nearest-even bfloat16
- * in the tile loader, FP32 accumulation.  BF16X3: x = hi + lo split into two
- * bfloat16 parts, lo*hi + hi*lo + hi*hi accumulated in FP32.  In every form
+ * in the tile loader, FP32 accumulation, for the first sketch and the power
+ * iterations; the second sketch Z = A^T Q1 and the core pass A Q2, which give
+ * the returned factors directly, run in the BF16X3 form.  BF16X3: every pass
+ * splits x = hi + lo into two bfloat16 parts and accumulates
+ * lo*hi + hi*lo + hi*hi in FP32.  In every form
  * the Gram matrices, Cholesky factors, the l x l core and its QRCP are FP64.
  * F64 needs an F64 A; F32/BF16/BF16X3 need an F32 A.
  * The thin QRs of the sketches are CholeskyQR2 (two CholeskyQR steps).  In
@@ -214,7 +222,9 @@ uint64_t corutv_rpca_workspace_bytes(int64_t m, int64_t n, int32_t k, int32_t p,
  * concurrently on different streams.  Kernel configurations depend only on
  * the request's shape, so a result is bit-identical alone and in a mix.
  * The request descriptor is copied; A, U, T, V and piv must stay valid and
- * unmodified until the ticket completes. */
+ * unmodified until the ticket completes.  The request is ordered after the
+ * work queued on the context stream (streams[0]) when corutv_submit is
+ * called: an event recorded there is waited for before its first kernel. */
 typedef struct corutv_request {
   corutv_mat A;
   corutv_mat U;
@@ -228,8 +238,9 @@ typedef struct corutv_request {
   corutv_opts opts;
 } corutv_request;
 
-/* Returns OK (admitted or queued), E_BUSY (queue full), E_NOMEM (footprint
- * larger than the whole workspace: can never run) or E_INVAL. */
+/* Returns OK (admitted or queued), E_BUSY (queue full: max_queue requests
+ * waiting for admission), E_NOMEM (footprint larger than the whole
+ * workspace: can never run) or E_INVAL. */
 int corutv_submit(corutv_ctx* ctx, const corutv_request* req, uint64_t* ticket);
 /* PENDING while queued or running; OK once outputs are valid (info filled,
  * ticket retired); otherwise the request's error code (ticket retired).
@@ -255,6 +266,13 @@ typedef struct corutv_pass_stats {
   double max_ms;       /* slowest single pass                             */
 } corutv_pass_stats;
 int corutv_pass_timing(corutv_ctx* ctx, int32_t enable, int32_t reset);
+/* Test hook for the error path: the after_checks-th next launch check of a
+ * call on this context (counting from 1) reports a HIP error, as a failed
+ * launch would: that call returns CORUTV_E_DEVICE and poisons the context
+ * (every later call returns CORUTV_E_DEVICE, queued requests complete with
+ * it).  No device fault is caused; kernels already queued run normally.
+ * 0 disarms. */
+int corutv_debug_inject_failure(corutv_ctx* ctx, int32_t after_checks);
 int corutv_get_pass_stats(corutv_ctx* ctx, corutv_pass_stats* out);
 
 /* ---- single steps (parity checks and diagnostics) -----------------------

@@ -106,6 +106,7 @@ def _load():
         "corutv_rpca_workspace_bytes": (U64, [I64, I64, I32, I32, I32]),
         "corutv_pass_timing": (ctypes.c_int, [P, I32, I32]),
         "corutv_get_pass_stats": (ctypes.c_int, [P, ctypes.POINTER(PassStats)]),
+        "corutv_debug_inject_failure": (ctypes.c_int, [P, I32]),
     }
     for name, (res, args) in sig.items():
         f = getattr(lib, name)
@@ -281,6 +282,10 @@ class Context:
     # -- measurement ----------------------------------------------------------
     def pass_timing(self, enable=True, reset=True):
         _check(lib.corutv_pass_timing(self.h, 1 if enable else 0, 1 if reset else 0), "pass_timing")
+
+    def inject_failure(self, after_checks):
+        """Test hook: the n-th next launch check fails as a HIP error would."""
+        _check(lib.corutv_debug_inject_failure(self.h, after_checks), "inject_failure")
 
     def pass_stats(self):
         st = PassStats()

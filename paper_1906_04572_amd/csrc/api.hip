@@ -18,6 +18,7 @@
 #include <thread>
 #include <vector>
 
+#include "arena.hpp"
 #include "internal.hpp"
 
 using namespace corutv;
@@ -154,6 +155,7 @@ struct corutv_ctx {
   char* ws = nullptr;
   size_t ws_bytes = 0;
   std::atomic<bool> poisoned{false};
+  std::atomic<int> inject_after{0};  // > 0: the n-th next launch check fails (test hook)
   std::mutex run_mu;  // serializes blocking calls on streams[0]
   // serving
   int max_queue = 4096;
@@ -166,7 +168,8 @@ struct corutv_ctx {
   std::thread sched;
   bool sched_started = false;
   std::vector<int> slot_busy;
-  std::vector<std::pair<size_t, size_t>> arena;  // allocated [off, off+size)
+  Arena arena;               // workspace ranges in use (requests and blocking calls)
+  int blocking_waiters = 0;  // blocking calls waiting for workspace: admissions pause
   int* host_status = nullptr;                    // pinned, kMaxQr per slot
   // pass timing (blocking decompositions only)
   bool timing = false;
@@ -182,10 +185,20 @@ struct corutv_ctx {
 
 namespace {
 
-#define HIPOK(expr)                                  \
-  do {                                               \
-    hipError_t e_ = (expr);                          \
-    if (e_ != hipSuccess) return CORUTV_E_DEVICE;    \
+// A launch check.  corutv_debug_inject_failure makes the n-th next check on a
+// context fail as a HIP error would, so the error path can be tested without
+// a real device fault.
+bool inject_hit(corutv_ctx* c) {
+  int v = c->inject_after.load();
+  while (v > 0 && !c->inject_after.compare_exchange_weak(v, v - 1)) {
+  }
+  return v == 1;
+}
+
+#define HIPOK(expr)                                                    \
+  do {                                                                 \
+    hipError_t e_ = (expr);                                            \
+    if (e_ != hipSuccess || inject_hit(ctx)) return CORUTV_E_DEVICE;  \
   } while (0)
 
 bool mat_ok(const corutv_mat* a) {
@@ -410,18 +423,24 @@ int enqueue_decompose(corutv_ctx* ctx, const Plan& pl, char* ws, const DecArgs& 
     }
     return hipSuccess;
   };
-  auto passA = [&](const void* opnd) {  // P X, X nn x ell -> mm x ell
+  // BF16: the sketches of the power loop run in BF16; the passes that give
+  // the returned factors directly -- the second sketch Z = P^T Q1 (whose QR
+  // is Q2) and the core pass P Q2 -- run in the split form (BF16X3), so the
+  // core is accurate to FP32 level and only the captured subspace carries
+  // the BF16 rounding of A.
+  const int prec_final = prec == P_BF16 ? P_BF16X3 : prec;
+  auto passA = [&](const void* opnd, int pr) {  // P X, X nn x ell -> mm x ell
     mark();
     hipError_t e = host_a ? stream_pass(tA, opnd, ldn, ldm)
-                          : launch_sketch(prec, tA, d.A.ptr, d.A.ld, Rb, Cb, opnd, ldn, ellp, part,
+                          : launch_sketch(pr, tA, d.A.ptr, d.A.ld, Rb, Cb, opnd, ldn, ellp, part,
                                           pl.part_elems, &pp, ctx->num_cu, s, ws + pl.o_sbf);
     mark();
     return e;
   };
-  auto passAt = [&](const void* opnd) {  // P^T Y, Y mm x ell -> nn x ell
+  auto passAt = [&](const void* opnd, int pr) {  // P^T Y, Y mm x ell -> nn x ell
     mark();
     hipError_t e = host_a ? stream_pass(tAt, opnd, ldm, ldn)
-                          : launch_sketch(prec, tAt, d.A.ptr, d.A.ld, Rb, Cb, opnd, ldm, ellp, part,
+                          : launch_sketch(pr, tAt, d.A.ptr, d.A.ld, Rb, Cb, opnd, ldm, ellp, part,
                                           pl.part_elems, &pp, ctx->num_cu, s, ws + pl.o_sbf);
     mark();
     return e;
@@ -429,21 +448,21 @@ int enqueue_decompose(corutv_ctx* ctx, const Plan& pl, char* ws, const DecArgs& 
   // Omega (nn x ell), then Q1 = qf(P Omega)
   HIPOK(launch_omega(nn, ell, ellp, d.seed, d.sub, f64 ? (double*)wop : nullptr,
                      f64 ? nullptr : (float*)wop, ldn, s));
-  HIPOK(passA(wop));
+  HIPOK(passA(wop, prec));
   HIPOK(qr_from_partials(pl, ws, pp, mm, ldm, q1, f64 ? nullptr : (float*)qop, st + nqr++, s, nullptr, !f64,
                          host_a));
   for (int it = 0; it < d.q; ++it) {
     // W = qf(P^T Q1); Q1 = qf(P W)
-    HIPOK(passAt(qsrc));
+    HIPOK(passAt(qsrc, prec));
     HIPOK(qr_from_partials(pl, ws, pp, nn, ldn, q2, f64 ? nullptr : (float*)wop, st + nqr++, s, nullptr, !f64,
                            host_a));
-    HIPOK(passA(wsrc));
+    HIPOK(passA(wsrc, prec));
     HIPOK(qr_from_partials(pl, ws, pp, mm, ldm, q1, f64 ? nullptr : (float*)qop, st + nqr++, s, nullptr, !f64,
                          host_a));
   }
   // Z = P^T Q1; Q2, R_Z = qf(Z)
   const bool core_rz = (d.opts.flags & CORUTV_FLAG_CORE_FROM_RZ) != 0;
-  HIPOK(passAt(qsrc));
+  HIPOK(passAt(qsrc, prec_final));
   HIPOK(qr_from_partials(pl, ws, pp, nn, ldn, q2, f64 ? nullptr : (float*)wop, st + nqr++, s,
                          core_rz ? core : nullptr, !f64, host_a));
   if (core_rz) {
@@ -452,7 +471,7 @@ int enqueue_decompose(corutv_ctx* ctx, const Plan& pl, char* ws, const DecArgs& 
     HIPOK(launch_qrcp(core, ell, lower_inner ? 0 : 1, ell, qt, rt, piv, qw, s));
   } else {
     // core D = Q1^T (P Q2)
-    HIPOK(passA(wsrc));
+    HIPOK(passA(wsrc, prec_final));
     if (!host_a) HIPOK(launch_sum_partials(pp, ell, ellp, x0, nullptr, ldm, s));
     const int sp = xty_splits(mm, ell);
     HIPOK(launch_xty(q1, ldm, x0, ldm, mm, ell, xp, sp, nullptr, s));
@@ -557,6 +576,42 @@ int poison(corutv_ctx* ctx) {
   return CORUTV_E_DEVICE;
 }
 
+// A blocking call's range of the workspace.  It is taken from the same arena
+// as the serving requests' ranges (under the context mutex, waiting while
+// requests in flight hold the space; the scheduler admits nothing new
+// meanwhile), so a blocking call never overlaps a request's scratch, and is
+// returned when the call ends.
+struct WsLease {
+  corutv_ctx* c = nullptr;
+  size_t off = 0;
+  bool held = false;
+  char* base() const { return c->ws + off; }
+  ~WsLease() {
+    if (!held) return;
+    std::lock_guard<std::mutex> lk(c->mu);
+    c->arena.release(off);
+    c->cv.notify_all();
+  }
+};
+
+int lease_ws(corutv_ctx* c, size_t bytes, WsLease* l) {
+  if (bytes > c->ws_bytes) return CORUTV_E_NOMEM;
+  std::unique_lock<std::mutex> lk(c->mu);
+  ++c->blocking_waiters;
+  bool got = false;
+  c->cv.wait(lk, [&] {
+    if (c->poisoned.load()) return true;
+    got = c->arena.alloc(bytes, &l->off);
+    return got;
+  });
+  --c->blocking_waiters;
+  c->cv.notify_all();
+  if (!got) return CORUTV_E_DEVICE;
+  l->c = c;
+  l->held = true;
+  return CORUTV_OK;
+}
+
 }  // namespace
 
 // ---------------------------------------------------------------------------
@@ -612,6 +667,7 @@ int corutv_create(corutv_ctx** out, const corutv_config* cfg) {
   for (int i = 0; i < cfg->n_streams; ++i) c->streams.push_back((hipStream_t)cfg->streams[i]);
   c->ws = (char*)cfg->workspace;
   c->ws_bytes = cfg->workspace_bytes;
+  c->arena.reset(c->ws_bytes);
   c->max_queue = cfg->max_queue > 0 ? cfg->max_queue : 4096;
   const int slots = std::max(1, cfg->n_streams - 1);
   c->slot_busy.assign(slots, 0);
@@ -653,6 +709,8 @@ int corutv_decompose(corutv_ctx* ctx, const corutv_mat* A, int32_t k, int32_t p,
   }
   if (pl.total > ctx->ws_bytes) return CORUTV_E_NOMEM;
   std::lock_guard<std::mutex> lk(ctx->run_mu);
+  WsLease lease;
+  if ((rc = lease_ws(ctx, pl.total, &lease)) != CORUTV_OK) return rc;
   hipStream_t s = ctx->streams[0];
   if (host_a && !ctx->copy_stream) {
     if (hipStreamCreateWithFlags(&ctx->copy_stream, hipStreamNonBlocking) != hipSuccess) return poison(ctx);
@@ -675,7 +733,7 @@ int corutv_decompose(corutv_ctx* ctx, const corutv_mat* A, int32_t k, int32_t p,
   }
   std::vector<hipEvent_t> pev;
   if (ctx->timing) pev.assign(ctx->ev_pool.begin(), ctx->ev_pool.begin() + 2 * npass);
-  rc = enqueue_decompose(ctx, pl, ctx->ws, d, s, &eq, ctx->timing ? &pev : nullptr);
+  rc = enqueue_decompose(ctx, pl, lease.base(), d, s, &eq, ctx->timing ? &pev : nullptr);
   if (rc == CORUTV_E_DEVICE) return poison(ctx);
   if (rc != CORUTV_OK) return rc;
   hipEventRecord(e1, s);
@@ -743,9 +801,11 @@ int corutv_sketch(corutv_ctx* ctx, const corutv_mat* A, int32_t trans, int32_t p
                       (bf ? align256(sketch_bf16_bytes(ellp, ldk)) : 0);
   if (need > ctx->ws_bytes) return CORUTV_E_NOMEM;
   std::lock_guard<std::mutex> lk(ctx->run_mu);
+  WsLease lease;
+  if ((rc = lease_ws(ctx, need, &lease)) != CORUTV_OK) return rc;
   hipStream_t s = ctx->streams[0];
-  char* xs = ctx->ws;
-  char* part = ctx->ws + align256((size_t)ellp * ldk * es);
+  char* xs = lease.base();
+  char* part = xs + align256((size_t)ellp * ldk * es);
   char* sbf = part + align256((size_t)cap * es);
   HIPOK(hipMemsetAsync(xs, 0, (size_t)ellp * ldk * es, s));
   HIPOK(hipMemcpy2DAsync(xs, ldk * es, X, ldx * es, klen * es, ell, hipMemcpyDeviceToDevice, s));
@@ -781,8 +841,10 @@ int corutv_tsqr(corutv_ctx* ctx, const double* X, int64_t rows, int32_t ell, int
                o_st = take(64), o_cw = take(chol_work_bytes(ell)), o_hh = take(hh_work_bytes(rows, ell));
   if (off > ctx->ws_bytes) return CORUTV_E_NOMEM;
   std::lock_guard<std::mutex> lk(ctx->run_mu);
+  WsLease lease;
+  if ((rc = lease_ws(ctx, off, &lease)) != CORUTV_OK) return rc;
   hipStream_t s = ctx->streams[0];
-  char* w = ctx->ws;
+  char* w = lease.base();
   double *x0 = (double*)(w + o_x0), *x1 = (double*)(w + o_x1), *qq = (double*)(w + o_q),
          *xp = (double*)(w + o_xp), *G = (double*)(w + o_g), *R1 = (double*)(w + o_r1),
          *R2 = (double*)(w + o_r2), *Ri = (double*)(w + o_ri), *Rh = (double*)(w + o_rh);
@@ -832,10 +894,13 @@ int corutv_qrcp(corutv_ctx* ctx, int32_t ell, const double* D, int64_t ldd, doub
   int rc = guard(ctx);
   if (rc) return rc;
   if (ell < 1 || ell > 256 || !D || !Qt || !R || !piv || ldd < ell) return CORUTV_E_INVAL;
-  if (((size_t)2 * ell * ell + 2 * ell) * 8 > ctx->ws_bytes) return CORUTV_E_NOMEM;
+  const size_t need = ((size_t)2 * ell * ell + 2 * ell) * 8;
+  if (need > ctx->ws_bytes) return CORUTV_E_NOMEM;
   std::lock_guard<std::mutex> lk(ctx->run_mu);
+  WsLease lease;
+  if ((rc = lease_ws(ctx, need, &lease)) != CORUTV_OK) return rc;
   hipStream_t s = ctx->streams[0];
-  HIPOK(launch_qrcp(D, ldd, 0, ell, Qt, R, piv, (double*)ctx->ws, s));
+  HIPOK(launch_qrcp(D, ldd, 0, ell, Qt, R, piv, (double*)lease.base(), s));
   if (hipStreamSynchronize(s) != hipSuccess) return poison(ctx);
   return CORUTV_OK;
 }
@@ -854,36 +919,19 @@ struct Job {
   int slot = -1;
   size_t off = 0;
   hipEvent_t e0 = nullptr, e1 = nullptr;
+  // recorded on the context stream at submit: the request starts after the
+  // work the caller had queued there (its inputs and zero-filled outputs)
+  hipEvent_t ready = nullptr;
   Enqueued eq;
+  ~Job() {
+    if (ready) hipEventDestroy(ready);
+  }
 };
 
 namespace {
 
 int* slot_status(corutv_ctx* c, int slot) { return c->host_status + (size_t)(slot + 1) * (kMaxQr + 8); }
 double* slot_sum(corutv_ctx* c, int slot) { return (double*)(slot_status(c, slot) + kMaxQr); }
-
-// first-fit allocation in the workspace; arena kept sorted by offset
-bool arena_alloc(corutv_ctx* c, size_t bytes, size_t* off) {
-  size_t cur = 0;
-  for (size_t i = 0; i <= c->arena.size(); ++i) {
-    const size_t end = i < c->arena.size() ? c->arena[i].first : c->ws_bytes;
-    if (end >= cur && end - cur >= bytes) {
-      c->arena.insert(c->arena.begin() + i, {cur, cur + bytes});
-      *off = cur;
-      return true;
-    }
-    if (i < c->arena.size()) cur = align256(c->arena[i].second);
-  }
-  return false;
-}
-
-void arena_free(corutv_ctx* c, size_t off) {
-  for (size_t i = 0; i < c->arena.size(); ++i)
-    if (c->arena[i].first == off) {
-      c->arena.erase(c->arena.begin() + i);
-      return;
-    }
-}
 
 hipStream_t slot_stream(corutv_ctx* c, int slot) {
   return c->streams.size() > 1 ? c->streams[1 + slot] : c->streams[0];
@@ -899,7 +947,7 @@ bool try_start(corutv_ctx* c, Job* j) {
     }
   if (slot < 0) return false;
   size_t off = 0;
-  if (!arena_alloc(c, j->pl.total, &off)) return false;
+  if (!c->arena.alloc(j->pl.total, &off)) return false;
   hipStream_t s = slot_stream(c, slot);
   j->slot = slot;
   j->off = off;
@@ -907,6 +955,7 @@ bool try_start(corutv_ctx* c, Job* j) {
   j->state = Job::RUNNING;
   int rc = CORUTV_OK;
   if (hipEventCreate(&j->e0) != hipSuccess || hipEventCreate(&j->e1) != hipSuccess) rc = CORUTV_E_DEVICE;
+  if (rc == CORUTV_OK && j->ready && hipStreamWaitEvent(s, j->ready, 0) != hipSuccess) rc = CORUTV_E_DEVICE;
   if (rc == CORUTV_OK) hipEventRecord(j->e0, s);
   if (rc == CORUTV_OK) rc = enqueue_decompose(c, j->pl, c->ws + off, j->d, s, &j->eq);
   if (rc == CORUTV_OK) {
@@ -924,7 +973,7 @@ bool try_start(corutv_ctx* c, Job* j) {
     j->rc = rc;
     j->state = Job::DONE;
     c->slot_busy[slot] = 0;
-    arena_free(c, off);
+    c->arena.release(off);
   }
   return true;
 }
@@ -938,8 +987,10 @@ void finish_job(corutv_ctx* c, Job* j) {
   j->info.ell = j->pl.ell;
   hipEventDestroy(j->e0);
   hipEventDestroy(j->e1);
+  if (j->ready) hipEventDestroy(j->ready);
+  j->ready = nullptr;
   c->slot_busy[j->slot] = 0;
-  arena_free(c, j->off);
+  c->arena.release(j->off);
   j->state = Job::DONE;
 }
 
@@ -961,13 +1012,20 @@ void scheduler(corutv_ctx* c) {
         j->rc = CORUTV_E_DEVICE;
         j->state = Job::DONE;
         c->slot_busy[j->slot] = 0;
-        arena_free(c, j->off);
+        c->arena.release(j->off);
         progress = true;
       }
     }
     // admissions, in arrival order (the head blocks later requests so that
     // large requests are not starved)
+    // (paused while a blocking call waits for workspace, so it gets the
+    // next range that frees up)
+    bool blocked = false;
     while (!c->queue.empty()) {
+      if (c->blocking_waiters > 0) {
+        blocked = true;
+        break;
+      }
       Job* j = c->queue.front();
       if (c->poisoned.load()) {
         j->rc = CORUTV_E_DEVICE;
@@ -976,7 +1034,10 @@ void scheduler(corutv_ctx* c) {
         progress = true;
         continue;
       }
-      if (!try_start(c, j)) break;
+      if (!try_start(c, j)) {
+        blocked = true;
+        break;
+      }
       c->queue.pop_front();
       progress = true;
     }
@@ -985,8 +1046,14 @@ void scheduler(corutv_ctx* c) {
     for (auto& kv : c->jobs)
       if (kv.second->state == Job::RUNNING) running = true;
     if (c->stop && c->queue.empty() && !running) break;
+    // Every wait releases the lock.  Running requests are polled; otherwise
+    // an admission blocked by a blocking call (waiting for workspace, or
+    // holding it) waits for that call's notification -- a predicate that
+    // is already true here would keep the lock and starve that call.
     if (running)
       c->cv.wait_for(lk, std::chrono::microseconds(20));
+    else if (blocked)
+      c->cv.wait(lk);
     else
       c->cv.wait(lk, [&] { return c->stop || !c->queue.empty(); });
   }
@@ -1025,6 +1092,11 @@ int corutv_submit(corutv_ctx* ctx, const corutv_request* req, uint64_t* ticket) 
   if (j->pl.total > ctx->ws_bytes) {
     delete j;
     return CORUTV_E_NOMEM;
+  }
+  if (hipEventCreateWithFlags(&j->ready, hipEventDisableTiming) != hipSuccess ||
+      hipEventRecord(j->ready, ctx->streams[0]) != hipSuccess) {
+    delete j;
+    return poison(ctx);
   }
   std::lock_guard<std::mutex> lk(ctx->mu);
   if ((int)ctx->queue.size() >= ctx->max_queue) {
@@ -1086,6 +1158,12 @@ int corutv_cancel(corutv_ctx* ctx, uint64_t ticket) {
   return CORUTV_OK;
 }
 
+int corutv_debug_inject_failure(corutv_ctx* ctx, int32_t after_checks) {
+  if (!ctx || after_checks < 0) return CORUTV_E_INVAL;
+  ctx->inject_after.store(after_checks);
+  return CORUTV_OK;
+}
+
 int corutv_pass_timing(corutv_ctx* ctx, int32_t enable, int32_t reset) {
   if (!ctx) return CORUTV_E_INVAL;
   std::lock_guard<std::mutex> lk(ctx->run_mu);
@@ -1143,7 +1221,7 @@ struct RpcaPlan {
   Plan dec;
   int ell = 0;
   size_t o_y = 0, o_b = 0, o_u = 0, o_v = 0, o_t = 0, o_tt = 0, o_p = 0, o_q = 0, o_part = 0,
-         o_sum = 0;
+         o_sum = 0, o_flag = 0;
   size_t total = 0;
 };
 
@@ -1167,6 +1245,7 @@ bool make_rpca_plan(int64_t m, int64_t n, int k, int p, int q, RpcaPlan* rp) {
   rp->o_q = take((size_t)n * ell * 8);
   rp->o_part = take((size_t)rpca_partial_blocks() * 8);
   rp->o_sum = take(4 * 8);
+  rp->o_flag = take(16);
   rp->total = off;
   return true;
 }
@@ -1198,8 +1277,10 @@ extern "C" int corutv_rpca(corutv_ctx* ctx, const corutv_mat* M, double lambda, 
   if (!(lambda > 0)) lambda = 1.0 / std::sqrt((double)std::max(m, n));
   const int ell = rp.ell;
   std::lock_guard<std::mutex> lk(ctx->run_mu);
+  WsLease lease;
+  if ((rc = lease_ws(ctx, rp.total, &lease)) != CORUTV_OK) return rc;
   hipStream_t s = ctx->streams[0];
-  char* ws = ctx->ws;
+  char* ws = lease.base();
   double* Y = (double*)(ws + rp.o_y);
   double* B = (double*)(ws + rp.o_b);
   double* U = (double*)(ws + rp.o_u);
@@ -1210,6 +1291,7 @@ extern "C" int corutv_rpca(corutv_ctx* ctx, const corutv_mat* M, double lambda, 
   double* Qm = (double*)(ws + rp.o_q);
   double* part = (double*)(ws + rp.o_part);
   double* sum = (double*)(ws + rp.o_sum);
+  int* sticky = (int*)(ws + rp.o_flag);  // OR of the loop's QR status words
   const int nb = rpca_partial_blocks();
   // Y and B share M's layout, packed
   const int lay = M->layout;
@@ -1238,6 +1320,7 @@ extern "C" int corutv_rpca(corutv_ctx* ctx, const corutv_mat* M, double lambda, 
     HIPOK(hipMemsetAsync(Y, 0, (size_t)m * n * 8, s));
   }
   HIPOK(launch_widen((const float*)M->ptr, lay, M->ld, m, n, B, ldi, s));
+  HIPOK(launch_fill_int(sticky, 1, 0, s));
   // ||M||_F
   HIPOK(launch_sumsq((const float*)M->ptr, lay, M->ld, m, n, part, s));
   HIPOK(launch_reduce(part, nb, 1, sum, nullptr, s));
@@ -1300,7 +1383,7 @@ extern "C" int corutv_rpca(corutv_ctx* ctx, const corutv_mat* M, double lambda, 
     HIPOK(launch_rpca_elementwise((const float*)M->ptr, lay, M->ld, (float*)S->ptr, S->layout, S->ld, Y,
                                   ldi, last ? nullptr : B, ldi, want_l ? (float*)L->ptr : nullptr,
                                   L ? L->layout : CORUTV_COL_MAJOR, L ? L->ld : 1, m, n, P, m, Q, n, T,
-                                  ell, ell, mu, mu_next, lambda, part, s));
+                                  ell, ell, mu, mu_next, lambda, part, eq.dev_status, eq.nqr, sticky, s));
     if (ctx->timing) hipEventRecord(ctx->ev_pool[2 * j + 1], s);
     HIPOK(launch_reduce(part, nb, 1, sum, nullptr, s));
     iters = j + 1;
@@ -1308,10 +1391,13 @@ extern "C" int corutv_rpca(corutv_ctx* ctx, const corutv_mat* M, double lambda, 
     mu = mu_next;
     if (tol > 0 || last) {
       double zs = 0;
+      int flags = 0;
       HIPOK(hipMemcpyAsync(&zs, sum, 8, hipMemcpyDeviceToHost, s));
+      HIPOK(hipMemcpyAsync(&flags, sticky, 4, hipMemcpyDeviceToHost, s));
       if (hipStreamSynchronize(s) != hipSuccess) return poison(ctx);
       zeta = std::sqrt(zs) / normM;
-      if (!std::isfinite(zeta)) return CORUTV_E_NUMERIC;
+      // a non-finite input to a QR of the loop (status bit 2) or residual
+      if ((flags & 2) || !std::isfinite(zeta)) return CORUTV_E_NUMERIC;
       if (tol > 0 && zeta < tol) break;
     }
   }

@@ -155,14 +155,16 @@ hipError_t launch_residual(const void* A, int dtype, int64_t lda, int64_t R, int
 // RPCA elementwise step (rpca.hip): S, Y (and B for the next iteration, L if
 // non-null) from M and the rank-r factors P (m x ell), Q (n x ell) with r the
 // number of diagonal entries of T above 1/mu; per-block sums of the squared
-// residual M - L - S go to part[rpca_partial_blocks()].
+// residual M - L - S go to part[rpca_partial_blocks()].  The nstatus status
+// words of the iteration's decomposition are OR-ed into *sticky (nullable).
 int rpca_partial_blocks();
 hipError_t launch_rpca_elementwise(const float* M, int lay_m, int64_t ldm, float* S, int lay_s,
                                    int64_t lds, double* Y, int64_t ldy, double* B, int64_t ldb, float* L,
                                    int lay_l, int64_t ldl, int64_t m, int64_t n, const double* P,
                                    int64_t ldp, const double* Q, int64_t ldq, const double* T,
                                    int64_t ldt, int ell, double mu, double mu_next, double lambda,
-                                   double* part, hipStream_t st);
+                                   double* part, const int* status, int nstatus, int* sticky,
+                                   hipStream_t st);
 hipError_t launch_sumsq(const float* X, int lay, int64_t ld, int64_t m, int64_t n, double* part,
                         hipStream_t st);
 hipError_t launch_widen(const float* X, int lay, int64_t ld, int64_t m, int64_t n, double* B, int64_t ldb,

@@ -42,6 +42,9 @@ struct RpcaArgs {
   double mu, mu_next, thresh;  // thresh = lambda / mu
   double inv_mu;               // 1 / mu (rank threshold)
   double* part;
+  const int* st;  // status words of the iteration's decomposition
+  int nst;
+  int* sticky;    // OR of every status word seen so far
 };
 
 __device__ __forceinline__ int64_t at(int lay, int64_t ld, int64_t i, int64_t j) {
@@ -66,6 +69,11 @@ __global__ void __launch_bounds__(256) rpca_step_kernel(RpcaArgs a) {
     atomicAdd(&rs, 1);
   __syncthreads();
   const int r = rs;
+  if (blockIdx.x == 0 && threadIdx.x == 0 && a.sticky) {
+    int acc = *a.sticky;
+    for (int i = 0; i < a.nst; ++i) acc |= a.st[i];
+    *a.sticky = acc;
+  }
   const bool colmaj = a.lay_m == CORUTV_COL_MAJOR;
   const int64_t len = colmaj ? a.m : a.n;     // elements along a storage line
   const int64_t nlines = colmaj ? a.n : a.m;
@@ -167,7 +175,8 @@ hipError_t launch_rpca_elementwise(const float* M, int lay_m, int64_t ldm, float
                                    int lay_l, int64_t ldl, int64_t m, int64_t n, const double* P,
                                    int64_t ldp, const double* Q, int64_t ldq, const double* T,
                                    int64_t ldt, int ell, double mu, double mu_next, double lambda,
-                                   double* part, hipStream_t st) {
+                                   double* part, const int* status, int nstatus, int* sticky,
+                                   hipStream_t st) {
   RpcaArgs a;
   a.M = M;
   a.S = S;
@@ -196,6 +205,9 @@ hipError_t launch_rpca_elementwise(const float* M, int lay_m, int64_t ldm, float
   a.thresh = lambda / mu;
   a.inv_mu = 1.0 / mu;
   a.part = part;
+  a.st = status;
+  a.nst = nstatus;
+  a.sticky = sticky;
   rpca_step_kernel<<<dim3(kRpcaBlocks), dim3(256), 0, st>>>(a);
   return hipGetLastError();
 }

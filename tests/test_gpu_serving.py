@@ -86,3 +86,103 @@ def test_admission_queueing_nomem_cancel():
     assert e.value.code == cu.E_NOMEM
     assert cu.lib.corutv_poll(ctx.h, 987654321, None) == cu.E_NOTFOUND
     ctx.close()
+
+
+@pytest.mark.parametrize("room", [4, 1.5])
+def test_blocking_call_while_tickets_in_flight(room):
+    """Blocking decompositions made while requests are in flight take their
+    own workspace range from the same arena: with room for several working
+    sets they run beside the requests, with room for little more than one
+    they wait for a request to finish.  Every result, ticket or blocking, is
+    bit-identical to the same decomposition run alone."""
+    import paper_1906_04572_amd as cu
+
+    _say("blocking call with tickets in flight, room", room)
+    streams = [torch.cuda.current_stream()] + [torch.cuda.Stream() for _ in range(3)]
+    need = max(cu.workspace_bytes(m, n, k, p, q, pr) for m, n, k, p, q, pr in REQS)
+    ctx = cu.Context(workspace_bytes=int(room * need), streams=streams)
+    As = _inputs()
+    alone = [ctx.decompose(A, k, p, q, seed=31, prec=prec) for (m, n, k, p, q, prec), A in zip(REQS, As)]
+    torch.cuda.synchronize()
+    tickets = [ctx.submit(A, k, p, q, seed=31, prec=prec) for (m, n, k, p, q, prec), A in zip(REQS, As)]
+    blocking = [ctx.decompose(As[i], REQS[i][2], REQS[i][3], REQS[i][4], seed=31, prec=REQS[i][5])
+                for i in (0, 2, 4)]
+    results = [ctx.wait(t) for t in tickets]
+    for i, res in enumerate(results):
+        for a, b in zip(res[:4], alone[i][:4]):
+            assert torch.equal(a, b), ("ticket", i)
+    for i, res in zip((0, 2, 4), blocking):
+        for a, b in zip(res[:4], alone[i][:4]):
+            assert torch.equal(a, b), ("blocking", i)
+    ctx.close()
+
+
+def test_queue_full_is_busy():
+    """With one slot, room for one working set and a queue of one, a burst of
+    submissions gets E_BUSY once the queue holds a request; the accepted
+    requests still complete with the right results."""
+    import paper_1906_04572_amd as cu
+
+    _say("queue full")
+    m, n, k, p, q = 4000, 3000, 60, 10, 2
+    streams = [torch.cuda.current_stream(), torch.cuda.Stream()]
+    need = cu.workspace_bytes(m, n, k, p, q, "f64")
+    ctx = cu.Context(workspace_bytes=need, streams=streams, max_queue=1)
+    A = torch.from_numpy(decaying(m, n, 300, 1e-4, seed=8)).cuda()
+    ref = ctx.decompose(A, k, p, q, seed=2)
+    accepted, busy = [], 0
+    for _ in range(8):
+        try:
+            accepted.append(ctx.submit(A, k, p, q, seed=2))
+        except cu.CorutvError as e:
+            assert e.code == cu.E_BUSY
+            busy += 1
+    assert busy >= 1 and len(accepted) >= 1
+    for t in accepted:
+        U, T, V, piv, info = ctx.wait(t)
+        assert torch.equal(U, ref[0]) and torch.equal(T, ref[1]) and torch.equal(V, ref[2])
+    ctx.close()
+
+
+def test_injected_device_error_poisons_the_context():
+    """The error path of a failed launch, forced from the host (no device
+    fault): the call returns E_DEVICE, the context is poisoned (every later
+    call and every queued request returns E_DEVICE) and it can still be
+    destroyed.  A fresh context works."""
+    import ctypes
+
+    import paper_1906_04572_amd as cu
+
+    _say("injected device error")
+    m, n, k, p, q = 2000, 1500, 20, 10, 1
+    streams = [torch.cuda.current_stream(), torch.cuda.Stream()]
+    need = cu.workspace_bytes(m, n, k, p, q, "f64")
+    A = torch.from_numpy(decaying(m, n, 200, 1e-4, seed=6)).cuda()
+    ctx = cu.Context(workspace_bytes=2 * need, streams=streams)
+    ref = ctx.decompose(A, k, p, q, seed=1)
+    ctx.inject_failure(5)
+    assert ctx.decompose_rc(A, k, p, q, 1) == cu.E_DEVICE
+    assert ctx.decompose_rc(A, k, p, q, 1) == cu.E_DEVICE
+    with pytest.raises(cu.CorutvError) as e:
+        ctx.submit(A, k, p, q, seed=1)
+    assert e.value.code == cu.E_DEVICE
+    torch.cuda.synchronize()
+    ctx.close()
+    # a request queued when the failure hits completes with E_DEVICE
+    ctx = cu.Context(workspace_bytes=need, streams=streams)
+    ctx.inject_failure(3)
+    ts = []
+    for _ in range(3):  # once the first request has failed, submit itself refuses
+        try:
+            ts.append(ctx.submit(A, k, p, q, seed=1))
+        except cu.CorutvError as e:
+            assert e.code == cu.E_DEVICE
+    assert ts
+    codes = [cu.lib.corutv_wait(ctx.h, t, None) for t in ts]
+    assert all(c == cu.E_DEVICE for c in codes), codes
+    torch.cuda.synchronize()
+    ctx.close()
+    fresh = cu.Context(workspace_bytes=need)
+    got = fresh.decompose(A, k, p, q, seed=1)
+    assert torch.equal(got[0], ref[0]) and torch.equal(got[1], ref[1])
+    fresh.close()
