@@ -146,7 +146,11 @@ typedef struct corutv_ctx corutv_ctx;
 
 /* Create a context bound to cfg->device, its streams and workspace.  The
  * workspace and streams must stay valid until corutv_destroy.  Returns
- * E_INVAL for a null/unaligned workspace or n_streams < 1. */
+ * E_INVAL for an unaligned workspace, a null one with nonzero
+ * workspace_bytes, or n_streams < 1.  A null workspace with zero bytes makes
+ * a context for corutv_decompose_noalloc (every other call then returns
+ * E_NOMEM).  Creation also looks up, once per device, the device address of
+ * the library's fixed scratch array used by corutv_decompose_noalloc. */
 int corutv_create(corutv_ctx** out, const corutv_config* cfg);
 
 /* Drain (finish) every queued or running request, stop the serving thread
@@ -185,6 +189,26 @@ uint64_t corutv_workspace_bytes_host(int64_t m, int64_t n, int32_t k, int32_t p,
 int corutv_decompose(corutv_ctx* ctx, const corutv_mat* A, int32_t k, int32_t p, int32_t q,
                      uint64_t seed, const corutv_opts* opts, corutv_mat* U, double* T,
                      int64_t ldt, corutv_mat* V, int32_t* piv, corutv_info* info);
+
+/* corutv_decompose for callers that cannot allocate device memory, e.g.
+ * code under HIP graph capture, tight serving loops, or hosts that forbid
+ * hipMalloc.  Same arguments, validation, kernels and results (bit for bit)
+ * as corutv_decompose; CORUTV_FLAG_A_HOST is rejected (E_INVAL).  Its
+ * scratch is not carved from the context's workspace but from a fixed array
+ * of 64 MiB inside the library's device memory, one per device, held until
+ * the process ends; the call itself allocates nothing (no hipMalloc,
+ * hipFree, event or stream creation).  A decomposition whose workspace
+ * (corutv_workspace_bytes) exceeds 64 MiB returns E_NOMEM -- e.g. a
+ * 2000 x 1500 F64 matrix at l = 30 needs 35 MiB, a 20000 x 15000 one at
+ * l = 110 needs 450 MiB.  Every call on one device shares that device's
+ * array and leaves its contents behind; the call clears what must start at
+ * zero itself.  Calls that overlapped on one device would race on the
+ * array, so within a process each call holds a per-device lock for its whole
+ * (blocking) duration and calls run one after another; other processes have
+ * their own copy.  Blocking, on the context stream. */
+int corutv_decompose_noalloc(corutv_ctx* ctx, const corutv_mat* A, int32_t k, int32_t p, int32_t q,
+                             uint64_t seed, const corutv_opts* opts, corutv_mat* U, double* T,
+                             int64_t ldt, corutv_mat* V, int32_t* piv, corutv_info* info);
 
 /* ALM-CoRUTV robust PCA (Sec. 4, Algorithm 2; operators of eq. 12).
  *   M      m x n F32 input (read only).  S: m x n F32 output (the sparse part).

@@ -92,6 +92,8 @@ def _load():
         "corutv_workspace_bytes_host": (U64, [I64, I64, I32, I32, I32, I32, I32, I32]),
         "corutv_decompose": (ctypes.c_int, [P, MP, I32, I32, I32, U64, ctypes.POINTER(Opts), MP, P, I64,
                                             MP, P, ctypes.POINTER(Info)]),
+        "corutv_decompose_noalloc": (ctypes.c_int, [P, MP, I32, I32, I32, U64, ctypes.POINTER(Opts), MP, P,
+                                                    I64, MP, P, ctypes.POINTER(Info)]),
         "corutv_rpca": (ctypes.c_int, [P, MP, D, I32, I32, I32, I32, D, U64, ctypes.POINTER(Opts), MP, MP,
                                        ctypes.POINTER(RpcaInfo)]),
         "corutv_submit": (ctypes.c_int, [P, ctypes.POINTER(Request), ctypes.POINTER(U64)]),
@@ -168,6 +170,7 @@ class Context:
 
     def __init__(self, workspace_bytes=1 << 30, device=0, streams=None, max_queue=0):
         self.device = torch.device("cuda", device)
+        # workspace_bytes = 0: no workspace (corutv_decompose_noalloc only)
         self.ws = torch.empty(int(workspace_bytes), dtype=torch.uint8, device=self.device)
         if streams is None:
             streams = [torch.cuda.current_stream(self.device)]
@@ -225,6 +228,22 @@ class Context:
                                   ctypes.byref(mu), T.data_ptr(), ell, ctypes.byref(mv), piv.data_ptr(),
                                   ctypes.byref(info))
         _check(rc, "decompose")
+        d = info.as_dict()
+        d["tri"] = TRI_NAME.get(d["tri"], d["tri"])
+        return U, T, V, piv, d
+
+    def decompose_noalloc(self, A, k, p, q, seed, prec="f64", tri="auto", want_err=False, out=None,
+                          core="pass"):
+        """decompose() through corutv_decompose_noalloc: scratch from the
+        library's fixed per-device array instead of the context workspace."""
+        U, T, V, piv = out if out is not None else self.alloc_outputs(A, k, p)
+        info = Info()
+        opts = Opts(PREC[prec], TRI[tri], 1 if want_err else 0, CORE[core], 0)
+        mu, mv = mat(U), mat(V)
+        rc = lib.corutv_decompose_noalloc(self.h, ctypes.byref(mat(A)), k, p, q, seed, ctypes.byref(opts),
+                                          ctypes.byref(mu), T.data_ptr(), k + p, ctypes.byref(mv),
+                                          piv.data_ptr(), ctypes.byref(info))
+        _check(rc, "decompose_noalloc")
         d = info.as_dict()
         d["tri"] = TRI_NAME.get(d["tri"], d["tri"])
         return U, T, V, piv, d

@@ -612,6 +612,36 @@ int lease_ws(corutv_ctx* c, size_t bytes, WsLease* l) {
   return CORUTV_OK;
 }
 
+// ---------------------------------------------------------------------------
+// Scratch of corutv_decompose_noalloc: a fixed array in the library's own
+// device memory, one copy per device (the code object's data), held until
+// the process ends.  Host code never passes `scratch` itself to a kernel --
+// on the host that name is only a stand-in -- but the device address that
+// hipGetSymbolAddress returns for it, looked up once per device at context
+// creation with that device current.
+constexpr size_t kScratchBytes = (size_t)64 << 20;
+constexpr int kMaxDevices = 64;
+static __device__ __align__(256) char scratch[kScratchBytes];
+std::mutex g_scratch_mu[kMaxDevices];  // one call at a time per device
+void* g_scratch_ptr[kMaxDevices] = {};
+std::mutex g_scratch_init_mu;
+
+// Called by corutv_create with `device` current.
+int scratch_setup(int device) {
+  if (device < 0 || device >= kMaxDevices) return CORUTV_E_INVAL;
+  std::lock_guard<std::mutex> lk(g_scratch_init_mu);
+  if (g_scratch_ptr[device]) return CORUTV_OK;
+  void* ptr = nullptr;
+  if (hipGetSymbolAddress(&ptr, HIP_SYMBOL(scratch)) != hipSuccess || !ptr) return CORUTV_E_DEVICE;
+  g_scratch_ptr[device] = ptr;
+  return CORUTV_OK;
+}
+
+void* scratch_ptr(int device) {
+  std::lock_guard<std::mutex> lk(g_scratch_init_mu);
+  return g_scratch_ptr[device];
+}
+
 }  // namespace
 
 // ---------------------------------------------------------------------------
@@ -651,7 +681,10 @@ uint64_t corutv_workspace_bytes_host(int64_t m, int64_t n, int32_t k, int32_t p,
 int corutv_create(corutv_ctx** out, const corutv_config* cfg) {
   if (!out || !cfg) return CORUTV_E_INVAL;
   *out = nullptr;
-  if (cfg->n_streams < 1 || !cfg->streams || !cfg->workspace) return CORUTV_E_INVAL;
+  if (cfg->n_streams < 1 || !cfg->streams) return CORUTV_E_INVAL;
+  // a null workspace only with zero bytes (a context for the allocation-free
+  // entry point; every other call then reports E_NOMEM)
+  if (!cfg->workspace && cfg->workspace_bytes != 0) return CORUTV_E_INVAL;
   if (((uintptr_t)cfg->workspace) % 256 != 0) return CORUTV_E_INVAL;
   corutv_ctx* c = new (std::nothrow) corutv_ctx();
   if (!c) return CORUTV_E_NOMEM;
@@ -659,6 +692,10 @@ int corutv_create(corutv_ctx** out, const corutv_config* cfg) {
   if (hipSetDevice(c->device) != hipSuccess) {
     delete c;
     return CORUTV_E_DEVICE;
+  }
+  if (int rs = scratch_setup(c->device)) {
+    delete c;
+    return rs;
   }
   int cus = 0;
   if (hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, c->device) == hipSuccess &&
@@ -675,8 +712,66 @@ int corutv_create(corutv_ctx** out, const corutv_config* cfg) {
     delete c;
     return CORUTV_E_DEVICE;
   }
+  // start / end events of blocking calls, made here so that the
+  // allocation-free entry point creates nothing
+  if (hipEventCreate(&c->dec_ev[0]) != hipSuccess || hipEventCreate(&c->dec_ev[1]) != hipSuccess) {
+    corutv_destroy(c);
+    return CORUTV_E_DEVICE;
+  }
   *out = c;
   return CORUTV_OK;
+}
+
+int corutv_decompose_noalloc(corutv_ctx* ctx, const corutv_mat* A, int32_t k, int32_t p, int32_t q,
+                             uint64_t seed, const corutv_opts* opts, corutv_mat* U, double* T, int64_t ldt,
+                             corutv_mat* V, int32_t* piv, corutv_info* info) {
+  int rc = guard(ctx);
+  if (rc) return rc;
+  if (!A || !U || !V || !opts) return CORUTV_E_INVAL;
+  DecArgs d;
+  d.A = *A;
+  d.U = *U;
+  d.V = *V;
+  d.T = T;
+  d.ldt = ldt;
+  d.piv = piv;
+  d.k = k;
+  d.p = p;
+  d.q = q;
+  d.seed = seed;
+  d.opts = *opts;
+  if ((rc = validate(d)) != CORUTV_OK) return rc;
+  if (opts->flags & CORUTV_FLAG_A_HOST) return CORUTV_E_INVAL;  // staging panels are not provided
+  Plan pl;
+  if (!make_plan(A->rows, A->cols, k, p, q, opts->prec, &pl)) return CORUTV_E_INVAL;
+  if (pl.total > kScratchBytes) return CORUTV_E_NOMEM;
+  char* ws = (char*)scratch_ptr(ctx->device);
+  if (!ws) return CORUTV_E_DEVICE;
+  std::lock_guard<std::mutex> lk(ctx->run_mu);
+  std::lock_guard<std::mutex> lks(g_scratch_mu[ctx->device]);
+  hipStream_t s = ctx->streams[0];
+  hipEvent_t e0 = ctx->dec_ev[0], e1 = ctx->dec_ev[1];
+  HIPOK(hipEventRecord(e0, s));
+  Enqueued eq;
+  rc = enqueue_decompose(ctx, pl, ws, d, s, &eq);
+  if (rc == CORUTV_E_DEVICE) return poison(ctx);
+  if (rc != CORUTV_OK) return rc;
+  int* hst = ctx->host_status;  // pinned, written back without staging
+  double* hsum = (double*)(ctx->host_status + kMaxQr);
+  if (hipEventRecord(e1, s) != hipSuccess ||
+      hipMemcpyAsync(hst, eq.dev_status, sizeof(int) * eq.nqr, hipMemcpyDeviceToHost, s) != hipSuccess)
+    return poison(ctx);
+  if (eq.dev_sum && hipMemcpyAsync(hsum, eq.dev_sum, 16, hipMemcpyDeviceToHost, s) != hipSuccess)
+    return poison(ctx);
+  if (hipStreamSynchronize(s) != hipSuccess) return poison(ctx);
+  float ms = 0.f;
+  hipEventElapsedTime(&ms, e0, e1);
+  rc = finish_info(eq, hst, eq.dev_sum ? hsum : nullptr, info);
+  if (info) {
+    info->gpu_ms = ms;
+    info->ell = pl.ell;
+  }
+  return rc;
 }
 
 int corutv_decompose(corutv_ctx* ctx, const corutv_mat* A, int32_t k, int32_t p, int32_t q,
