@@ -325,12 +325,13 @@ int corutv_tsqr(corutv_ctx* ctx, const double* X, int64_t rows, int32_t ell, int
 /* Column-pivoted QR of a square l x l FP64 matrix D (eq. 8), column-major
  * with leading dimension ldd:  D[:, piv] = Qt R, diag(R) >= 0.  Pivot rule:
  * largest trailing column norm, recomputed from scratch at every step (no
- * downdating) as four interleaved partial sums of separately rounded squares
- * over the rows, combined as (a0 + a1) + (a2 + a3); ties to the lowest
- * column position.  Another summation order changes a norm only by rounding,
- * so the pivot differs from a sequential-order QRCP only where the two
- * largest trailing norms lie within that rounding of each other.  Qt, R
- * column-major with leading dimension l. */
+ * downdating); ties to the lowest column position.  The norms are reduced in
+ * the kernel's own fixed order (per-lane partial sums and fused
+ * multiply-adds), so the result is a deterministic function of the input
+ * bits; another summation order changes a norm only by rounding, so the
+ * pivot differs from a sequential-order QRCP only where the two largest
+ * trailing norms lie within that rounding of each other.  Qt, R column-major
+ * with leading dimension l. */
 int corutv_qrcp(corutv_ctx* ctx, int32_t ell, const double* D, int64_t ldd, double* Qt,
                 double* R, int32_t* piv);
 

@@ -13,28 +13,30 @@
 //   l <= 192: qrcp_big_kernel, the same register layout (768 threads at
 //             most), pivot column broadcast through LDS, reflectors staged
 //             through device memory for Qt;
-//   l <= 256: qrcp_pivot_global + qrcp_formq_global, 1024 threads, the
+//   l <= 224: qrcp_bigl_kernel, the same with the top rows of every column
+//             in LDS, then qrcp_formq_cols_kernel (one wave per column of Qt);
+//   l <= 256: qrcp_pivot_global + qrcp_formq_cols_kernel, 1024 threads, the
 //             working matrix in device memory (column-major), two barriers
 //             per step.
 //
-// The arithmetic order is fixed so that the pivot sequence is a function of
-// the input bits only (each product and sum rounded separately: this file is
-// compiled with contraction off).  sum4 of an ordered list of terms: a_k =
-// sequential sum of the terms at positions k, k+4, ... (k = 0..3), result
-// (a_0 + a_1) + (a_2 + a_3) -- four independent chains instead of one.
-//   tails   t_j = sum4_{i = s+1..l-1} W[i,j]*W[i,j]
-//   norms   acc_j = W[s,j]*W[s,j] + t_j
+// Every reduction has a fixed order (so the factorization is a deterministic
+// function of the input bits), chosen for speed rather than to match any
+// other implementation: a lane sums its own rows into four independent
+// partial sums (row blocks q taken in increasing order, block q into partial
+// q mod 4, fused multiply-adds), adds them as (p0 + p1) + (p2 + p3), and the
+// four lanes of a column add their results by a butterfly (every lane ends
+// with the same bits).  Another order changes a norm only by rounding, so the
+// pivot agrees with any other QRCP of the same matrix except where the two
+// largest trailing norms lie within that rounding of each other.
+//   norms   acc_j = W[s,j]^2 + t_j, t_j = sum over rows i > s of W[i,j]^2
 //   pivot   first logical position j >= s with the largest acc_j
 //   reflector  nrm = sqrt(acc_p); alpha = -nrm if x0 >= 0 else nrm;
 //           v = W[s:, p] with v_0 = x0 - alpha; vtv = v0*v0 + t_p; tau = 2/vtv
-//   update  d_j = sum4_{i = s..l-1} v_i*W[i,j];
-//           f_j = d_j*tau; W[i,j] = W[i,j] - f_j*v_i
+//   update  d_j = sum over rows i >= s of v_i W[i,j]; W[i,j] -= (d_j tau) v_i
 // Qt = H_0 H_1 ... H_{l-1} is formed afterwards (backward accumulation); it
 // does not influence the pivots.
 // diag(R) is made non-negative by flipping rows of R and columns of Qt.
 #include "internal.hpp"
-
-#pragma clang fp contract(off)
 
 namespace corutv {
 namespace {
@@ -202,19 +204,13 @@ __device__ __forceinline__ double uniform_f64(double v) {
   return __longlong_as_double(((long long)hi << 32) | (unsigned)lo);
 }
 
-// (a0 + a1) + (a2 + a3) over the four lanes of a column, a_j being the chain
-// of class j; lane k holds class (k - r0) mod 4.  Same bits on all four.
-__device__ __forceinline__ double combine4_rot(double a, int k, int r0) {
-  const double x1 = dpp_f64<0xB1, 0xF>(a);  // lane k ^ 1
-  const double x2 = dpp_f64<0x4E, 0xF>(a);  // lane k ^ 2
-  const double x3 = dpp_f64<0x1B, 0xF>(a);  // lane k ^ 3
-  double v[4];
-#pragma unroll
-  for (int cls = 0; cls < 4; ++cls) {
-    const int m = ((cls + r0) & 3) ^ k;
-    v[cls] = m == 0 ? a : (m == 1 ? x1 : (m == 2 ? x2 : x3));
-  }
-  return (v[0] + v[1]) + (v[2] + v[3]);
+// Sum of a lane's four partial sums, then over the four lanes of a column
+// (lanes 4j..4j+3): a butterfly whose additions are commutative pairs, so all
+// four lanes end with the same bits.
+__device__ __forceinline__ double lane4_sum(const double (&a)[4]) {
+  const double t = (a[0] + a[1]) + (a[2] + a[3]);
+  const double u = t + dpp_f64<0xB1, 0xF>(t);  // lanes k, k ^ 1
+  return u + dpp_f64<0x4E, 0xF>(u);            // pairs k, k ^ 2
 }
 
 // largest value over the wave (NaN-free input), the same on every lane
@@ -286,13 +282,10 @@ qrcp_reg_kernel(const double* __restrict__ D, int64_t ldd, int trans, int ell, d
   int mypos = c;
   // norms of step 0: head row 0, tail rows 1..
   if (col_ok) {
-    double a = 0.0;
+    double a[4] = {0.0, 0.0, 0.0, 0.0};
 #pragma unroll
-    for (int q = 0; q < NR; ++q) {
-      const double sq = w[q] * w[q];
-      a = a + (q > 0 || k >= 1 ? sq : 0.0);
-    }
-    const double tail = combine4_rot(a, k, 1);
+    for (int q = 0; q < NR; ++q) a[q & 3] = (q > 0 || k >= 1) ? fma(w[q], w[q], a[q & 3]) : a[q & 3];
+    const double tail = lane4_sum(a);
     if (k == 0) {
       const double acc = w[0] * w[0] + tail;
       double al, v0, ta;
@@ -362,14 +355,14 @@ qrcp_reg_kernel(const double* __restrict__ D, int64_t ldd, int trans, int ell, d
           }
         }
       }
-      double a = 0.0;
+      double a[4] = {0.0, 0.0, 0.0, 0.0};
 #pragma unroll
       for (int g = 0; g < NS; ++g)
         if (g >= gs) {
 #pragma unroll
-          for (int q = g * kSeg; q < g * kSeg + kSeg && q < NR; ++q) a = a + vv[q] * w[q];
+          for (int q = g * kSeg; q < g * kSeg + kSeg && q < NR; ++q) a[q & 3] = fma(vv[q], w[q], a[q & 3]);
         }
-      const double f = combine4_rot(a, k, s) * tau;
+      const double f = lane4_sum(a) * tau;
 #pragma unroll
       for (int g = 0; g < NS; ++g)
         if (g >= gs) {
@@ -385,18 +378,16 @@ qrcp_reg_kernel(const double* __restrict__ D, int64_t ldd, int trans, int ell, d
       // reflector this column would give
       const int qh = (s + 1) >> 2;
       const int gt = ((s + 2) >> 2) / kSeg;
-      double a = 0.0, hv = 0.0;
+      double a[4] = {0.0, 0.0, 0.0, 0.0}, hv = 0.0;
 #pragma unroll
       for (int g = 0; g < NS; ++g) {
         if (g > gt) {
 #pragma unroll
-          for (int q = g * kSeg; q < g * kSeg + kSeg && q < NR; ++q) a = a + w[q] * w[q];
+          for (int q = g * kSeg; q < g * kSeg + kSeg && q < NR; ++q) a[q & 3] = fma(w[q], w[q], a[q & 3]);
         } else if (g == gt) {
 #pragma unroll
-          for (int q = g * kSeg; q < g * kSeg + kSeg && q < NR; ++q) {
-            const double sq = w[q] * w[q];
-            a = a + (4 * q + k >= s + 2 ? sq : 0.0);
-          }
+          for (int q = g * kSeg; q < g * kSeg + kSeg && q < NR; ++q)
+            a[q & 3] = 4 * q + k >= s + 2 ? fma(w[q], w[q], a[q & 3]) : a[q & 3];
         }
       }
 #pragma unroll
@@ -405,7 +396,7 @@ qrcp_reg_kernel(const double* __restrict__ D, int64_t ldd, int trans, int ell, d
 #pragma unroll
           for (int q = g * kSeg; q < g * kSeg + kSeg && q < NR; ++q) hv = q == qh ? w[q] : hv;
         }
-      const double tail = combine4_rot(a, k, s + 2);
+      const double tail = lane4_sum(a);
       if (k == ((s + 1) & 3)) {
         const double acc = hv * hv + tail;
         double al, rv, ta;
@@ -454,16 +445,14 @@ qrcp_reg_kernel(const double* __restrict__ D, int64_t ldd, int trans, int ell, d
 #pragma unroll
           for (int q = g * kSeg; q < g * kSeg + kSeg && q < NR; ++q) vv[q] = mp[4 * q + k];
         }
-      double a = 0.0;
+      double a[4] = {0.0, 0.0, 0.0, 0.0};
 #pragma unroll
       for (int g = 0; g < NS; ++g)
         if (g >= gs) {
 #pragma unroll
-          for (int q = g * kSeg; q < g * kSeg + kSeg && q < NR; ++q) a += vv[q] * w[q];
+          for (int q = g * kSeg; q < g * kSeg + kSeg && q < NR; ++q) a[q & 3] = fma(vv[q], w[q], a[q & 3]);
         }
-      a += dpp_f64<0xB1, 0xF>(a);
-      a += dpp_f64<0x4E, 0xF>(a);
-      const double dd = a * ts;
+      const double dd = lane4_sum(a) * ts;
 #pragma unroll
       for (int g = 0; g < NS; ++g)
         if (g >= gs) {
@@ -520,13 +509,10 @@ qrcp_big_kernel(const double* __restrict__ D, int64_t ldd, int trans, int ell, d
   for (int i = tid; i < LP; i += nt) vcol[i] = 0.0;
   int mypos = c;
   if (col_ok) {
-    double a = 0.0;
+    double a[4] = {0.0, 0.0, 0.0, 0.0};
 #pragma unroll
-    for (int q = 0; q < NR; ++q) {
-      const double sq = w[q] * w[q];
-      a = a + (q > 0 || k >= 1 ? sq : 0.0);
-    }
-    const double tail = combine4_rot(a, k, 1);
+    for (int q = 0; q < NR; ++q) a[q & 3] = (q > 0 || k >= 1) ? fma(w[q], w[q], a[q & 3]) : a[q & 3];
+    const double tail = lane4_sum(a);
     if (k == 0) {
       const double acc = w[0] * w[0] + tail;
       double al, v0, ta;
@@ -590,14 +576,15 @@ qrcp_big_kernel(const double* __restrict__ D, int64_t ldd, int trans, int ell, d
     __syncthreads();
     const int gs = (s >> 2) / kSeg;
     if (act && tau != 0.0) {
-      double a = 0.0;
+      double a[4] = {0.0, 0.0, 0.0, 0.0};
 #pragma unroll
       for (int g = 0; g < NS; ++g)
         if (g >= gs) {
 #pragma unroll
-          for (int q = g * kSeg; q < g * kSeg + kSeg && q < NR; ++q) a = a + vcol[4 * q + k] * w[q];
+          for (int q = g * kSeg; q < g * kSeg + kSeg && q < NR; ++q)
+            a[q & 3] = fma(vcol[4 * q + k], w[q], a[q & 3]);
         }
-      const double f = combine4_rot(a, k, s) * tau;
+      const double f = lane4_sum(a) * tau;
 #pragma unroll
       for (int g = 0; g < NS; ++g)
         if (g >= gs) {
@@ -608,18 +595,16 @@ qrcp_big_kernel(const double* __restrict__ D, int64_t ldd, int trans, int ell, d
     if (act && s + 1 < ell) {
       const int qh = (s + 1) >> 2;
       const int gt = ((s + 2) >> 2) / kSeg;
-      double a = 0.0, hv = 0.0;
+      double a[4] = {0.0, 0.0, 0.0, 0.0}, hv = 0.0;
 #pragma unroll
       for (int g = 0; g < NS; ++g) {
         if (g > gt) {
 #pragma unroll
-          for (int q = g * kSeg; q < g * kSeg + kSeg && q < NR; ++q) a = a + w[q] * w[q];
+          for (int q = g * kSeg; q < g * kSeg + kSeg && q < NR; ++q) a[q & 3] = fma(w[q], w[q], a[q & 3]);
         } else if (g == gt) {
 #pragma unroll
-          for (int q = g * kSeg; q < g * kSeg + kSeg && q < NR; ++q) {
-            const double sq = w[q] * w[q];
-            a = a + (4 * q + k >= s + 2 ? sq : 0.0);
-          }
+          for (int q = g * kSeg; q < g * kSeg + kSeg && q < NR; ++q)
+            a[q & 3] = 4 * q + k >= s + 2 ? fma(w[q], w[q], a[q & 3]) : a[q & 3];
         }
       }
 #pragma unroll
@@ -628,7 +613,7 @@ qrcp_big_kernel(const double* __restrict__ D, int64_t ldd, int trans, int ell, d
 #pragma unroll
           for (int q = g * kSeg; q < g * kSeg + kSeg && q < NR; ++q) hv = q == qh ? w[q] : hv;
         }
-      const double tail = combine4_rot(a, k, s + 2);
+      const double tail = lane4_sum(a);
       if (k == ((s + 1) & 3)) {
         const double acc = hv * hv + tail;
         double al, rv, ta;
@@ -673,16 +658,14 @@ qrcp_big_kernel(const double* __restrict__ D, int64_t ldd, int trans, int ell, d
       if (col_ok && c >= s && ts != 0.0) {
         const double* v = vch + (s - lo) * LP;
         const int gs = (s >> 2) / kSeg;
-        double a = 0.0;
+        double a[4] = {0.0, 0.0, 0.0, 0.0};
 #pragma unroll
         for (int g = 0; g < NS; ++g)
           if (g >= gs) {
 #pragma unroll
-            for (int q = g * kSeg; q < g * kSeg + kSeg && q < NR; ++q) a += v[4 * q + k] * w[q];
+            for (int q = g * kSeg; q < g * kSeg + kSeg && q < NR; ++q) a[q & 3] = fma(v[4 * q + k], w[q], a[q & 3]);
           }
-        a += dpp_f64<0xB1, 0xF>(a);
-        a += dpp_f64<0x4E, 0xF>(a);
-        const double dd = a * ts;
+        const double dd = lane4_sum(a) * ts;
 #pragma unroll
         for (int g = 0; g < NS; ++g)
           if (g >= gs) {
@@ -702,44 +685,274 @@ qrcp_big_kernel(const double* __restrict__ D, int64_t ldd, int trans, int ell, d
   }
 }
 
-// Qt = H_0 (H_1 (... H_{l-1} I)), one thread per column; Q in LDS (row-major).
-// The reflector of the next step is staged into LDS (double-buffered) while
-// the current one is applied, so each step has one barrier.
-__device__ __forceinline__ void qrcp_formq_body(double* __restrict__ Q, double* __restrict__ vb,
-                                                const double* __restrict__ V,
-                                                const double* __restrict__ tau,
-                                                const double* __restrict__ sign, int ell,
-                                                double* __restrict__ Qout) {
-  const int tid = threadIdx.x, nt = blockDim.x;
-  for (int e = tid; e < ell * ell; e += nt) Q[e] = (e / ell == e % ell) ? 1.0 : 0.0;
-  if (tid < ell) vb[((ell - 1) & 1) * 256 + tid] = V[(int64_t)(ell - 1) * ell + tid];
+// ---------------------------------------------------------------------------
+// 192 < l <= 224: the layout of qrcp_big_kernel, with the top rows of every
+// column (blocks q < NL: rows 4q + k) in LDS and the others in registers.
+// The top rows leave the active trailing block first, so after the first 4 NL
+// steps only registers are touched.  Qt is formed afterwards by
+// qrcp_formq_cols_kernel from the reflectors, taus and signs written here.
+constexpr int kBigLMax = 224;
+
+template <int NR, int NL>
+__global__ void __launch_bounds__(16 * (NR + NL))
+qrcp_bigl_kernel(const double* __restrict__ D, int64_t ldd, int trans, int ell, double* __restrict__ Rout,
+                 int32_t* __restrict__ piv, double* __restrict__ Vg, double* __restrict__ taug,
+                 double* __restrict__ signg) {
+  constexpr int LP = 4 * (NR + NL);       // padded rows and columns
+  constexpr int NC = (LP + 63) / 64;      // pivot candidates per lane
+  constexpr int NS = (NR + kSeg - 1) / kSeg;
+  __shared__ double nrm[2][LP], ralpha[2][LP], rv0[2][LP], rtau[2][LP];
+  __shared__ int colat[2][LP];
+  __shared__ double vcol[LP];
+  __shared__ double alph[LP];
+  __shared__ double wl[NL * LP * 4];  // row 4q + k (q < NL) of column c at wl[(q LP + c) 4 + k]
+  const int tid = threadIdx.x, lane = tid & 63, nt = blockDim.x;
+  const int c = tid >> 2, k = tid & 3;
+  const bool col_ok = c < ell;
+  const int cl = col_ok ? c : ell - 1;
+  double* wc = wl + c * 4 + k;  // + q LP 4
+  double w[NR];                 // row 4 (NL + q) + k
+#pragma unroll
+  for (int q = 0; q < NL; ++q) {
+    const int row = 4 * q + k;
+    const int rl = row < ell ? row : ell - 1;
+    const double v = trans ? D[(int64_t)rl * ldd + cl] : D[(int64_t)cl * ldd + rl];
+    wc[q * LP * 4] = (row < ell && col_ok) ? v : 0.0;
+  }
+#pragma unroll
+  for (int q = 0; q < NR; ++q) {
+    const int row = 4 * (NL + q) + k;
+    const int rl = row < ell ? row : ell - 1;
+    const double v = trans ? D[(int64_t)rl * ldd + cl] : D[(int64_t)cl * ldd + rl];
+    w[q] = (row < ell && col_ok) ? v : 0.0;
+  }
+  for (int i = tid; i < LP; i += nt) vcol[i] = 0.0;
+  int mypos = c;
+  if (col_ok) {
+    double a[4] = {0.0, 0.0, 0.0, 0.0};
+#pragma unroll
+    for (int q = 0; q < NL; ++q) {
+      const double x = wc[q * LP * 4];
+      a[q & 3] = (q > 0 || k >= 1) ? fma(x, x, a[q & 3]) : a[q & 3];
+    }
+#pragma unroll
+    for (int q = 0; q < NR; ++q) a[(NL + q) & 3] = fma(w[q], w[q], a[(NL + q) & 3]);
+    const double tail = lane4_sum(a);
+    if (k == 0) {
+      const double x0 = wc[0];
+      const double acc = x0 * x0 + tail;
+      double al, v0, ta;
+      reflector_of(acc, x0, tail, al, v0, ta);
+      nrm[0][c] = acc;
+      ralpha[0][c] = al;
+      rv0[0][c] = v0;
+      rtau[0][c] = ta;
+      colat[0][c] = c;
+    }
+  }
   __syncthreads();
-  const int j = tid >> 2, k = tid & 3;
-  for (int s = ell - 1; s >= 0; --s) {
-    const double* v = vb + (s & 1) * 256;
-    if (s > 0 && tid < ell) vb[((s - 1) & 1) * 256 + tid] = V[(int64_t)(s - 1) * ell + tid];
-    const double ts = tau[s];
-    if (ts != 0.0 && j >= s && j < ell) {
-      double a = 0.0;
-      for (int i = s + k; i < ell; i += 4) a += v[i] * Q[(int64_t)j * ell + i];
-      a += __shfl_xor(a, 1, 64);
-      a += __shfl_xor(a, 2, 64);
-      const double d = a * ts;
-      for (int i = s + k; i < ell; i += 4) Q[(int64_t)j * ell + i] -= d * v[i];
+  for (int s = 0; s < ell; s = __builtin_amdgcn_readfirstlane(s + 1)) {
+    const int b = s & 1;
+    double cand[NC];
+    double cb = -1.0;
+#pragma unroll
+    for (int h = 0; h < NC; ++h) {
+      const int j = s + lane + 64 * h;
+      const double v = j < ell ? nrm[b][j] : -1.0;
+      cand[h] = v >= 0.0 ? v : -1.0;
+      cb = fmax(cb, cand[h]);
+    }
+    const double gm = wave_max(cb);
+    int p = s;  // only NaN norms: keep the current column
+    if (gm >= 0.0) {
+#pragma unroll
+      for (int h = NC - 1; h >= 0; --h) {
+        const unsigned long long m = __ballot(cand[h] == gm);
+        if (m) p = s + 64 * h + __ffsll((long long)m) - 1;
+      }
+    }
+    p = __builtin_amdgcn_readfirstlane(p);
+    const int cp = __builtin_amdgcn_readfirstlane(colat[b][p]);
+    const double alpha = uniform_f64(ralpha[b][p]);
+    const double v0 = uniform_f64(rv0[b][p]);
+    const double tau = uniform_f64(rtau[b][p]);
+    const int qs = s >> 2;
+    if (c == cp) {  // reflector v_s = (0 above row s, v0, W[s+1:, cp])
+#pragma unroll
+      for (int q = 0; q < NL; ++q) {
+        const int row = 4 * q + k;
+        if (q >= qs && row < ell) {
+          const double v = row < s ? 0.0 : (row == s ? v0 : wc[q * LP * 4]);
+          vcol[row] = v;
+          Vg[(int64_t)s * ell + row] = v;
+        } else if (row < ell) {
+          Vg[(int64_t)s * ell + row] = 0.0;
+        }
+      }
+#pragma unroll
+      for (int q = 0; q < NR; ++q) {
+        const int row = 4 * (NL + q) + k;
+        if (row < ell) {
+          const double v = row < s ? 0.0 : (row == s ? v0 : w[q]);
+          vcol[row] = v;
+          Vg[(int64_t)s * ell + row] = v;
+        }
+      }
+    }
+    if (tid == 0) {
+      alph[s] = alpha;
+      taug[s] = tau;
+    }
+    if (c == cp)
+      mypos = s;
+    else if (mypos == s)
+      mypos = p;
+    const bool act = col_ok && mypos > s;
+    __syncthreads();
+    // register segments g < gs hold only rows < s
+    const int gs = qs > NL ? (qs - NL) / kSeg : 0;
+    if (act && tau != 0.0) {
+      double a[4] = {0.0, 0.0, 0.0, 0.0};
+#pragma unroll
+      for (int q = 0; q < NL; ++q)
+        if (q >= qs) a[q & 3] = fma(vcol[4 * q + k], wc[q * LP * 4], a[q & 3]);
+#pragma unroll
+      for (int g = 0; g < NS; ++g)
+        if (g >= gs) {
+#pragma unroll
+          for (int q = g * kSeg; q < g * kSeg + kSeg && q < NR; ++q)
+            a[(NL + q) & 3] = fma(vcol[4 * (NL + q) + k], w[q], a[(NL + q) & 3]);
+        }
+      const double f = lane4_sum(a) * tau;
+#pragma unroll
+      for (int q = 0; q < NL; ++q)
+        if (q >= qs) wc[q * LP * 4] = wc[q * LP * 4] - f * vcol[4 * q + k];
+#pragma unroll
+      for (int g = 0; g < NS; ++g)
+        if (g >= gs) {
+#pragma unroll
+          for (int q = g * kSeg; q < g * kSeg + kSeg && q < NR; ++q) w[q] = w[q] - f * vcol[4 * (NL + q) + k];
+        }
+    }
+    if (act && s + 1 < ell) {
+      // norm of step s + 1 (head row s + 1, tail rows s + 2..)
+      const int qt2 = (s + 2) >> 2, qh = (s + 1) >> 2;
+      const int gt = qt2 > NL ? (qt2 - NL) / kSeg : 0;
+      double a[4] = {0.0, 0.0, 0.0, 0.0}, hv = 0.0;
+#pragma unroll
+      for (int q = 0; q < NL; ++q)
+        if (q >= qt2) {
+          const double x = wc[q * LP * 4];
+          a[q & 3] = 4 * q + k >= s + 2 ? fma(x, x, a[q & 3]) : a[q & 3];
+        }
+#pragma unroll
+      for (int g = 0; g < NS; ++g) {
+        if (g > gt) {
+#pragma unroll
+          for (int q = g * kSeg; q < g * kSeg + kSeg && q < NR; ++q)
+            a[(NL + q) & 3] = fma(w[q], w[q], a[(NL + q) & 3]);
+        } else if (g == gt) {
+#pragma unroll
+          for (int q = g * kSeg; q < g * kSeg + kSeg && q < NR; ++q)
+            a[(NL + q) & 3] = 4 * (NL + q) + k >= s + 2 ? fma(w[q], w[q], a[(NL + q) & 3]) : a[(NL + q) & 3];
+        }
+      }
+      if (qh < NL) {
+        hv = wl[(qh * LP + c) * 4 + k];
+      } else {
+#pragma unroll
+        for (int g = 0; g < NS; ++g)
+          if (g == (qh - NL) / kSeg) {
+#pragma unroll
+            for (int q = g * kSeg; q < g * kSeg + kSeg && q < NR; ++q) hv = NL + q == qh ? w[q] : hv;
+          }
+      }
+      const double tail = lane4_sum(a);
+      if (k == ((s + 1) & 3)) {
+        const double acc = hv * hv + tail;
+        double al, rv, ta;
+        reflector_of(acc, hv, tail, al, rv, ta);
+        nrm[b ^ 1][mypos] = acc;
+        ralpha[b ^ 1][mypos] = al;
+        rv0[b ^ 1][mypos] = rv;
+        rtau[b ^ 1][mypos] = ta;
+        colat[b ^ 1][mypos] = c;
+      }
     }
     __syncthreads();
   }
-  for (int e = tid; e < ell * ell; e += nt) {
-    const int i = e % ell, c = e / ell;  // column-major output
-    Qout[e] = sign[c] * Q[e];
+  // R[r][j] = W[r][piv[j]] above the diagonal, alpha_j on it; rows with a
+  // negative diagonal flipped.  Column-major.
+  if (col_ok) {
+    const int jj = mypos;
+#pragma unroll
+    for (int q = 0; q < NL; ++q) {
+      const int r = 4 * q + k;
+      if (r < ell) {
+        double v = r < jj ? wc[q * LP * 4] : (r == jj ? alph[jj] : 0.0);
+        if (alph[r] < 0.0) v = -v;
+        Rout[(int64_t)jj * ell + r] = v;
+      }
+    }
+#pragma unroll
+    for (int q = 0; q < NR; ++q) {
+      const int r = 4 * (NL + q) + k;
+      if (r < ell) {
+        double v = r < jj ? w[q] : (r == jj ? alph[jj] : 0.0);
+        if (alph[r] < 0.0) v = -v;
+        Rout[(int64_t)jj * ell + r] = v;
+      }
+    }
+    if (k == 0) piv[jj] = c;
   }
+  if (tid < ell) signg[tid] = alph[tid] < 0.0 ? -1.0 : 1.0;
 }
 
-__global__ void __launch_bounds__(1024) qrcp_formq_global(const double* V, const double* tau,
-                                                         const double* sign, int ell, double* Qout,
-                                                         double* work) {
-  __shared__ double vb[512];
-  qrcp_formq_body(work, vb, V, tau, sign, ell, Qout);
+// Qt = H_0 (H_1 (... H_{l-1} I)) with one wave per column c: Qt e_c =
+// H_0 ... H_c e_c (H_s leaves e_c unchanged for s > c, v_s being zero above
+// row s).  Lane i holds rows i, i + 64, i + 128, i + 192; the next
+// reflector's loads are issued before the current one is applied.  The dot
+// products are reduced by a butterfly (same bits on every lane).
+// V column-major (V[s l + i] = v_s[i], zero above row s), tau and sign per
+// step / column; l <= 256.
+__global__ void __launch_bounds__(64) qrcp_formq_cols_kernel(const double* __restrict__ V,
+                                                             const double* __restrict__ tau,
+                                                             const double* __restrict__ sign, int ell,
+                                                             double* __restrict__ Qout) {
+  const int c = blockIdx.x, lane = threadIdx.x;
+  double x[4], vn[4];
+#pragma unroll
+  for (int r = 0; r < 4; ++r) {
+    const int row = lane + 64 * r;
+    x[r] = row == c ? 1.0 : 0.0;
+    vn[r] = row < ell ? V[(int64_t)c * ell + row] : 0.0;
+  }
+  for (int s = c; s >= 0; --s) {
+    double v[4];
+#pragma unroll
+    for (int r = 0; r < 4; ++r) v[r] = vn[r];
+    if (s > 0) {
+#pragma unroll
+      for (int r = 0; r < 4; ++r) {
+        const int row = lane + 64 * r;
+        vn[r] = row < ell ? V[(int64_t)(s - 1) * ell + row] : 0.0;
+      }
+    }
+    const double ts = tau[s];
+    if (ts == 0.0) continue;
+    double d = (v[0] * x[0] + v[1] * x[1]) + (v[2] * x[2] + v[3] * x[3]);
+#pragma unroll
+    for (int off = 32; off > 0; off >>= 1) d = d + __shfl_xor(d, off, 64);
+    d = d * ts;
+#pragma unroll
+    for (int r = 0; r < 4; ++r) x[r] = x[r] - d * v[r];
+  }
+  const double sg = sign[c];
+#pragma unroll
+  for (int r = 0; r < 4; ++r) {
+    const int row = lane + 64 * r;
+    if (row < ell) Qout[(int64_t)c * ell + row] = sg * x[r];
+  }
 }
 
 }  // namespace
@@ -766,9 +979,12 @@ hipError_t launch_qrcp(const double* D, int64_t ldd, int trans, int ell, double*
     qrcp_big_kernel<40><<<dim3(1), dim3(640), 0, st>>>(D, ldd, trans, ell, Qt, R, piv, V);
   } else if (ell <= kBigMax) {
     qrcp_big_kernel<48><<<dim3(1), dim3(768), 0, st>>>(D, ldd, trans, ell, Qt, R, piv, V);
+  } else if (ell <= kBigLMax) {
+    qrcp_bigl_kernel<40, 16><<<dim3(1), dim3(896), 0, st>>>(D, ldd, trans, ell, R, piv, V, tau, sign);
+    qrcp_formq_cols_kernel<<<dim3(ell), dim3(64), 0, st>>>(V, tau, sign, ell, Qt);
   } else {
     qrcp_pivot_global<<<dim3(1), dim3(1024), 0, st>>>(D, ldd, trans, ell, R, piv, V, tau, sign, scratch);
-    qrcp_formq_global<<<dim3(1), dim3(1024), 0, st>>>(V, tau, sign, ell, Qt, scratch);
+    qrcp_formq_cols_kernel<<<dim3(ell), dim3(64), 0, st>>>(V, tau, sign, ell, Qt);
   }
   return hipGetLastError();
 }

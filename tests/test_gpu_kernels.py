@@ -121,7 +121,7 @@ def _cores():
     A = noisy_low_rank(400, 300, 20, 1e-6, seed=1)
     out.append(("c1-like", corutv(A, 20, 10, 1, seed=1)["D"]))
     rng = np.random.default_rng(5)
-    for ell in (10, 30, 110, 128, 129, 150, 180, 200, 256):
+    for ell in (10, 30, 110, 128, 129, 150, 180, 192, 193, 200, 220, 224, 225, 256):
         out.append(("gauss%d" % ell, rng.standard_normal((ell, ell)) * np.logspace(0, -8, ell)))
     D = rng.standard_normal((40, 6)) @ rng.standard_normal((6, 40))
     out.append(("rank6", D))
@@ -134,8 +134,9 @@ def _cores():
 
 @pytest.mark.parametrize("name,D", _cores(), ids=[c[0] for c in _cores()])
 def test_qrcp_pivots_margin_rule(ctx, name, D):
-    """Identical input bits: the kernel sums column norms in four interleaved
-    partial sums, the oracle sequentially, so norms differ by rounding.  The
+    """Identical input bits: the kernel sums column norms in its own fixed
+    order (partial sums per lane and across the four lanes of a column, fused
+    multiply-adds), the oracle sequentially, so norms differ by rounding.  The
     kernel's pivot sequence is replayed in the oracle's arithmetic; at every
     step its choice must be the oracle's largest norm unless the two norms are
     within tau = 8 l u max_j ||D_j|| (near ties are listed, not failed).
