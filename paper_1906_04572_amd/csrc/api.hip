@@ -32,6 +32,8 @@ constexpr int kMaxQr = 64;  // status words (one per tall-skinny QR)
 // whose orthogonality loss bound u l (||R||_F ||R^-1||_F)^2 is below the FP32
 // unit roundoff needs no second step.
 constexpr double kOneStepThr = 5.9604644775390625e-08;  // 2^-24
+// Sketches with at most this many columns take the three-launch CholeskyQR2.
+constexpr int kQr16Max = 16;
 
 struct Plan {
   int64_t mm = 0, nn = 0;  // oriented problem: mm >= nn rows of Q1 / Q2
@@ -43,7 +45,8 @@ struct Plan {
   // byte offsets
   size_t o_wop = 0, o_qop = 0, o_part = 0, o_x0 = 0, o_x1 = 0, o_q1 = 0, o_q2 = 0, o_xp = 0,
          o_g = 0, o_r = 0, o_rinv = 0, o_core = 0, o_qt = 0, o_rt = 0, o_qw = 0, o_tt = 0,
-         o_piv = 0, o_st = 0, o_res = 0, o_sum = 0, o_cw = 0, o_sbf = 0, o_stage = 0, o_hh = 0;
+         o_piv = 0, o_st = 0, o_res = 0, o_sum = 0, o_cw = 0, o_sbf = 0, o_stage = 0, o_hh = 0,
+         o_q16 = 0;
   // host-resident A: panels of panel_rows storage rows, stage_ld elements each
   int64_t panel_rows = 0, stage_ld = 0;
   size_t stage_bytes = 0;  // one staging panel
@@ -123,6 +126,7 @@ bool make_plan(int64_t m, int64_t n, int k, int p, int q, int prec, Plan* pl) {
   pl->o_cw = take(chol_work_bytes((int)ell));
   pl->o_hh = take(std::max(hh_work_bytes(pl->mm, (int)ell), hh_work_bytes(pl->nn, (int)ell)));
   if (prec == P_BF16 || prec == P_BF16X3) pl->o_sbf = take(sketch_bf16_bytes(pl->ellp, pl->ldx));
+  if (ell <= kQr16Max) pl->o_q16 = take(qr16_work_bytes());
   pl->total = off;
   return true;
 }
@@ -282,6 +286,13 @@ hipError_t qr_from_partials(const Plan& pl, char* ws, const Partials& pp, int64_
   hipError_t e;
   // summed: the sketch is already in x0 (passes over a host-resident A)
   if (!summed && (e = launch_sum_partials(pp, ell, pl.ellp, x0, nullptr, ld, s)) != hipSuccess) return e;
+  if (ell <= kQr16Max) {
+    if ((e = launch_qr16(x0, x1, ld, rows, ell, q64, q32, rfac, st, (double*)(ws + pl.o_q16),
+                         one_step ? kOneStepThr : 0.0, s)) != hipSuccess)
+      return e;
+    return launch_householder_qr(x0, ld, rows, ell, x1, ld, q64, ld, q32, ld, rfac, st,
+                                 (double*)(ws + pl.o_hh), s);
+  }
   if ((e = launch_xty(x0, ld, x0, ld, rows, ell, xp, splits, nullptr, s)) != hipSuccess) return e;
   if ((e = launch_reduce(xp, splits, l2, G, nullptr, s)) != hipSuccess) return e;
   if ((e = launch_chol(G, ell, R, Ri, st, nullptr, cw, s, one_step ? kOneStepThr : 0.0)) != hipSuccess)
@@ -370,6 +381,7 @@ int enqueue_decompose(corutv_ctx* ctx, const Plan& pl, char* ws, const DecArgs& 
   if (!f64) zero(qop, (size_t)ellp * ldm * es);
   zero(q1, (size_t)ellp * ldm * 8);
   zero(q2, (size_t)ellp * ldn * 8);
+  if (ell <= kQr16Max) zero(ws + pl.o_q16 + qr16_work_bytes() - 256, 256);  // block counter
   HIPOK(launch_zero_ranges(z, s));
   // F64 path: the FP64 bases are the pass operands themselves
   const void* qsrc = f64 ? (const void*)q1 : qop;

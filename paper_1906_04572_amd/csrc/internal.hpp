@@ -111,6 +111,18 @@ hipError_t launch_chol(const double* G, int ell, double* R, double* Rinv, int* s
 hipError_t launch_trprod(const double* R2, const double* R1, int ell, double* R, const int* status,
                          hipStream_t st);
 
+// CholeskyQR2 of X (rows x ell, ell <= 16, column-major FP64, ld) in three
+// launches: Q (FP64, columns ell..15 zero; optional float copy), R (nullable,
+// ell x ell column-major: R2 R1, or R1 when one step suffices), status bits as
+// launch_chol (1: breakdown, the caller's Householder fallback runs; 2:
+// non-finite data; 4: one step, allowed when single_thr > 0).  X1: rows x 16
+// scratch (ld).  work: qr16_work_bytes() bytes whose last 256 bytes (the
+// block counter) must be zero before the first use; the kernels leave them
+// zero.
+size_t qr16_work_bytes();
+hipError_t launch_qr16(const double* X, double* X1, int64_t ld, int64_t rows, int ell, double* Q, float* Q32,
+                       double* R, int* status, double* work, double single_thr, hipStream_t st);
+
 // Householder thin QR of X (rows x ell, column-major FP64) -> Q (diag R >= 0,
 // FP64 and optionally a float copy), R (nullable); runs only when
 // (*status & 3) == 1 (a Cholesky breakdown on finite data).  work: rows x ell

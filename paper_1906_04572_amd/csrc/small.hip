@@ -685,6 +685,210 @@ __global__ void __launch_bounds__(1024) chol_kernel(const double* __restrict__ G
 }
 
 // ---------------------------------------------------------------------------
+// CholeskyQR2 of a sketch with l <= 16 columns in three launches (eq. 6):
+//   step 0: Gram of X;                      last block: R1, R1^-1 = chol(G)
+//   step 1: X1 = X R1^-1 and the Gram of X1; last block: R2, R2^-1, R = R2 R1
+//           (when the first step already suffices, status 4: Q = X R1^-1)
+//   step 2: Q = X1 R2^-1
+// The rows are split into nblk row blocks (one workgroup each); a block
+// stages 256 rows at a time in LDS and accumulates their Gram on FP64
+// matrix cores (v_mfma_f64_16x16x4f64: lane l feeds row 4t + l/16, column
+// l%16 as both operands), the four waves' sums are added in wave order and
+// written as the block's partial.  The last block to finish (a counter in
+// device memory, agent-scope fences on both sides) adds the partials in
+// block order and factors the Gram with the same one-wave 16 x 16 kernel,
+// breakdown rule and one-step rule as chol_kernel.  No block waits for
+// another.  Status bits as for chol_kernel; after bit 1 the Householder
+// fallback takes over from X.
+constexpr int kQ16MaxBlocks = 64;
+constexpr int kQ16Chunk = 256;
+
+struct Q16Args {
+  const double* x0;   // the sketch X (rows x l, column-major, ld)
+  double* x1;         // X1 (rows x 16, ld)
+  int64_t ld, rows;
+  int ell, nblk;
+  double* gpart;      // nblk x 256 partial Grams (row-major 16 x 16)
+  double* tiles;      // 4 x 256: R1, R1^-1, R2, R2^-1 (row-major 16 x 16)
+  double* rfac;       // nullable: R (l x l, column-major)
+  double* q64;        // Q (rows x 16, ld; columns l..15 zero)
+  float* q32;         // nullable float copy of Q (ld)
+  int* status;
+  int* counter;
+  double single_thr;
+};
+
+template <int STEP>
+__global__ void __launch_bounds__(256) q16_kernel(Q16Args a) {
+  __shared__ double tile[kQ16Chunk * 16];
+  __shared__ double rinv[256];
+  __shared__ double wacc[4][256];
+  __shared__ double gm[256], ex[256], xs[256];
+  __shared__ double red[8];
+  __shared__ int is_last;
+  const int sw = *a.status;
+  if (STEP >= 1 && (sw & 3)) return;  // breakdown or non-finite data: nothing to do here
+  if (STEP == 2 && (sw & 4)) return;  // the first step already wrote Q
+  const bool final1 = STEP == 1 && (sw & 4);
+  const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
+  const int ell = a.ell;
+  if (STEP >= 1) rinv[tid] = a.tiles[(STEP == 1 ? 1 : 3) * 256 + tid];
+  if (final1 && blockIdx.x == 0 && a.rfac && tid < ell * ell) {  // R = R1
+    const int i = tid % ell, j = tid / ell;
+    a.rfac[tid] = a.tiles[i * 16 + j];
+  }
+  __syncthreads();
+  const int64_t r0 = (int64_t)blockIdx.x * a.rows / a.nblk;
+  const int64_t r1 = (int64_t)(blockIdx.x + 1) * a.rows / a.nblk;
+  const double* src = STEP == 2 ? a.x1 : a.x0;
+  const bool gram = !(STEP == 2 || final1);
+  d4c acc = {0.0, 0.0, 0.0, 0.0};
+  // row i of the input from a clamped address (every load unconditional); the
+  // next chunk's row is loaded before the current one is used
+  auto load_row = [&](int64_t i, double* x) {
+    const int64_t ic = i < r1 ? i : r1 - 1;
+#pragma unroll
+    for (int k = 0; k < 16; ++k) x[k] = src[(int64_t)(k < ell ? k : ell - 1) * a.ld + ic];
+  };
+  double xn[16];
+  load_row(r0 + tid, xn);
+  for (int64_t c0 = r0; c0 < r1; c0 += kQ16Chunk) {
+    const int64_t i = c0 + tid;
+    double x[16];
+#pragma unroll
+    for (int k = 0; k < 16; ++k) x[k] = k < ell ? xn[k] : 0.0;
+    if (c0 + kQ16Chunk < r1) load_row(i + kQ16Chunk, xn);
+    double y[16];
+    if (i < r1) {
+      if (STEP == 0) {
+#pragma unroll
+        for (int j = 0; j < 16; ++j) y[j] = x[j];
+      } else {
+#pragma unroll
+        for (int j = 0; j < 16; ++j) {
+          double v = 0.0;
+#pragma unroll
+          for (int k = 0; k <= j; ++k) v = fma(x[k], rinv[k * 16 + j], v);
+          y[j] = j < ell ? v : 0.0;
+        }
+      }
+      if (STEP == 1 && !final1) {
+#pragma unroll
+        for (int j = 0; j < 16; ++j) a.x1[(int64_t)j * a.ld + i] = y[j];
+      } else if (STEP >= 1) {
+#pragma unroll
+        for (int j = 0; j < 16; ++j) {
+          a.q64[(int64_t)j * a.ld + i] = y[j];
+          if (a.q32) a.q32[(int64_t)j * a.ld + i] = (float)y[j];
+        }
+      }
+    } else {
+#pragma unroll
+      for (int j = 0; j < 16; ++j) y[j] = 0.0;
+    }
+    if (!gram) continue;
+#pragma unroll
+    for (int j = 0; j < 16; ++j) tile[tid * 16 + j] = y[j];
+    __syncthreads();
+#pragma unroll
+    for (int t = 0; t < 16; ++t) {
+      const double v = tile[(wave * 64 + 4 * t + (lane >> 4)) * 16 + (lane & 15)];
+      acc = __builtin_amdgcn_mfma_f64_16x16x4f64(v, v, acc, 0, 0, 0);
+    }
+    __syncthreads();
+  }
+  if (!gram) return;
+  // block partial: the four waves' sums in wave order
+#pragma unroll
+  for (int q = 0; q < 4; ++q) wacc[wave][((lane >> 4) + 4 * q) * 16 + (lane & 15)] = acc[q];
+  __syncthreads();
+  if (wave == 0) {
+#pragma unroll
+    for (int q = 0; q < 4; ++q) {
+      const int e = lane + 64 * q;
+      a.gpart[(int64_t)blockIdx.x * 256 + e] = ((wacc[0][e] + wacc[1][e]) + wacc[2][e]) + wacc[3][e];
+    }
+    __threadfence();  // the partial is visible device-wide before the count
+    if (lane == 0) is_last = atomicAdd(a.counter, 1) == a.nblk - 1;
+  }
+  __syncthreads();
+  if (!is_last) return;
+  __threadfence();  // every other block's partial is visible from here on
+  {
+    // every partial in flight at once (clamped addresses), then added in
+    // block order; the clamped extra terms are not added
+    double parts[kQ16MaxBlocks];
+#pragma unroll
+    for (int b = 0; b < kQ16MaxBlocks; ++b) parts[b] = a.gpart[(int64_t)(b < a.nblk ? b : 0) * 256 + tid];
+    double g = 0.0;
+#pragma unroll
+    for (int b = 0; b < kQ16MaxBlocks; ++b)
+      if (b < a.nblk) g += parts[b];
+    const int r = tid >> 4, c = tid & 15;
+    // identity in the padding, as chol_kernel
+    gm[tid] = (r < ell && c < ell) ? g : (r == c ? 1.0 : 0.0);
+  }
+  // breakdown threshold 4 l u max_i G_ii; a non-finite diagonal is bit 2
+  if (wave == 0) {
+    const double d = lane < ell ? gm[lane * 17] : 0.0;
+    double mx = isfinite(d) ? d : -1.0;
+    double bad = isfinite(d) ? 0.0 : 1.0;
+#pragma unroll
+    for (int off = 32; off > 0; off >>= 1) {
+      mx = fmax(mx, __shfl_xor(mx, off, 64));
+      bad = fmax(bad, __shfl_xor(bad, off, 64));
+    }
+    if (lane == 0) {
+      red[0] = mx;
+      red[1] = bad;
+    }
+  }
+  __syncthreads();
+  if (wave == 0) {
+    bool ok = false;
+    if (red[1] != 0.0) {
+      if (lane == 0) atomicOr(a.status, 2);
+    } else {
+      const double thr = 4.0 * ell * 2.220446049250313e-16 * red[0];
+      ok = chol_diag16(gm, 0, ell, thr, gm, ex, xs, lane);
+      if (!ok && lane == 0) atomicOr(a.status, 1);
+    }
+    if (ok) {
+      // R (upper, row-major) and R^-1 (xs, row-major) for the next launch
+      double* Rt = a.tiles + (STEP == 0 ? 0 : 2) * 256;
+      double* Ri = a.tiles + (STEP == 0 ? 1 : 3) * 256;
+      double ssr = 0.0, ssi = 0.0;
+#pragma unroll
+      for (int q = 0; q < 4; ++q) {
+        const int e = lane + 64 * q, r = e >> 4, c = e & 15;
+        const double vr = gm[e], vi = xs[e];
+        Rt[e] = vr;
+        Ri[e] = vi;
+        if (r < ell && c < ell) {
+          ssr += vr * vr;
+          ssi += vi * vi;
+        }
+      }
+      if (STEP == 0 && a.single_thr > 0.0) {
+        ssr = wave_sum_f64(ssr);
+        ssi = wave_sum_f64(ssi);
+        if (lane == 0 && 2.220446049250313e-16 * ell * ssr * ssi <= a.single_thr) atomicOr(a.status, 4);
+      }
+      if (STEP == 1 && a.rfac) {  // R = R2 R1, column-major l x l
+        const double* R1 = a.tiles;
+        for (int e = lane; e < ell * ell; e += 64) {
+          const int i = e % ell, j = e / ell;
+          double v = 0.0;
+          for (int t = i; t <= j; ++t) v = fma(gm[i * 16 + t], R1[t * 16 + j], v);
+          a.rfac[e] = i <= j ? v : 0.0;
+        }
+      }
+    }
+    if (lane == 0) atomicExch(a.counter, 0);  // ready for the next launch
+  }
+}
+
+// ---------------------------------------------------------------------------
 // Householder thin QR (fallback after a Cholesky breakdown).  A tall X is
 // factored as a two-level tree (TSQR, Demmel, Grigori, Hoemmen and Langou):
 // each of P row panels is reduced by Householder reflections in its own
@@ -1100,6 +1304,38 @@ hipError_t launch_add_cols(double* y, const double* x, int64_t rows, int cols, i
   if (rows == 0 || cols == 0) return hipSuccess;
   const int64_t bx = std::min<int64_t>((rows + 255) / 256, 64);
   add_cols_kernel<<<dim3((unsigned)bx, (unsigned)cols), dim3(256), 0, st>>>(y, x, rows, cols, ld);
+  return hipGetLastError();
+}
+
+int qr16_blocks(int64_t rows) {
+  const int64_t b = (rows + 1023) / 1024;
+  return (int)std::max<int64_t>(1, std::min<int64_t>(kQ16MaxBlocks, b));
+}
+
+size_t qr16_work_bytes() { return ((size_t)kQ16MaxBlocks * 256 + 4 * 256) * 8 + 256; }
+
+hipError_t launch_qr16(const double* X, double* X1, int64_t ld, int64_t rows, int ell, double* Q, float* Q32,
+                       double* R, int* status, double* work, double single_thr, hipStream_t st) {
+  if (ell < 1 || ell > 16 || rows < ell) return hipErrorInvalidValue;
+  Q16Args a;
+  a.x0 = X;
+  a.x1 = X1;
+  a.ld = ld;
+  a.rows = rows;
+  a.ell = ell;
+  a.nblk = qr16_blocks(rows);
+  a.gpart = work;
+  a.tiles = work + (size_t)kQ16MaxBlocks * 256;
+  a.counter = (int*)(a.tiles + 4 * 256);
+  a.rfac = R;
+  a.q64 = Q;
+  a.q32 = Q32;
+  a.status = status;
+  a.single_thr = single_thr;
+  const dim3 grid((unsigned)a.nblk);
+  q16_kernel<0><<<grid, dim3(256), 0, st>>>(a);
+  q16_kernel<1><<<grid, dim3(256), 0, st>>>(a);
+  q16_kernel<2><<<grid, dim3(256), 0, st>>>(a);
   return hipGetLastError();
 }
 

@@ -116,6 +116,61 @@ def test_f32_cases(ctx, m, n, k, p, q, layout):
     assert np.max(np.abs(V.T @ V - np.eye(ell))) <= 1e-5
 
 
+@pytest.mark.parametrize("m,n,k,p,q,tri,layout,prec", [
+    (70001, 300, 5, 5, 1, "auto", "col", "f64"),    # 64 row blocks, ragged; the frames shape
+    (300, 70001, 5, 5, 1, "auto", "row", "f64"),    # wide: the transposed problem
+    (5000, 1200, 12, 4, 2, "upper", "row", "f64"),  # l = 16
+    (1100, 900, 1, 0, 1, "lower", "col", "f64"),    # l = 1
+    (2047, 1025, 7, 2, 0, "auto", "row", "f64"),
+    (20000, 3000, 10, 6, 1, "auto", "row", "f32"),  # one-step route in FP32 storage
+    (3000, 20000, 10, 5, 2, "auto", "col", "bf16x3"),
+])
+def test_small_sketch_cholesky_qr_against_oracle(ctx, m, n, k, p, q, tri, layout, prec):
+    """Sketches with l <= 16 columns take the three-launch CholeskyQR2 (Gram
+    and Cholesky in the last row block to finish): F64 to the 1e-10 bars,
+    F32/BF16X3 |e_gpu - e_oracle| <= 1e-5, across block counts, ragged
+    blocks, l = 1 and l = 16, both triangles and layouts."""
+    _say("small-l QR", m, n, k, p, q, tri, layout, prec)
+    dt = np.float64 if prec == "f64" else np.float32
+    A = decaying(m, n, min(m, n) // 2, 1e-4, seed=m + 7 * n, kind="exp", tau=max(k / 2, 2)).astype(dt)
+    A64 = A.astype(np.float64)
+    ref = corutv(A64, k, p, q, seed=21, tri=tri)
+    if prec == "f64":
+        got = _run(ctx, A64, k, p, q, 21, "f64", tri, layout)
+        info = _check_f64(A64, k, p, q, 21, tri, got, ref)
+    else:
+        U, T, V, piv, info = _run(ctx, A, k, p, q, 21, prec, tri, layout)
+        e_ref = rel_err(A64, ref["U"], ref["T"], ref["V"])
+        assert abs(info["rel_err"] - e_ref) <= 1e-5, (info["rel_err"], e_ref)
+        ell = k + p
+        assert np.max(np.abs(U.T @ U - np.eye(ell))) <= 1e-5
+        assert np.max(np.abs(V.T @ V - np.eye(ell))) <= 1e-5
+    assert info["qr_fallbacks"] == 0
+
+
+@pytest.mark.parametrize("rows,ell,rank", [(70001, 10, 5), (300, 16, 3), (5000, 1, 0)])
+def test_small_sketch_breakdown_takes_householder(ctx, rows, ell, rank):
+    """A rank-deficient sketch with l <= 16: the three-launch CholeskyQR2
+    reports the breakdown and the Householder fallback gives an orthonormal
+    basis whose first `rank` columns (unique) equal the oracle's; through the
+    whole decomposition of an exactly rank-`rank` matrix (rank 0: the zero
+    matrix)."""
+    _say("small-l breakdown", rows, ell, rank)
+    rng = np.random.default_rng(rows + ell)
+    n = max(ell + 5, 40)
+    A = rng.standard_normal((rows, rank)) @ rng.standard_normal((rank, n)) if rank else np.zeros((rows, n))
+    U, T, V, piv, info = _run(ctx, A, ell, 0, 1, 3, "f64", "auto", "row")
+    assert info["qr_fallbacks"] >= 1
+    assert np.max(np.abs(U.T @ U - np.eye(ell))) <= 1e-13
+    assert np.max(np.abs(V.T @ V - np.eye(ell))) <= 1e-13
+    a_fro = max(np.linalg.norm(A), 1.0)
+    assert np.linalg.norm(A - U @ T @ V.T) <= 1e-12 * a_fro
+    if rank:
+        ref = corutv(A, ell, 0, 1, seed=3)
+        Ah, Ar = U @ T @ V.T, ref["U"] @ ref["T"] @ ref["V"].T
+        assert np.linalg.norm(Ah - Ar) <= 1e-10 * a_fro
+
+
 @pytest.mark.parametrize("prec", ["f32", "bf16x3", "f64"])
 def test_one_step_cholesky_qr_well_conditioned(ctx, prec):
     # exp(-i/25) decay: the sketches have condition numbers of a few dozen, so
