@@ -74,7 +74,7 @@ struct SketchArgs {
 // branch between the two load paths costs the compiler its exact count of
 // outstanding loads, and it then waits for more of them than needed.
 template <typename T, int MB, bool TRANS, int NB, bool VEC>
-__global__ void __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(sizeof(T) == 4 ? 3 : (MB <= 8 ? 2 : 1)))) sketch_kernel(SketchArgs a) {
+__global__ void __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(sizeof(T) == 4 ? (MB <= 8 ? 3 : 2) : (MB <= 8 ? 2 : 1)))) sketch_kernel(SketchArgs a) {
   using M = Mma<T>;
   using acc_t = typename M::acc;
   using v16 = typename M::v16;
@@ -307,10 +307,11 @@ __device__ __forceinline__ void split8(const float* x, bf8& hi, bf8& lo, bool wa
 // (split_bf16_kernel, same rounding), so it is staged into LDS as bf16 and
 // fed to the matrix cores without per-wave conversion.
 template <int MB, bool TRANS, int NB, bool X3, bool VEC>
-__global__ void __launch_bounds__(256) sketch_bf16_kernel(SketchArgs a) {
-  // k values per LDS stage: two MFMA blocks for BF16 (more bytes of A in
-  // flight per stage); one for BF16X3, whose registers allow no more
-  constexpr int KC = X3 ? 32 : 64;
+__global__ void __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(MB > 8 ? 2 : 1))) sketch_bf16_kernel(SketchArgs a) {
+  // k values per LDS stage: two MFMA blocks for BF16 up to 128 sketch columns
+  // (more bytes of A in flight per stage); one for BF16X3 and for wider
+  // sketches, whose registers allow no more
+  constexpr int KC = (X3 || MB > 8) ? 32 : 64;
   constexpr int KB = KC / 32;            // MFMA blocks per stage
   constexpr int ELLP = MB * 16;
   constexpr int LDKB = KC + 8;           // LDS row stride in bf16 (16 bytes of pad)
@@ -496,7 +497,7 @@ __global__ void split_bf16_kernel(const float* __restrict__ S, int64_t n, __bf16
 
 template <int MB, bool TRANS, bool X3, bool VEC>
 void* bf16_ptr() {
-  constexpr int NB = MB <= 8 ? 2 : 1;
+  constexpr int NB = 2;
   return (void*)&sketch_bf16_kernel<MB, TRANS, NB, X3, VEC>;
 }
 
@@ -525,7 +526,7 @@ void* pick_bf16(int mb) {
 
 template <typename T, int MB, bool TRANS, bool VEC>
 void* kernel_ptr() {
-  constexpr int NB = MB <= 8 ? 2 : 1;
+  constexpr int NB = 2;
   return (void*)&sketch_kernel<T, MB, TRANS, NB, VEC>;
 }
 
@@ -576,14 +577,14 @@ int occupancy_of(void* fn) {
 }
 
 // k values per stage of each kernel family
-int kc_of(int prec) { return prec == P_F64 ? 16 : (prec == P_BF16 ? 64 : 32); }
+int kc_of(int prec, int mb) { return prec == P_F64 ? 16 : (prec == P_BF16 && mb <= 8 ? 64 : 32); }
 
 constexpr int64_t kOneChunkBytes = 1 << 20;
 
 // gx: workgroups per XCD (the grid is 8 gx)
 void geometry(int64_t N, int64_t K, int ellp, int elem, int kc, int gx, Partials* p) {
   const int mb = ellp / 16;
-  const int nb = mb <= 8 ? 2 : 1;
+  const int nb = 2;
   const int tw = 64 * nb;
   p->ellp = ellp;
   p->tw = tw;
@@ -618,7 +619,7 @@ int64_t partials_capacity(int64_t n_out, int64_t k_len, int ellp, int prec) {
   // prec P_F32 stands for every float form (F32 and the bf16 ones)
   int64_t best = 0;
   const int elem = prec == P_F64 ? 8 : 4;
-  const int kcs[2] = {kc_of(prec), kc_of(P_BF16)};
+  const int kcs[2] = {kc_of(prec, ellp / 16), kc_of(P_BF16, ellp / 16)};
   for (int v = 0; v < (prec == P_F64 ? 1 : 2); ++v)
     for (int occ = 1; occ <= kOccCap; ++occ) {
       Partials p;
@@ -657,7 +658,7 @@ hipError_t launch_sketch(int prec, int trans, const void* A, int64_t lda, int64_
   const int64_t K = trans ? R : C;
   int gx = (num_cu / 8) * occupancy_of(fn);
   if (gx < 1) gx = 1;
-  const int kc = kc_of(prec);
+  const int kc = kc_of(prec, mb);
   geometry(N, K, ellp, elem, kc, gx, part);
   while (need_elems(*part) > part_elems && gx > 1) {
     gx = gx > 8 ? gx - 8 : gx - 1;
