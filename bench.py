@@ -137,18 +137,22 @@ def pass_roofline(prec, avg_pass_ms, m, n, ell):
 
 
 def device_decaying(torch, m, n, r, eps, seed, kind="exp", tau=25.0, alpha=1.5):
-    """A = U0 diag(sigma) V0^T + eps N drawn on the device (seeded torch
-    generator, float64, rounded to float32): the workload recipe at sizes the
-    host would take minutes to draw."""
+    """A = U0 diag(sigma) V0^T + eps N at sizes the host would take minutes to
+    form: the Haar factors U0, V0 are drawn on the host (numpy, seeded, QR of
+    Gaussians), the product and the noise (seeded torch generator) on the
+    device in float64, the result rounded to float32."""
+    from workloads import haar
+
     dev = torch.device("cuda", 0)
-    g = torch.Generator(device=dev)
-    g.manual_seed(seed)
-    U0 = torch.linalg.qr(torch.randn(m, r, generator=g, device=dev, dtype=torch.float64)).Q
-    V0 = torch.linalg.qr(torch.randn(n, r, generator=g, device=dev, dtype=torch.float64)).Q
+    rng = np.random.default_rng(seed)
+    U0 = torch.from_numpy(haar(rng, m, r)).to(dev)
+    V0 = torch.from_numpy(haar(rng, n, r)).to(dev)
     i = torch.arange(1, r + 1, device=dev, dtype=torch.float64)
     sig = torch.exp(-i / tau) if kind == "exp" else i ** -alpha
     A = (U0 * sig) @ V0.T.contiguous()
     del U0, V0
+    g = torch.Generator(device=dev)
+    g.manual_seed(seed)
     A += eps * torch.randn(m, n, generator=g, device=dev, dtype=torch.float64)
     A32 = A.float()
     del A

@@ -73,8 +73,10 @@ struct SketchArgs {
 // loads are allowed.  A template argument, not a runtime flag: a runtime
 // branch between the two load paths costs the compiler its exact count of
 // outstanding loads, and it then waits for more of them than needed.
-template <typename T, int MB, bool TRANS, int NB, bool VEC>
-__global__ void __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(sizeof(T) == 4 ? (MB <= 8 ? 3 : 2) : (MB <= 8 ? 2 : 1)))) sketch_kernel(SketchArgs a) {
+// WG waves per workgroup; they share each staged block of the skinny operand,
+// so a workgroup covers 16 NB WG output rows per tile.
+template <typename T, int MB, bool TRANS, int NB, bool VEC, int WG>
+__global__ void __launch_bounds__(64 * WG) __attribute__((amdgpu_waves_per_eu(sizeof(T) == 4 ? (MB <= 8 ? 3 : 2) : (MB <= 8 ? 2 : 1)))) sketch_kernel(SketchArgs a) {
   using M = Mma<T>;
   using acc_t = typename M::acc;
   using v16 = typename M::v16;
@@ -83,9 +85,10 @@ __global__ void __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(sizeof
   constexpr int KG = KC / 16;           // 16-k MFMA groups per stage
   constexpr int ELLP = MB * 16;
   constexpr int LDK = KC + E16;         // LDS row stride (one vector of pad)
-  constexpr int TW = 64 * NB;           // output rows per workgroup tile
+  constexpr int TW = 16 * NB * WG;      // output rows per workgroup tile
+  constexpr int NT = 64 * WG;           // threads
   constexpr int VPR = KC / E16;         // vectors per skinny row per stage
-  constexpr int SPASS = (ELLP * VPR + 255) / 256;
+  constexpr int SPASS = (ELLP * VPR + NT - 1) / NT;
   __shared__ __attribute__((aligned(16))) T lds_s[2][ELLP * LDK];
 
   const int tid = threadIdx.x;
@@ -129,7 +132,7 @@ __global__ void __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(sizeof
         // of the last chunk, with zero padding (library-internal buffers)
 #pragma unroll
         for (int p = 0; p < SPASS; ++p) {
-          const int v = tid + 256 * p;
+          const int v = tid + NT * p;
           const int c = min(v / VPR, ELLP - 1), kv = v % VPR;
           sreg[p] = *(const v16*)(S + (int64_t)c * a.lds + (int64_t)kb * KC + kv * E16);
         }
@@ -137,7 +140,7 @@ __global__ void __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(sizeof
       auto store_skinny = [&](int buf) {
 #pragma unroll
         for (int p = 0; p < SPASS; ++p) {
-          const int v = tid + 256 * p;
+          const int v = tid + NT * p;
           const int c = v / VPR, kv = v % VPR;
           if (c < ELLP) *(v16*)&lds_s[buf][c * LDK + kv * E16] = sreg[p];
         }
@@ -306,8 +309,8 @@ __device__ __forceinline__ void split8(const float* x, bf8& hi, bf8& lo, bool wa
 // The skinny operand arrives pre-split into bf16 hi (S) and lo (S2) parts
 // (split_bf16_kernel, same rounding), so it is staged into LDS as bf16 and
 // fed to the matrix cores without per-wave conversion.
-template <int MB, bool TRANS, int NB, bool X3, bool VEC>
-__global__ void __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(MB > 8 ? 2 : 1))) sketch_bf16_kernel(SketchArgs a) {
+template <int MB, bool TRANS, int NB, bool X3, bool VEC, int WG>
+__global__ void __launch_bounds__(64 * WG) __attribute__((amdgpu_waves_per_eu(MB > 8 ? 2 : 1))) sketch_bf16_kernel(SketchArgs a) {
   // k values per LDS stage: two MFMA blocks for BF16 up to 128 sketch columns
   // (more bytes of A in flight per stage); one for BF16X3 and for wider
   // sketches, whose registers allow no more
@@ -315,9 +318,10 @@ __global__ void __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(MB > 8
   constexpr int KB = KC / 32;            // MFMA blocks per stage
   constexpr int ELLP = MB * 16;
   constexpr int LDKB = KC + 8;           // LDS row stride in bf16 (16 bytes of pad)
-  constexpr int TW = 64 * NB;
+  constexpr int TW = 16 * NB * WG;
+  constexpr int NT = 64 * WG;
   constexpr int VPR = KC / 8;            // 16-byte vectors per skinny row per stage
-  constexpr int SPASS = (ELLP * VPR + 255) / 256;
+  constexpr int SPASS = (ELLP * VPR + NT - 1) / NT;
   constexpr int NPART = X3 ? 2 : 1;
   __shared__ __attribute__((aligned(16))) __bf16 lds_s[NPART][2][ELLP * LDKB];
 
@@ -358,7 +362,7 @@ __global__ void __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(MB > 8
         for (int h = 0; h < NPART; ++h)
 #pragma unroll
           for (int p = 0; p < SPASS; ++p) {
-            const int v = tid + 256 * p;
+            const int v = tid + NT * p;
             const int c = min(v / VPR, ELLP - 1), kv = v % VPR;
             sreg[h][p] = *(const f4*)(Sp[h] + (int64_t)c * a.lds + (int64_t)kb * KC + kv * 8);
           }
@@ -368,7 +372,7 @@ __global__ void __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(MB > 8
         for (int h = 0; h < NPART; ++h)
 #pragma unroll
           for (int p = 0; p < SPASS; ++p) {
-            const int v = tid + 256 * p;
+            const int v = tid + NT * p;
             const int c = v / VPR, kv = v % VPR;
             if (c < ELLP) *(f4*)&lds_s[h][buf][c * LDKB + kv * 8] = sreg[h][p];
           }
@@ -431,14 +435,8 @@ __global__ void __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(MB > 8
       load_b(gk0, bcur, mcur);
 #pragma unroll
       for (int e = 0; e < NB * KB * 8; ++e) bcur[e] = ((mcur >> e) & 1u) ? bcur[e] : 0.f;
-      for (int kb = gk0; kb < gk1; ++kb, ++iter) {
-        const int buf = iter & 1;
-        store_skinny(buf);
-        __syncthreads();
-        const int kn = kb + 1 < gk1 ? kb + 1 : kb;
-        load_skinny(kn);
-        load_b(kn, bnext, mnext);
-        __builtin_amdgcn_sched_barrier(0);  // loads ahead of the products
+      // products of one stage of A (bcur) with the staged skinny block buf
+      auto products = [&](int buf) {
 #pragma unroll
         for (int kk = 0; kk < KB; ++kk) {
           bf8 bh[NB], bl[NB];
@@ -460,8 +458,46 @@ __global__ void __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(MB > 8
             }
           }
         }
+      };
+      if constexpr (MB > 8 && !X3) {
+        // wide sketches in plain BF16 (one 32-k block per stage): two stages
+        // of A in flight (measured slower for BF16X3, whose products fill
+        // the time the second stage would cover).
+        // The two prefetch buffers alternate by stage parity (the loop body
+        // is written twice), so no register copy waits for a load in flight.
+        float bna[NB * KB * 8], bnb[NB * KB * 8];
+        uint32_t ma, mb2;
+        load_b(gk0 + 1 < gk1 ? gk0 + 1 : gk1 - 1, bna, ma);
+        load_b(gk0 + 2 < gk1 ? gk0 + 2 : gk1 - 1, bnb, mb2);
+        auto body = [&](int kb, float* bnx, uint32_t& mx) {
+          const int buf = iter & 1;
+          store_skinny(buf);
+          __syncthreads();
+          load_skinny(kb + 1 < gk1 ? kb + 1 : kb);
+          __builtin_amdgcn_sched_barrier(0);
+          products(buf);
 #pragma unroll
-        for (int e = 0; e < NB * KB * 8; ++e) bcur[e] = ((mnext >> e) & 1u) ? bnext[e] : 0.f;
+          for (int e = 0; e < NB * KB * 8; ++e) bcur[e] = ((mx >> e) & 1u) ? bnx[e] : 0.f;
+          load_b(kb + 3 < gk1 ? kb + 3 : gk1 - 1, bnx, mx);
+          ++iter;
+        };
+        for (int kb = gk0; kb < gk1; kb += 2) {
+          body(kb, bna, ma);
+          if (kb + 1 < gk1) body(kb + 1, bnb, mb2);
+        }
+      } else {
+        for (int kb = gk0; kb < gk1; ++kb, ++iter) {
+          const int buf = iter & 1;
+          store_skinny(buf);
+          __syncthreads();
+          const int kn = kb + 1 < gk1 ? kb + 1 : kb;
+          load_skinny(kn);
+          load_b(kn, bnext, mnext);
+          __builtin_amdgcn_sched_barrier(0);  // loads ahead of the products
+          products(buf);
+#pragma unroll
+          for (int e = 0; e < NB * KB * 8; ++e) bcur[e] = ((mnext >> e) & 1u) ? bnext[e] : 0.f;
+        }
       }
     }
     const int64_t slot = ((int64_t)x * a.gx + jw) * a.maxslot + (t - tfirst);
@@ -495,10 +531,19 @@ __global__ void split_bf16_kernel(const float* __restrict__ S, int64_t n, __bf16
   }
 }
 
+// Waves per workgroup of each pass kernel: eight (256 output rows sharing one
+// staged skinny block, half the skinny operand's L2 reads per byte of A) where
+// two waves per SIMD is the register limit anyway; four where the FP32 kernel
+// runs three waves per SIMD or the FP64 kernel needs one SIMD's registers per
+// wave.
+constexpr int wg_for(int prec, int mb) {
+  return prec == P_F64 ? 4 : (prec == P_F32 ? (mb > 8 ? 8 : 4) : 8);
+}
+
 template <int MB, bool TRANS, bool X3, bool VEC>
 void* bf16_ptr() {
   constexpr int NB = 2;
-  return (void*)&sketch_bf16_kernel<MB, TRANS, NB, X3, VEC>;
+  return (void*)&sketch_bf16_kernel<MB, TRANS, NB, X3, VEC, wg_for(P_BF16, MB)>;
 }
 
 template <bool TRANS, bool X3, bool VEC>
@@ -527,7 +572,7 @@ void* pick_bf16(int mb) {
 template <typename T, int MB, bool TRANS, bool VEC>
 void* kernel_ptr() {
   constexpr int NB = 2;
-  return (void*)&sketch_kernel<T, MB, TRANS, NB, VEC>;
+  return (void*)&sketch_kernel<T, MB, TRANS, NB, VEC, wg_for(sizeof(T) == 8 ? P_F64 : P_F32, MB)>;
 }
 
 template <typename T, bool TRANS, bool VEC>
@@ -560,14 +605,14 @@ constexpr int kOccCap = 4;
 std::mutex g_occ_mu;
 std::map<void*, int> g_occ;
 
-int occupancy_of(void* fn) {
+int occupancy_of(void* fn, int threads) {
   {
     std::lock_guard<std::mutex> lk(g_occ_mu);
     auto it = g_occ.find(fn);
     if (it != g_occ.end()) return it->second;
   }
   int occ = 0;
-  if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&occ, (const void*)fn, 256, 0) != hipSuccess)
+  if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&occ, (const void*)fn, threads, 0) != hipSuccess)
     occ = 1;
   if (occ < 1) occ = 1;
   occ = occ < kOccCap ? occ : kOccCap;
@@ -582,10 +627,9 @@ int kc_of(int prec, int mb) { return prec == P_F64 ? 16 : (prec == P_BF16 && mb 
 constexpr int64_t kOneChunkBytes = 1 << 20;
 
 // gx: workgroups per XCD (the grid is 8 gx)
-void geometry(int64_t N, int64_t K, int ellp, int elem, int kc, int gx, Partials* p) {
-  const int mb = ellp / 16;
+void geometry(int64_t N, int64_t K, int ellp, int elem, int kc, int gx, int wg, Partials* p) {
   const int nb = 2;
-  const int tw = 64 * nb;
+  const int tw = 16 * nb * wg;
   p->ellp = ellp;
   p->tw = tw;
   p->elem = elem;
@@ -619,13 +663,18 @@ int64_t partials_capacity(int64_t n_out, int64_t k_len, int ellp, int prec) {
   // prec P_F32 stands for every float form (F32 and the bf16 ones)
   int64_t best = 0;
   const int elem = prec == P_F64 ? 8 : 4;
-  const int kcs[2] = {kc_of(prec, ellp / 16), kc_of(P_BF16, ellp / 16)};
-  for (int v = 0; v < (prec == P_F64 ? 1 : 2); ++v)
-    for (int occ = 1; occ <= kOccCap; ++occ) {
-      Partials p;
-      geometry(n_out, k_len, ellp, elem, kcs[v], 32 * occ, &p);
-      const int64_t e = need_elems(p);
-      if (e > best) best = e;
+  // every stage depth and workgroup size of the float kernels (a cover)
+  const int kcs[3] = {16, 32, 64}, wgs[2] = {4, 8};
+  for (int v = 0; v < 3; ++v)
+    for (int w = 0; w < 2; ++w) {
+      if (prec == P_F64 && (kcs[v] != 16 || wgs[w] != 4)) continue;
+      if (prec != P_F64 && kcs[v] == 16) continue;
+      for (int occ = 1; occ <= kOccCap; ++occ) {
+        Partials p;
+        geometry(n_out, k_len, ellp, elem, kcs[v], 32 * occ, wgs[w], &p);
+        const int64_t e = need_elems(p);
+        if (e > best) best = e;
+      }
     }
   return best;
 }
@@ -656,13 +705,14 @@ hipError_t launch_sketch(int prec, int trans, const void* A, int64_t lda, int64_
   if (!fn) return hipErrorInvalidValue;
   const int64_t N = trans ? C : R;
   const int64_t K = trans ? R : C;
-  int gx = (num_cu / 8) * occupancy_of(fn);
+  const int wg = wg_for(prec == P_F64 ? P_F64 : (prec == P_F32 ? P_F32 : P_BF16), mb);
+  int gx = (num_cu / 8) * occupancy_of(fn, 64 * wg);
   if (gx < 1) gx = 1;
   const int kc = kc_of(prec, mb);
-  geometry(N, K, ellp, elem, kc, gx, part);
+  geometry(N, K, ellp, elem, kc, gx, wg, part);
   while (need_elems(*part) > part_elems && gx > 1) {
     gx = gx > 8 ? gx - 8 : gx - 1;
-    geometry(N, K, ellp, elem, kc, gx, part);
+    geometry(N, K, ellp, elem, kc, gx, wg, part);
   }
   if (need_elems(*part) > part_elems) return hipErrorInvalidValue;
   part->ptr = part_buf;
@@ -694,7 +744,7 @@ hipError_t launch_sketch(int prec, int trans, const void* A, int64_t lda, int64_
   a.gx = part->gx;
   a.maxslot = part->maxslot;
   void* args[] = {&a};
-  return hipLaunchKernel((const void*)fn, dim3(8 * gx), dim3(256), args, 0, st);
+  return hipLaunchKernel((const void*)fn, dim3(8 * gx), dim3(64 * wg), args, 0, st);
 }
 
 }  // namespace corutv
