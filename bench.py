@@ -493,6 +493,7 @@ def main():
     ap.add_argument("--no-precision-form", action="store_true", help="skip the 50000 x 30000 leg")
     ap.add_argument("--rpca-only", action="store_true", help="only run the robust PCA leg")
     ap.add_argument("--precision-form-only", action="store_true", help="only run the 50000 x 30000 leg")
+    ap.add_argument("--small-only", action="store_true", help="only run the 2000 x 1500 latency leg")
     ap.add_argument("--copy-calibration", action="store_true",
                     help="only run 4 plain 1 GiB device copies (calibrates the HBM byte counters)")
     ap.add_argument("--peaks", action="store_true",
@@ -527,6 +528,9 @@ def main():
         return
     if args.precision_form_only:
         print(json.dumps(c3_leg(cu, torch)), flush=True)
+        return
+    if args.small_only:
+        print(json.dumps(c1_leg(cu, torch)), flush=True)
         return
 
     dev = torch.device("cuda", 0)

@@ -25,6 +25,7 @@
 //    Each workgroup writes one partial tile per output tile it touches; the
 //    consumer kernel sums them in a fixed order, so results are
 //    deterministic (no atomics).
+#include <algorithm>
 #include <map>
 #include <mutex>
 
@@ -625,6 +626,7 @@ int occupancy_of(void* fn, int threads) {
 int kc_of(int prec, int mb) { return prec == P_F64 ? 16 : (prec == P_BF16 && mb <= 8 ? 64 : 32); }
 
 constexpr int64_t kOneChunkBytes = 1 << 20;
+constexpr int kMinUnits = 16;
 
 // gx: workgroups per XCD (the grid is 8 gx)
 void geometry(int64_t N, int64_t K, int ellp, int elem, int kc, int gx, int wg, Partials* p) {
@@ -640,9 +642,12 @@ void geometry(int64_t N, int64_t K, int ellp, int elem, int kc, int gx, int wg, 
   p->nchunk = K * ellp * elem <= kOneChunkBytes ? 1 : 8;
   p->nkx = (int)((nk + p->nchunk - 1) / p->nchunk);
   if (p->nkx < 1) p->nkx = 1;
-  gx = gx * 8 / p->nchunk;  // workgroups per chunk (the grid is 8 gx either way)
-  p->gx = gx;
+  gx = gx * 8 / p->nchunk;  // workgroups per chunk (the grid is nchunk gx)
   const int64_t U = (int64_t)p->tiles * p->nkx;
+  // a small pass keeps at least kMinUnits (tile, k-block) units per
+  // workgroup: fewer workgroups, and so fewer partial tiles to write and sum
+  if (U < (int64_t)gx * kMinUnits) gx = (int)std::max<int64_t>(1, U / kMinUnits);
+  p->gx = gx;
   int ms = 1;
   for (int j = 0; j < gx; ++j) {
     const int64_t u0 = (int64_t)j * U / gx, u1 = (int64_t)(j + 1) * U / gx;
@@ -744,7 +749,7 @@ hipError_t launch_sketch(int prec, int trans, const void* A, int64_t lda, int64_
   a.gx = part->gx;
   a.maxslot = part->maxslot;
   void* args[] = {&a};
-  return hipLaunchKernel((const void*)fn, dim3(8 * gx), dim3(64 * wg), args, 0, st);
+  return hipLaunchKernel((const void*)fn, dim3(part->nchunk * part->gx), dim3(64 * wg), args, 0, st);
 }
 
 }  // namespace corutv

@@ -1012,10 +1012,12 @@ __device__ void hh_apply(const double* __restrict__ W, int64_t ldw, int64_t rows
   }
 }
 
-constexpr int kHhLds = 7168;  // doubles of a matrix reduced in LDS (56 KB)
+constexpr int kHhLds = 7168;       // doubles of a panel reduced in LDS (56 KB)
+constexpr int kHhRootLds = 18432;  // doubles of LDS of the one-workgroup QR (144 KB)
 
 // One workgroup: X (rows x ell) -> Q (diag R >= 0), R (nullable, ld ell).
-// X is reduced in LDS when it fits, else in the workspace W.
+// The working copy of X and then Q are kept in LDS when both fit, else the
+// working copy alone, else both live in device memory (W and Q).
 __global__ void __launch_bounds__(1024) householder_kernel(const double* __restrict__ X,
                                                            int64_t ldx, int64_t rows, int ell,
                                                            double* __restrict__ W, int64_t ldw,
@@ -1024,14 +1026,18 @@ __global__ void __launch_bounds__(1024) householder_kernel(const double* __restr
                                                            double* __restrict__ R,
                                                            const int* status) {
   if ((*status & 3) != 1) return;  // only after a Cholesky breakdown
-  __shared__ double sw[kHhLds];
+  __shared__ double sw[kHhRootLds];
   __shared__ double tau[256], alpha[256], vhead[256];
   __shared__ double red[16];
   const int tid = threadIdx.x;
-  const bool lds = rows * ell <= kHhLds;
+  const int64_t n = rows * ell;
+  const bool lds = n <= kHhRootLds;
+  const bool qlds = 2 * n <= kHhRootLds;
   double* Wp = lds ? sw : W;
   const int64_t ldp = lds ? rows : ldw;
-  for (int64_t e = tid; e < rows * ell; e += 1024) {
+  double* Qp = qlds ? sw + n : Q;
+  const int64_t ldqp = qlds ? rows : ldq;
+  for (int64_t e = tid; e < n; e += 1024) {
     const int64_t i = e % rows;
     const int j = (int)(e / rows);
     Wp[(int64_t)j * ldp + i] = X[(int64_t)j * ldx + i];
@@ -1048,22 +1054,20 @@ __global__ void __launch_bounds__(1024) householder_kernel(const double* __restr
     }
   }
   // Q = H_0 ... H_{ell-1} [I; 0]
-  for (int64_t e = tid; e < rows * ell; e += 1024) {
+  for (int64_t e = tid; e < n; e += 1024) {
     const int64_t i = e % rows;
     const int j = (int)(e / rows);
-    Q[(int64_t)j * ldq + i] = i == j ? 1.0 : 0.0;
+    Qp[(int64_t)j * ldqp + i] = i == j ? 1.0 : 0.0;
   }
   __syncthreads();
-  hh_apply<1024>(Wp, ldp, rows, ell, tau, vhead, Q, ldq, true);
+  hh_apply<1024>(Wp, ldp, rows, ell, tau, vhead, Qp, ldqp, true);
   // sign normalisation diag(R) >= 0: flip the columns of Q with alpha < 0
-  for (int64_t e = tid; e < rows * ell; e += 1024) {
+  for (int64_t e = tid; e < n; e += 1024) {
     const int64_t i = e % rows;
     const int j = (int)(e / rows);
-    double v = Q[(int64_t)j * ldq + i];
-    if (alpha[j] < 0.0) {
-      v = -v;
-      Q[(int64_t)j * ldq + i] = v;
-    }
+    double v = Qp[(int64_t)j * ldqp + i];
+    if (alpha[j] < 0.0) v = -v;
+    if (qlds || alpha[j] < 0.0) Q[(int64_t)j * ldq + i] = v;
     if (Q32) Q32[(int64_t)j * ldq32 + i] = (float)v;
   }
 }
@@ -1137,7 +1141,8 @@ __global__ void __launch_bounds__(256) hh_expand_kernel(const double* __restrict
                                                         float* __restrict__ Q32, int64_t ldq32,
                                                         const int* status) {
   if ((*status & 3) != 1) return;
-  __shared__ double sw[kHhLds];
+  // LDS panels: the reflectors and the panel of Q both in LDS
+  __shared__ double sw[kHhLds], sq[kHhLds];
   __shared__ double tau[256], vhead[256];
   const int tid = threadIdx.x, b = blockIdx.x;
   int64_t r0, hb;
@@ -1147,22 +1152,26 @@ __global__ void __launch_bounds__(256) hh_expand_kernel(const double* __restrict
     tau[s] = tv[(int64_t)b * 2 * ell + s];
     vhead[s] = tv[(int64_t)b * 2 * ell + ell + s];
   }
+  double* Qp = lds ? sq : Q + r0;
+  const int64_t ldqp = lds ? hb : ldq;
   for (int64_t e = tid; e < hb * ell; e += 256) {
     const int64_t i = e % hb;
     const int j = (int)(e / hb);
-    Q[(int64_t)j * ldq + r0 + i] = i < ell ? Qr[(int64_t)j * ldr + (int64_t)b * ell + i] : 0.0;
+    Qp[(int64_t)j * ldqp + i] = i < ell ? Qr[(int64_t)j * ldr + (int64_t)b * ell + i] : 0.0;
     if (lds) sw[(int64_t)j * hb + i] = W[(int64_t)j * ldw + r0 + i];
   }
   __syncthreads();
   if (lds)
-    hh_apply<256>(sw, hb, hb, ell, tau, vhead, Q + r0, ldq, false);
+    hh_apply<256>(sw, hb, hb, ell, tau, vhead, sq, hb, false);
   else
     hh_apply<256>(W + r0, ldw, hb, ell, tau, vhead, Q + r0, ldq, false);
-  if (Q32) {
+  if (lds || Q32) {
     for (int64_t e = tid; e < hb * ell; e += 256) {
       const int64_t i = e % hb;
       const int j = (int)(e / hb);
-      Q32[(int64_t)j * ldq32 + r0 + i] = (float)Q[(int64_t)j * ldq + r0 + i];
+      const double v = Qp[(int64_t)j * ldqp + i];
+      if (lds) Q[(int64_t)j * ldq + r0 + i] = v;
+      if (Q32) Q32[(int64_t)j * ldq32 + r0 + i] = (float)v;
     }
   }
 }
