@@ -1177,6 +1177,285 @@ __global__ void __launch_bounds__(256) hh_expand_kernel(const double* __restrict
 }
 
 // ---------------------------------------------------------------------------
+// The same three Householder steps for l <= 64, organised for small l: thread
+// t serves column j = t % L (L = 16, 32 or 64 >= l) and the rows
+// i = t / L + G q (G = NT / L row groups), so every column operation of a
+// step (the norm, the dot products with the reflector, the update) runs for
+// all columns at once.  A sum over the rows adds each thread's partial sum
+// (its rows in increasing order) over the row groups: the lanes of a wave by
+// a butterfly over the group bits of the lane index, then the waves in wave
+// order through LDS (double-buffered: one barrier per sum); every thread
+// reads the column's total with the same bits.  Working copies in LDS are
+// row-major with row stride L + 1.
+template <bool RowMajor>
+struct HhMat {
+  double* p;
+  int64_t ld;
+  __device__ __forceinline__ double& at(int64_t i, int j) const { return RowMajor ? p[i * ld + j] : p[(int64_t)j * ld + i]; }
+};
+
+template <int NT, int L>
+__device__ __forceinline__ double col_sum_at(double part, double* red, int buf, int col) {
+  const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+#pragma unroll
+  for (int off = L; off < 64; off <<= 1) part = part + __shfl_xor(part, off, 64);
+  double* rb = red + buf * (NT / 64) * L;
+  if (lane < L) rb[wave * L + lane] = part;
+  __syncthreads();
+  double tot = 0.0;
+#pragma unroll
+  for (int w = 0; w < NT / 64; ++w) tot += rb[w * L + col];
+  return tot;
+}
+
+// Own rows i >= s of thread row group r: r + G q, the first one at or after s.
+template <int G>
+__device__ __forceinline__ int64_t hh_first_row(int r, int s) {
+  const int d = s - r;
+  return d <= 0 ? (int64_t)r : r + (int64_t)((d + G - 1) / G) * G;
+}
+
+// sum over own rows i >= s of v_i B(i, j), v_i = (i == s ? v0 : W(i, s)):
+// four rows in flight, four partial sums added as (a0 + a1) + (a2 + a3)
+template <int G, typename MB>
+__device__ __forceinline__ double hh_rows_dot(HhMat<true> W, MB B, int64_t rows, int r, int s, int j, double v0) {
+  double a0 = 0.0, a1 = 0.0, a2 = 0.0, a3 = 0.0;
+  int64_t i = hh_first_row<G>(r, s);
+  for (; i + 3 * G < rows; i += 4 * G) {
+    const double x0 = i == s ? v0 : W.at(i, s), x1 = W.at(i + G, s), x2 = W.at(i + 2 * G, s),
+                 x3 = W.at(i + 3 * G, s);
+    const double y0 = B.at(i, j), y1 = B.at(i + G, j), y2 = B.at(i + 2 * G, j), y3 = B.at(i + 3 * G, j);
+    a0 = fma(x0, y0, a0);
+    a1 = fma(x1, y1, a1);
+    a2 = fma(x2, y2, a2);
+    a3 = fma(x3, y3, a3);
+  }
+  for (; i < rows; i += G) a0 = fma(i == s ? v0 : W.at(i, s), B.at(i, j), a0);
+  return (a0 + a1) + (a2 + a3);
+}
+
+// B(i, j) -= d v_i over own rows i >= s
+template <int G, typename MB>
+__device__ __forceinline__ void hh_rows_axpy(HhMat<true> W, MB B, int64_t rows, int r, int s, int j, double v0,
+                                             double d) {
+  int64_t i = hh_first_row<G>(r, s);
+  if (i == s && i < rows) {
+    B.at(i, j) -= d * v0;
+    i += G;
+  }
+  for (; i + 3 * G < rows; i += 4 * G) {
+    const double x0 = W.at(i, s), x1 = W.at(i + G, s), x2 = W.at(i + 2 * G, s), x3 = W.at(i + 3 * G, s);
+    B.at(i, j) -= d * x0;
+    B.at(i + G, j) -= d * x1;
+    B.at(i + 2 * G, j) -= d * x2;
+    B.at(i + 3 * G, j) -= d * x3;
+  }
+  for (; i < rows; i += G) B.at(i, j) -= d * W.at(i, s);
+}
+
+// Householder reduction of the rows x ell matrix W (LDS, row-major) in place;
+// the same outputs as hh_factor.  red: 2 (NT/64) L doubles of LDS.
+template <int NT, int L>
+__device__ void hh_factor_s(HhMat<true> W, int64_t rows, int ell, double* tau, double* alpha, double* vhead,
+                            double* red) {
+  constexpr int G = NT / L;
+  const int t = threadIdx.x, j = t % L, r = t / L;
+  int buf = 0;  // consecutive sums use alternate halves of red
+  for (int s = 0; s < ell; ++s) {
+    // squared norm of column s over rows >= s (threads of column s)
+    double p = 0.0;
+    if (j == s) p = hh_rows_dot<G>(W, W, rows, r, s, s, W.at(s, s) /* v_s = x_s here */);
+    const double nrm2 = col_sum_at<NT, L>(p, red, buf, s);
+    buf ^= 1;
+    const double x0 = W.at(s, s);
+    const double nrm = sqrt(nrm2);
+    double ts = 0.0, v0 = 0.0, a = 0.0;
+    if (nrm != 0.0) {
+      a = x0 >= 0.0 ? -nrm : nrm;
+      v0 = x0 - a;
+      ts = 2.0 / (nrm2 - x0 * x0 + v0 * v0);
+    }
+    if (t == 0) {
+      tau[s] = ts;
+      alpha[s] = a;
+      vhead[s] = v0;
+    }
+    if (ts == 0.0) continue;  // uniform: a zero column needs no reflector
+    // d_j = tau v^T W[:, j] for the columns right of s, then the update
+    const bool act = j > s && j < ell;
+    double d = act ? hh_rows_dot<G>(W, W, rows, r, s, j, v0) : 0.0;
+    d = col_sum_at<NT, L>(d, red, buf, j) * ts;
+    buf ^= 1;
+    if (act) hh_rows_axpy<G>(W, W, rows, r, s, j, v0, d);
+  }
+  __syncthreads();
+}
+
+// Q <- H_0 ... H_{ell-1} Q with the reflectors of hh_factor_s in W (LDS,
+// row-major); identity: Q starts as [I; 0] (columns j < s untouched at s).
+template <int NT, int L, bool QRow>
+__device__ void hh_apply_s(HhMat<true> W, int64_t rows, int ell, const double* tau, const double* vhead,
+                           HhMat<QRow> Q, bool identity, double* red) {
+  constexpr int G = NT / L;
+  const int t = threadIdx.x, j = t % L, r = t / L;
+  int buf = 0;
+  for (int s = ell - 1; s >= 0; --s) {
+    const double ts = tau[s], v0 = vhead[s];
+    if (ts == 0.0) continue;
+    const bool act = j < ell && (!identity || j >= s);
+    double d = act ? hh_rows_dot<G>(W, Q, rows, r, s, j, v0) : 0.0;
+    d = col_sum_at<NT, L>(d, red, buf, j) * ts;
+    buf ^= 1;
+    if (act) hh_rows_axpy<G>(W, Q, rows, r, s, j, v0, d);
+  }
+  __syncthreads();
+}
+
+constexpr int kHhSmallLds = 17920;  // doubles of working copies in LDS (140 KB)
+
+// One workgroup (the root of the tree, or a whole short X): X (rows x ell,
+// column-major) -> Q (diag R >= 0), R (nullable).  W in LDS; Q in LDS when
+// both fit, else in device memory.
+template <int L, bool QInLds>
+__global__ void __launch_bounds__(1024) householder_s_kernel(const double* __restrict__ X, int64_t ldx,
+                                                             int64_t rows, int ell, double* __restrict__ Q,
+                                                             int64_t ldq, float* __restrict__ Q32, int64_t ldq32,
+                                                             double* __restrict__ R, const int* status) {
+  if ((*status & 3) != 1) return;
+  __shared__ double sw[kHhSmallLds];
+  __shared__ double tau[L], alpha[L], vhead[L];
+  __shared__ double red[2 * 16 * L];
+  const int tid = threadIdx.x;
+  // row stride L + 1 (no two rows of a column in one bank) when it fits, else L
+  const int64_t LS = (QInLds ? 2 : 1) * rows * (L + 1) <= kHhSmallLds ? L + 1 : L;
+  HhMat<true> W{sw, LS};
+  for (int64_t e = tid; e < rows * L; e += 1024) {
+    const int64_t i = e / L;
+    const int j = (int)(e % L);
+    W.at(i, j) = j < ell ? X[(int64_t)j * ldx + i] : 0.0;
+  }
+  __syncthreads();
+  hh_factor_s<1024, L>(W, rows, ell, tau, alpha, vhead, red);
+  if (R) {
+    for (int e = tid; e < ell * ell; e += 1024) {
+      const int i = e % ell, j = e / ell;
+      double v = i < j ? W.at(i, j) : (i == j ? alpha[i] : 0.0);
+      if (alpha[i] < 0.0) v = -v;
+      R[e] = v;
+    }
+  }
+  auto run = [&](auto Qm) {
+    for (int64_t e = tid; e < rows * L; e += 1024) {
+      const int64_t i = e / L;
+      const int j = (int)(e % L);
+      if (j < ell) Qm.at(i, j) = i == j ? 1.0 : 0.0;
+    }
+    __syncthreads();
+    hh_apply_s<1024, L>(W, rows, ell, tau, vhead, Qm, true, red);
+    for (int64_t e = tid; e < rows * L; e += 1024) {
+      const int64_t i = e / L;
+      const int j = (int)(e % L);
+      if (j >= ell) continue;
+      double v = Qm.at(i, j);
+      if (alpha[j] < 0.0) v = -v;
+      Q[(int64_t)j * ldq + i] = v;
+      if (Q32) Q32[(int64_t)j * ldq32 + i] = (float)v;
+    }
+  };
+  if constexpr (QInLds)
+    run(HhMat<true>{sw + rows * LS, LS});
+  else
+    run(HhMat<false>{Q, ldq});
+}
+
+// Tree level 1 for l <= 64: panel b (rows split evenly) reduced in LDS.
+template <int L>
+__global__ void __launch_bounds__(1024) hh_panel_s_kernel(const double* __restrict__ X, int64_t ldx, int64_t rows,
+                                                         int ell, int P, double* __restrict__ W, int64_t ldw,
+                                                         double* __restrict__ Rs, double* __restrict__ tv,
+                                                         const int* status) {
+  if ((*status & 3) != 1) return;
+  constexpr int LS = L + 1;
+  __shared__ double sw[kHhSmallLds];
+  __shared__ double tau[L], alpha[L], vhead[L];
+  __shared__ double red[2 * 16 * L];
+  const int tid = threadIdx.x, b = blockIdx.x;
+  const int64_t r0 = (int64_t)b * rows / P, hb = (int64_t)(b + 1) * rows / P - r0;
+  HhMat<true> Wm{sw, LS};
+  for (int64_t e = tid; e < hb * L; e += 1024) {
+    const int64_t i = e / L;
+    const int j = (int)(e % L);
+    Wm.at(i, j) = j < ell ? X[(int64_t)j * ldx + r0 + i] : 0.0;
+  }
+  __syncthreads();
+  hh_factor_s<1024, L>(Wm, hb, ell, tau, alpha, vhead, red);
+  const int64_t ldr = (int64_t)P * ell;
+  for (int e = tid; e < ell * ell; e += 1024) {
+    const int i = e % ell, j = e / ell;
+    Rs[(int64_t)j * ldr + (int64_t)b * ell + i] = i < j ? Wm.at(i, j) : (i == j ? alpha[i] : 0.0);
+  }
+  for (int q = tid; q < ell; q += 1024) {
+    tv[(int64_t)b * 2 * ell + q] = tau[q];
+    tv[(int64_t)b * 2 * ell + ell + q] = vhead[q];
+  }
+  // the reflectors (and R's entries above them) to W, column-major
+  for (int64_t e = tid; e < hb * ell; e += 1024) {
+    const int64_t i = e % hb;
+    const int j = (int)(e / hb);
+    W[(int64_t)j * ldw + r0 + i] = Wm.at(i, j);
+  }
+}
+
+// Tree level 2 for l <= 64: panel b of Q is its reflectors (staged in LDS)
+// applied to [Qr rows b ell ... ; 0]; the panel of Q in LDS when both fit.
+template <int L, bool QInLds>
+__global__ void __launch_bounds__(1024) hh_expand_s_kernel(const double* __restrict__ W, int64_t ldw, int64_t rows,
+                                                          int ell, int P, const double* __restrict__ Qr,
+                                                          const double* __restrict__ tv, double* __restrict__ Q,
+                                                          int64_t ldq, float* __restrict__ Q32, int64_t ldq32,
+                                                          const int* status) {
+  if ((*status & 3) != 1) return;
+  constexpr int LS = L + 1;
+  __shared__ double sw[kHhSmallLds];
+  __shared__ double tau[L], vhead[L];
+  __shared__ double red[2 * 16 * L];
+  const int tid = threadIdx.x, b = blockIdx.x;
+  const int64_t r0 = (int64_t)b * rows / P, hb = (int64_t)(b + 1) * rows / P - r0;
+  const int64_t ldr = (int64_t)P * ell;
+  for (int q = tid; q < ell; q += 1024) {
+    tau[q] = tv[(int64_t)b * 2 * ell + q];
+    vhead[q] = tv[(int64_t)b * 2 * ell + ell + q];
+  }
+  HhMat<true> Wm{sw, LS};
+  for (int64_t e = tid; e < hb * L; e += 1024) {
+    const int64_t i = e / L;
+    const int j = (int)(e % L);
+    Wm.at(i, j) = j < ell ? W[(int64_t)j * ldw + r0 + i] : 0.0;
+  }
+  auto run = [&](auto Qm) {
+    for (int64_t e = tid; e < hb * L; e += 1024) {
+      const int64_t i = e / L;
+      const int j = (int)(e % L);
+      if (j < ell) Qm.at(i, j) = i < ell ? Qr[(int64_t)j * ldr + (int64_t)b * ell + i] : 0.0;
+    }
+    __syncthreads();
+    hh_apply_s<1024, L>(Wm, hb, ell, tau, vhead, Qm, false, red);
+    for (int64_t e = tid; e < hb * L; e += 1024) {
+      const int64_t i = e / L;
+      const int j = (int)(e % L);
+      if (j >= ell) continue;
+      const double v = Qm.at(i, j);
+      if (QInLds) Q[(int64_t)j * ldq + r0 + i] = v;
+      if (Q32) Q32[(int64_t)j * ldq32 + r0 + i] = (float)v;
+    }
+  };
+  if constexpr (QInLds)
+    run(HhMat<true>{sw + hb * LS, LS});
+  else
+    run(HhMat<false>{Q + r0, ldq});
+}
+
+// ---------------------------------------------------------------------------
 __global__ void copy_tri_kernel(const double* __restrict__ src, int ell, int trans, int upper,
                                 double* __restrict__ dst, int64_t ldd) {
   const int e = blockIdx.x * blockDim.x + threadIdx.x;
@@ -1485,9 +1764,36 @@ hipError_t launch_householder_qr(const double* X, int64_t ldx, int64_t rows, int
                                  double* R, const int* status, double* hw, hipStream_t st) {
   const HhTree tr = hh_tree(rows, ell);
   const int P = tr.P;
+  // l <= 64: the kernels that work on all columns at once, where their LDS
+  // copies fit
+  const int L = ell <= 16 ? 16 : (ell <= 32 ? 32 : (ell <= 64 ? 64 : 0));
+  auto fits = [&](int64_t r, int copies) { return L > 0 && copies * r * L <= kHhSmallLds; };
+  auto fits_padded = [&](int64_t r, int copies) { return L > 0 && copies * r * (L + 1) <= kHhSmallLds; };
+  auto one_wg = [&](const double* x, int64_t ldxx, int64_t r, double* q, int64_t ldqq, float* q32, int64_t ldq32x,
+                    double* wk, int64_t ldwk) {
+    // (with Q in device memory the older kernel is the faster one)
+    if (!fits(r, 2)) {
+      householder_kernel<<<dim3(1), dim3(1024), 0, st>>>(x, ldxx, r, ell, wk, ldwk, q, ldqq, q32, ldq32x, R,
+                                                         status);
+      return;
+    }
+    const bool ql = true;
+#define CORUTV_HH_ONE(LL)                                                                                  \
+  if (L == LL) {                                                                                             \
+    if (ql)                                                                                                  \
+      householder_s_kernel<LL, true><<<dim3(1), dim3(1024), 0, st>>>(x, ldxx, r, ell, q, ldqq, q32, ldq32x, R, \
+                                                                    status);                                \
+    else                                                                                                     \
+      householder_s_kernel<LL, false><<<dim3(1), dim3(1024), 0, st>>>(x, ldxx, r, ell, q, ldqq, q32, ldq32x, R,\
+                                                                     status);                               \
+  }
+    CORUTV_HH_ONE(16)
+    CORUTV_HH_ONE(32)
+    CORUTV_HH_ONE(64)
+#undef CORUTV_HH_ONE
+  };
   if (P < 2) {
-    householder_kernel<<<dim3(1), dim3(1024), 0, st>>>(X, ldx, rows, ell, work, ldw, Q, ldq, Q32, ldq32,
-                                                       R, status);
+    one_wg(X, ldx, rows, Q, ldq, Q32, ldq32, work, ldw);
     return hipGetLastError();
   }
   if (!hw) return hipErrorInvalidValue;
@@ -1496,6 +1802,26 @@ hipError_t launch_householder_qr(const double* X, int64_t ldx, int64_t rows, int
   double* Rw = Rs + pe * ell;  // the root's working copy
   double* Qr = Rw + pe * ell;  // the root's Q
   double* tv = Qr + pe * ell;  // per panel: tau[ell], vhead[ell]
+  const int64_t hb = (rows + P - 1) / P;  // rows of the largest LDS panel
+  if (tr.lds && fits_padded(hb, 1)) {
+    const bool ql = fits_padded(hb, 2);
+#define CORUTV_HH_TREE(LL)                                                                                      \
+  if (L == LL) {                                                                                                  \
+    hh_panel_s_kernel<LL><<<dim3(P), dim3(1024), 0, st>>>(X, ldx, rows, ell, P, work, ldw, Rs, tv, status);        \
+    one_wg(Rs, pe, pe, Qr, pe, nullptr, 0, Rw, pe);                                                               \
+    if (ql)                                                                                                       \
+      hh_expand_s_kernel<LL, true><<<dim3(P), dim3(1024), 0, st>>>(work, ldw, rows, ell, P, Qr, tv, Q, ldq, Q32,   \
+                                                                 ldq32, status);                                 \
+    else                                                                                                          \
+      hh_expand_kernel<<<dim3(P), dim3(256), 0, st>>>(work, ldw, rows, ell, tr.h, P, tr.lds, Qr, tv, Q, ldq, Q32,  \
+                                                      ldq32, status);                                            \
+  }
+    CORUTV_HH_TREE(16)
+    CORUTV_HH_TREE(32)
+    CORUTV_HH_TREE(64)
+#undef CORUTV_HH_TREE
+    return hipGetLastError();
+  }
   hh_panel_kernel<<<dim3(P), dim3(256), 0, st>>>(X, ldx, rows, ell, tr.h, P, tr.lds, work, ldw, Rs, tv,
                                                  status);
   householder_kernel<<<dim3(1), dim3(1024), 0, st>>>(Rs, pe, pe, ell, Rw, pe, Qr, pe, nullptr, 0, R,
