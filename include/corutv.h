@@ -238,6 +238,13 @@ int corutv_rpca(corutv_ctx* ctx, const corutv_mat* M, double lambda, int32_t k, 
                 corutv_mat* L, corutv_mat* S, corutv_rpca_info* info);
 /* Workspace bytes corutv_rpca needs for an m x n input (0 for invalid sizes). */
 uint64_t corutv_rpca_workspace_bytes(int64_t m, int64_t n, int32_t k, int32_t p, int32_t q);
+/* The rank history of the last successful corutv_rpca call on ctx (Sec. 4,
+ * Algorithm 2, eq. 12): r_j, the number of diagonal entries of T_j above
+ * 1/mu_j that iteration j kept, for the first min(iterations, 4096)
+ * iterations.  Writes min(n, that count) entries to ranks (host memory,
+ * nullable when n = 0) and the count to *count (nullable).  Returns E_INVAL
+ * for a null ctx or n < 0. */
+int corutv_rpca_ranks(corutv_ctx* ctx, int32_t* ranks, int32_t n, int32_t* count);
 
 /* ---- serving ------------------------------------------------------------
  * Non-blocking decompositions with continuous batching: requests queue on the

@@ -106,6 +106,7 @@ def _load():
         "corutv_tsqr": (ctypes.c_int, [P, P, I64, I32, I64, P, I64, P, I64, ctypes.POINTER(I32)]),
         "corutv_qrcp": (ctypes.c_int, [P, I32, P, I64, P, P, P]),
         "corutv_rpca_workspace_bytes": (U64, [I64, I64, I32, I32, I32]),
+        "corutv_rpca_ranks": (ctypes.c_int, [P, ctypes.POINTER(I32), I32, ctypes.POINTER(I32)]),
         "corutv_pass_timing": (ctypes.c_int, [P, I32, I32]),
         "corutv_get_pass_stats": (ctypes.c_int, [P, ctypes.POINTER(PassStats)]),
         "corutv_debug_inject_failure": (ctypes.c_int, [P, I32]),
@@ -324,7 +325,17 @@ class Context:
                              ctypes.byref(opts), ctypes.byref(ml) if ml is not None else None,
                              ctypes.byref(ms), ctypes.byref(info))
         _check(rc, "rpca")
-        return L, S, info.as_dict()
+        out = info.as_dict()
+        out["ranks"] = self.rpca_ranks()
+        return L, S, out
+
+    def rpca_ranks(self):
+        """r_j of every iteration of the last rpca call (up to 4096)."""
+        cnt = ctypes.c_int32()
+        _check(lib.corutv_rpca_ranks(self.h, None, 0, ctypes.byref(cnt)), "rpca_ranks")
+        buf = (ctypes.c_int32 * max(cnt.value, 1))()
+        _check(lib.corutv_rpca_ranks(self.h, buf, cnt.value, None), "rpca_ranks")
+        return [int(buf[i]) for i in range(cnt.value)]
 
     # -- serving --------------------------------------------------------------
     def submit(self, A, k, p, q, seed, prec="f64", tri="auto", want_err=False, out=None, core="pass"):

@@ -185,6 +185,8 @@ struct corutv_ctx {
   hipEvent_t stage_ev[5] = {};  // ready[2], free[2], start
   // start / end of a blocking decomposition (created on first use)
   hipEvent_t dec_ev[2] = {};
+  // r_j of the last corutv_rpca call (Algorithm 2)
+  std::vector<int32_t> rank_hist;
 };
 
 namespace {
@@ -265,7 +267,9 @@ struct Enqueued {
 };
 
 // Thin QR of the sketch held in the stream-K partials `pp` (rows x ell):
-// CholeskyQR2 with FP64 Gram and Cholesky, Householder after a breakdown.
+// CholeskyQR2 with FP64 Gram and Cholesky, Householder after a breakdown;
+// sketches of at most 16 columns take Householder directly (where its
+// register-resident kernels cover the rows).
 // Outputs: q64 (FP64, may be scratch) and, for the F32 path, q32.
 // one_step: the first Cholesky may decide (status 4) that a second step is
 // not needed; then Q = X R1^-1 goes straight to the outputs and the kernels
@@ -286,6 +290,9 @@ hipError_t qr_from_partials(const Plan& pl, char* ws, const Partials& pp, int64_
   hipError_t e;
   // summed: the sketch is already in x0 (passes over a host-resident A)
   if (!summed && (e = launch_sum_partials(pp, ell, pl.ellp, x0, nullptr, ld, s)) != hipSuccess) return e;
+  if (hhr_direct(rows, ell))  // few columns: Householder directly, in registers
+    return launch_householder_qr(x0, ld, rows, ell, x1, ld, q64, ld, q32, ld, rfac, st, (double*)(ws + pl.o_hh),
+                                 s, 1);
   if (ell <= kQr16Max) {
     if ((e = launch_qr16(x0, x1, ld, rows, ell, q64, q32, rfac, st, (double*)(ws + pl.o_q16),
                          one_step ? kOneStepThr : 0.0, s)) != hipSuccess)
@@ -1324,11 +1331,14 @@ int corutv_destroy(corutv_ctx* ctx) {
 // ALM-CoRUTV (Sec. 4, Algorithm 2)
 namespace {
 
+// iterations whose r_j is recorded
+constexpr int kRankHist = 4096;
+
 struct RpcaPlan {
   Plan dec;
   int ell = 0;
   size_t o_y = 0, o_b = 0, o_u = 0, o_v = 0, o_t = 0, o_tt = 0, o_p = 0, o_q = 0, o_part = 0,
-         o_sum = 0, o_flag = 0;
+         o_sum = 0, o_flag = 0, o_hist = 0;
   size_t total = 0;
 };
 
@@ -1353,11 +1363,21 @@ bool make_rpca_plan(int64_t m, int64_t n, int k, int p, int q, RpcaPlan* rp) {
   rp->o_part = take((size_t)rpca_partial_blocks() * 8);
   rp->o_sum = take(4 * 8);
   rp->o_flag = take(16);
+  rp->o_hist = take(kRankHist * sizeof(int32_t));
   rp->total = off;
   return true;
 }
 
 }  // namespace
+
+extern "C" int corutv_rpca_ranks(corutv_ctx* ctx, int32_t* ranks, int32_t n, int32_t* count) {
+  if (!ctx || n < 0 || (n > 0 && !ranks)) return CORUTV_E_INVAL;
+  std::lock_guard<std::mutex> lk(ctx->run_mu);
+  const int32_t c = (int32_t)ctx->rank_hist.size();
+  for (int32_t i = 0; i < std::min(n, c); ++i) ranks[i] = ctx->rank_hist[i];
+  if (count) *count = c;
+  return CORUTV_OK;
+}
 
 extern "C" uint64_t corutv_rpca_workspace_bytes(int64_t m, int64_t n, int32_t k, int32_t p, int32_t q) {
   RpcaPlan rp;
@@ -1399,6 +1419,7 @@ extern "C" int corutv_rpca(corutv_ctx* ctx, const corutv_mat* M, double lambda, 
   double* part = (double*)(ws + rp.o_part);
   double* sum = (double*)(ws + rp.o_sum);
   int* sticky = (int*)(ws + rp.o_flag);  // OR of the loop's QR status words
+  int* hist = (int*)(ws + rp.o_hist);     // r_j per iteration
   const int nb = rpca_partial_blocks();
   // Y and B share M's layout, packed
   const int lay = M->layout;
@@ -1490,13 +1511,14 @@ extern "C" int corutv_rpca(corutv_ctx* ctx, const corutv_mat* M, double lambda, 
     HIPOK(launch_rpca_elementwise((const float*)M->ptr, lay, M->ld, (float*)S->ptr, S->layout, S->ld, Y,
                                   ldi, last ? nullptr : B, ldi, want_l ? (float*)L->ptr : nullptr,
                                   L ? L->layout : CORUTV_COL_MAJOR, L ? L->ld : 1, m, n, P, m, Q, n, T,
-                                  ell, ell, mu, mu_next, lambda, part, eq.dev_status, eq.nqr, sticky, s));
+                                  ell, ell, mu, mu_next, lambda, part, eq.dev_status, eq.nqr, sticky,
+                                  j < kRankHist ? hist + j : nullptr, s));
     if (ctx->timing) hipEventRecord(ctx->ev_pool[2 * j + 1], s);
-    HIPOK(launch_reduce(part, nb, 1, sum, nullptr, s));
     iters = j + 1;
     mu_last = mu;
     mu = mu_next;
-    if (tol > 0 || last) {
+    if (tol > 0 || last) {  // the residual is needed: sum the step's partials
+      HIPOK(launch_reduce(part, nb, 1, sum, nullptr, s));
       double zs = 0;
       int flags = 0;
       HIPOK(hipMemcpyAsync(&zs, sum, 8, hipMemcpyDeviceToHost, s));
@@ -1511,6 +1533,8 @@ extern "C" int corutv_rpca(corutv_ctx* ctx, const corutv_mat* M, double lambda, 
   // final rank: diagonal entries of the last T above 1/mu_last
   std::vector<double> Th((size_t)ell * ell);
   HIPOK(hipMemcpyAsync(Th.data(), T, Th.size() * 8, hipMemcpyDeviceToHost, s));
+  std::vector<int32_t> rh((size_t)std::min(iters, kRankHist));
+  if (!rh.empty()) HIPOK(hipMemcpyAsync(rh.data(), hist, rh.size() * 4, hipMemcpyDeviceToHost, s));
   hipEventRecord(e1, s);
   if (hipStreamSynchronize(s) != hipSuccess) return poison(ctx);
   float ms = 0;
@@ -1522,6 +1546,7 @@ extern "C" int corutv_rpca(corutv_ctx* ctx, const corutv_mat* M, double lambda, 
       if (hipEventElapsedTime(&em, ctx->ev_pool[2 * j], ctx->ev_pool[2 * j + 1]) == hipSuccess) step_ms += em;
     }
   }
+  ctx->rank_hist.swap(rh);
   int r = 0;  // diagonal entries above the last threshold (eq. 12)
   for (int i = 0; i < ell; ++i) r += Th[(size_t)i * ell + i] > 1.0 / mu_last ? 1 : 0;
   if (info) {

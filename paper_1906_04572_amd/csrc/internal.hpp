@@ -125,14 +125,19 @@ hipError_t launch_qr16(const double* X, double* X1, int64_t ld, int64_t rows, in
 
 // Householder thin QR of X (rows x ell, column-major FP64) -> Q (diag R >= 0,
 // FP64 and optionally a float copy), R (nullable); runs only when
-// (*status & 3) == 1 (a Cholesky breakdown on finite data).  work: rows x ell
-// (must not overlap X or Q); hw: hh_work_bytes(rows, ell) bytes for the
-// two-level tree of a tall X (nullable when that is 0).
+// (*status & 3) == 1 (a Cholesky breakdown on finite data), or always with
+// force (the direct route, which sets status bit 2 on non-finite data; only
+// where hhr_direct(rows, ell) holds).  work: rows x ell (must not overlap X
+// or Q); hw: hh_work_bytes(rows, ell) bytes for the two-level tree of a tall
+// X (nullable when that is 0).
 hipError_t launch_householder_qr(const double* X, int64_t ldx, int64_t rows, int ell, double* work,
                                  int64_t ldw, double* Q, int64_t ldq, float* Q32, int64_t ldq32,
-                                 double* R, const int* status, double* hw, hipStream_t st);
+                                 double* R, int* status, double* hw, hipStream_t st, int force = 0);
 int hh_panels(int64_t rows, int ell);
 size_t hh_work_bytes(int64_t rows, int ell);
+// Whether a sketch of rows x ell takes Householder QR directly (ell <= 16 and
+// the register-resident kernels cover rows).
+bool hhr_direct(int64_t rows, int ell);
 hipError_t launch_fill_int(int* p, int n, int v, hipStream_t st);
 
 // Up to kZeroRanges device ranges to clear in one launch: ptr[r] 16-byte
@@ -166,9 +171,10 @@ hipError_t launch_residual(const void* A, int dtype, int64_t lda, int64_t R, int
 
 // RPCA elementwise step (rpca.hip): S, Y (and B for the next iteration, L if
 // non-null) from M and the rank-r factors P (m x ell), Q (n x ell) with r the
-// number of diagonal entries of T above 1/mu; per-block sums of the squared
-// residual M - L - S go to part[rpca_partial_blocks()].  The nstatus status
-// words of the iteration's decomposition are OR-ed into *sticky (nullable).
+// number of diagonal entries of T above 1/mu (written to *rank_out when that
+// is non-null); per-block sums of the squared residual M - L - S go to
+// part[rpca_partial_blocks()].  The nstatus status words of the iteration's
+// decomposition are OR-ed into *sticky (nullable).
 int rpca_partial_blocks();
 hipError_t launch_rpca_elementwise(const float* M, int lay_m, int64_t ldm, float* S, int lay_s,
                                    int64_t lds, double* Y, int64_t ldy, double* B, int64_t ldb, float* L,
@@ -176,7 +182,7 @@ hipError_t launch_rpca_elementwise(const float* M, int lay_m, int64_t ldm, float
                                    int64_t ldp, const double* Q, int64_t ldq, const double* T,
                                    int64_t ldt, int ell, double mu, double mu_next, double lambda,
                                    double* part, const int* status, int nstatus, int* sticky,
-                                   hipStream_t st);
+                                   int* rank_out, hipStream_t st);
 hipError_t launch_sumsq(const float* X, int lay, int64_t ld, int64_t m, int64_t n, double* part,
                         hipStream_t st);
 hipError_t launch_widen(const float* X, int lay, int64_t ld, int64_t m, int64_t n, double* B, int64_t ldb,

@@ -45,6 +45,7 @@ struct RpcaArgs {
   const int* st;  // status words of the iteration's decomposition
   int nst;
   int* sticky;    // OR of every status word seen so far
+  int* rank_out;  // nullable: receives r
 };
 
 __device__ __forceinline__ int64_t at(int lay, int64_t ld, int64_t i, int64_t j) {
@@ -69,10 +70,13 @@ __global__ void __launch_bounds__(256) rpca_step_kernel(RpcaArgs a) {
     atomicAdd(&rs, 1);
   __syncthreads();
   const int r = rs;
-  if (blockIdx.x == 0 && threadIdx.x == 0 && a.sticky) {
-    int acc = *a.sticky;
-    for (int i = 0; i < a.nst; ++i) acc |= a.st[i];
-    *a.sticky = acc;
+  if (blockIdx.x == 0 && threadIdx.x == 0) {
+    if (a.sticky) {
+      int acc = *a.sticky;
+      for (int i = 0; i < a.nst; ++i) acc |= a.st[i];
+      *a.sticky = acc;
+    }
+    if (a.rank_out) *a.rank_out = r;
   }
   const bool colmaj = a.lay_m == CORUTV_COL_MAJOR;
   const int64_t len = colmaj ? a.m : a.n;     // elements along a storage line
@@ -176,7 +180,7 @@ hipError_t launch_rpca_elementwise(const float* M, int lay_m, int64_t ldm, float
                                    int64_t ldp, const double* Q, int64_t ldq, const double* T,
                                    int64_t ldt, int ell, double mu, double mu_next, double lambda,
                                    double* part, const int* status, int nstatus, int* sticky,
-                                   hipStream_t st) {
+                                   int* rank_out, hipStream_t st) {
   RpcaArgs a;
   a.M = M;
   a.S = S;
@@ -208,6 +212,7 @@ hipError_t launch_rpca_elementwise(const float* M, int lay_m, int64_t ldm, float
   a.st = status;
   a.nst = nstatus;
   a.sticky = sticky;
+  a.rank_out = rank_out;
   rpca_step_kernel<<<dim3(kRpcaBlocks), dim3(256), 0, st>>>(a);
   return hipGetLastError();
 }

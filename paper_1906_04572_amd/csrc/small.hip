@@ -1456,6 +1456,400 @@ __global__ void __launch_bounds__(1024) hh_expand_s_kernel(const double* __restr
 }
 
 // ---------------------------------------------------------------------------
+// Householder QR with the working matrix in registers (l <= 64, panels of at
+// most 16 rows per thread).  Thread t serves column j = t % L and the rows
+// i = r + G q (r = t / L, G = 1024 / L, q < R) of its panel, holding W(i, j)
+// in w[q].  One step s needs column s at every thread of a row group (the
+// row group's lane s holds it): a DPP row broadcast for L = 16, register
+// reads of the one or two row groups of a wave otherwise.  Each step takes a
+// single sum over the rows: p_j = x^T W(:, j) over rows >= s, x = column s,
+// gives both ||x||^2 (j = s) and, with the pivot row W(s, :), the reflector
+// products v^T W(:, j) = p_j - alpha W(s, j) (v = x - alpha e_s).  A sum
+// over the rows adds each thread's partial sum (rows in increasing order, in
+// four partial sums) over the row groups of a wave by a butterfly; then the
+// first wave adds the waves' sums in wave order and publishes the column
+// totals (two barriers; every thread reading all the waves' sums would cost
+// more LDS bandwidth than the second barrier).
+template <int S>
+__device__ __forceinline__ double hhr_bc16_one(double v) {
+  // v_mov_b64_dpp row_newbcast:S
+  return __longlong_as_double(__builtin_amdgcn_update_dpp(0LL, __double_as_longlong(v), 0x150 + S, 0xF, 0xF, false));
+}
+
+template <int S, int R>
+__device__ __forceinline__ void hhr_bc16(const double (&w)[R], double (&x)[R]) {
+#pragma unroll
+  for (int q = 0; q < R; ++q) x[q] = hhr_bc16_one<S>(w[q]);
+}
+
+// x[q] = the value of column s (uniform) in w[q] of the thread's row group
+template <int L, int R>
+__device__ __forceinline__ void hhr_col(const double (&w)[R], double (&x)[R], int s) {
+  if constexpr (L == 16) {
+    switch (s) {
+      case 0: hhr_bc16<0, R>(w, x); break;
+      case 1: hhr_bc16<1, R>(w, x); break;
+      case 2: hhr_bc16<2, R>(w, x); break;
+      case 3: hhr_bc16<3, R>(w, x); break;
+      case 4: hhr_bc16<4, R>(w, x); break;
+      case 5: hhr_bc16<5, R>(w, x); break;
+      case 6: hhr_bc16<6, R>(w, x); break;
+      case 7: hhr_bc16<7, R>(w, x); break;
+      case 8: hhr_bc16<8, R>(w, x); break;
+      case 9: hhr_bc16<9, R>(w, x); break;
+      case 10: hhr_bc16<10, R>(w, x); break;
+      case 11: hhr_bc16<11, R>(w, x); break;
+      case 12: hhr_bc16<12, R>(w, x); break;
+      case 13: hhr_bc16<13, R>(w, x); break;
+      case 14: hhr_bc16<14, R>(w, x); break;
+      default: hhr_bc16<15, R>(w, x); break;
+    }
+  } else if constexpr (L == 32) {
+    const bool upper = (threadIdx.x & 63) >= 32;
+#pragma unroll
+    for (int q = 0; q < R; ++q) {
+      const double a = readlane_f64(w[q], s), b = readlane_f64(w[q], s + 32);
+      x[q] = upper ? b : a;
+    }
+  } else {
+#pragma unroll
+    for (int q = 0; q < R; ++q) x[q] = readlane_f64(w[q], s);
+  }
+}
+
+// The one reflector step of hhr_apply with the broadcast taken per row
+// instead of into a register array (the apply holds two arrays already):
+// MODE 0 returns the partial sum of v_i y_i over own rows i >= s (< nr),
+// MODE 1 applies y_i -= d v_i; v_i = column s of w, v_s = v0.
+template <int L, int R, int MODE, typename BC>
+__device__ __forceinline__ double hhr_refl_rows(BC bc, const double (&w)[R], double (&y)[R], int r, int s,
+                                                double v0, double d, int nr) {
+  constexpr int G = 1024 / L, QM = (L + G - 1) / G;
+  double a[4] = {0.0, 0.0, 0.0, 0.0};
+#pragma unroll
+  for (int q = 0; q < R; ++q) {
+    double v = bc(w[q]);
+    if (q < QM) {  // rows below L: the head and the rows above it
+      const int i = r + G * q;
+      v = i == s ? v0 : (i > s ? v : 0.0);
+    }
+    if (MODE == 0) a[q & 3] = fma(v, y[q], a[q & 3]);
+    else y[q] = fma(-d, v, y[q]);
+  }
+  return (a[0] + a[1]) + (a[2] + a[3]);
+}
+
+template <int L, int R, int MODE>
+__device__ __forceinline__ double hhr_refl(const double (&w)[R], double (&y)[R], int r, int s, double v0, double d,
+                                           int nr) {
+  if constexpr (L == 16) {
+    switch (s) {
+#define CORUTV_RF(S) \
+  case S:            \
+    return hhr_refl_rows<L, R, MODE>([](double v) { return hhr_bc16_one<S>(v); }, w, y, r, s, v0, d, nr);
+      CORUTV_RF(0) CORUTV_RF(1) CORUTV_RF(2) CORUTV_RF(3) CORUTV_RF(4) CORUTV_RF(5) CORUTV_RF(6) CORUTV_RF(7)
+      CORUTV_RF(8) CORUTV_RF(9) CORUTV_RF(10) CORUTV_RF(11) CORUTV_RF(12) CORUTV_RF(13) CORUTV_RF(14)
+#undef CORUTV_RF
+      default:
+        return hhr_refl_rows<L, R, MODE>([](double v) { return hhr_bc16_one<15>(v); }, w, y, r, s, v0, d, nr);
+    }
+  } else if constexpr (L == 32) {
+    const bool upper = (threadIdx.x & 63) >= 32;
+    return hhr_refl_rows<L, R, MODE>(
+        [s, upper](double v) {
+          const double a = readlane_f64(v, s), b = readlane_f64(v, s + 32);
+          return upper ? b : a;
+        },
+        w, y, r, s, v0, d, nr);
+  } else {
+    return hhr_refl_rows<L, R, MODE>([s](double v) { return readlane_f64(v, s); }, w, y, r, s, v0, d, nr);
+  }
+}
+
+// a + b with a, b the two halves that v_permlane16_swap (rows of 16 lanes)
+// or v_permlane32_swap (halves of 32 lanes) hand out for the operand pair
+// (v, v): every lane gets the same sum of its row and the paired row
+template <bool k32>
+__device__ __forceinline__ double hhr_swap_add(double v) {
+  const long long b = __double_as_longlong(v);
+  const unsigned lo = (unsigned)b, hi = (unsigned)(b >> 32);
+  unsigned a0, a1, b0, b1;
+  if constexpr (k32) {
+    const auto l = __builtin_amdgcn_permlane32_swap(lo, lo, false, false);
+    const auto h = __builtin_amdgcn_permlane32_swap(hi, hi, false, false);
+    a0 = l[0]; b0 = l[1]; a1 = h[0]; b1 = h[1];
+  } else {
+    const auto l = __builtin_amdgcn_permlane16_swap(lo, lo, false, false);
+    const auto h = __builtin_amdgcn_permlane16_swap(hi, hi, false, false);
+    a0 = l[0]; b0 = l[1]; a1 = h[0]; b1 = h[1];
+  }
+  const double x = __longlong_as_double(((long long)a1 << 32) | a0);
+  const double y = __longlong_as_double(((long long)b1 << 32) | b0);
+  return x + y;  // (even row or lower half) + (odd row or upper half)
+}
+
+// sum over the row groups of a wave (lane bits >= log2 L), in the same
+// order in every lane
+template <int L>
+__device__ __forceinline__ double hhr_wave_rows(double p) {
+  if constexpr (L <= 16) p = hhr_swap_add<false>(p);
+  if constexpr (L <= 32) p = hhr_swap_add<true>(p);
+  return p;
+}
+
+// sum over own rows i >= lo of x_i y_i.  Rows at or beyond the panel's
+// height hold zeros, and rows below lo occur only among the first L rows
+// (lo < ell <= L), so only those take a mask.
+template <int L, int R>
+__device__ __forceinline__ double hhr_dot(const double (&x)[R], const double (&y)[R], int r, int lo) {
+  constexpr int G = 1024 / L, QM = (L + G - 1) / G;
+  double a[4] = {0.0, 0.0, 0.0, 0.0};
+#pragma unroll
+  for (int q = 0; q < R; ++q) {
+    const double xv = (q < QM && r + G * q < lo) ? 0.0 : x[q];
+    a[q & 3] = fma(xv, y[q], a[q & 3]);
+  }
+  return (a[0] + a[1]) + (a[2] + a[3]);
+}
+
+// y_i -= d v_i over own rows i >= s, v_i = x[q], v_s = v0
+template <int L, int R>
+__device__ __forceinline__ void hhr_axpy(const double (&x)[R], double (&y)[R], int r, int s, double v0, double d) {
+  constexpr int G = 1024 / L, QM = (L + G - 1) / G;
+#pragma unroll
+  for (int q = 0; q < R; ++q) {
+    double v = x[q];
+    if (q < QM) {
+      const int i = r + G * q;
+      v = i == s ? v0 : (i > s ? v : 0.0);
+    }
+    y[q] = fma(-d, v, y[q]);
+  }
+}
+
+// Column totals of the per-thread partial sums p: the row groups of each
+// wave, then (first wave) the 16 waves in order.  Barrier 1 publishes the
+// waves' sums (and whatever the caller wrote before it), barrier 2 the
+// totals.  part: 16 L doubles, tot: L doubles (LDS).
+template <int L>
+__device__ __forceinline__ void hhr_totals(double p, double* part, double* tot) {
+  const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+  p = hhr_wave_rows<L>(p);
+  if (lane < L) part[wave * L + lane] = p;
+  __syncthreads();
+  if (wave == 0 && lane < L) {
+    double a = 0.0;
+#pragma unroll
+    for (int w = 0; w < 16; ++w) a += part[w * L + lane];
+    tot[lane] = a;
+  }
+  __syncthreads();
+}
+
+// LDS of the register-resident kernels
+template <int L>
+struct HhrLds {
+  double part[16 * L], tot[L], prow[2 * L];
+  double tau[L], alpha[L], vhead[L];
+};
+
+// Householder reduction of the nr x ell panel held in w (zeros outside it).
+// Afterwards w holds R above the diagonal, the reflector tails below it and
+// the original x_s on the diagonal; tau, alpha (R's diagonal) and vhead (the
+// first entry of each reflector) go to LDS.  Ends with a barrier.
+template <int L, int R>
+__device__ void hhr_factor(double (&w)[R], int nr, int ell, HhrLds<L>& sh) {
+  constexpr int G = 1024 / L;
+  const int t = threadIdx.x, j = t % L, r = t / L;
+  for (int s = 0; s < ell; ++s) {
+    double x[R];
+    hhr_col<L, R>(w, x, s);
+    const double p = hhr_dot<L, R>(x, w, r, s);
+    double* prow = sh.prow + (s & 1) * L;
+    if (s % G == r) {  // this row group holds the pivot row s
+      double pv = 0.0;
+#pragma unroll
+      for (int q = 0; q < R; ++q)
+        if (q == s / G) pv = w[q];
+      prow[j] = pv;
+    }
+    hhr_totals<L>(p, sh.part, sh.tot);
+    const double ts = sh.tot[s], tj = sh.tot[j];
+    const double x0 = prow[s], wsj = prow[j];
+    const double nrm = sqrt(ts);
+    double tv = 0.0, v0 = 0.0, a = 0.0;
+    if (nrm != 0.0) {
+      a = x0 >= 0.0 ? -nrm : nrm;
+      v0 = x0 - a;
+      tv = 2.0 / (ts - x0 * x0 + v0 * v0);
+    }
+    if (t == 0) {
+      sh.tau[s] = tv;
+      sh.alpha[s] = a;
+      sh.vhead[s] = v0;
+    }
+    // column s itself keeps x (the reflector's tail): d = 0 there
+    const double d = (tv != 0.0 && j > s && j < ell) ? tv * (tj - a * wsj) : 0.0;
+    hhr_axpy<L, R>(x, w, r, s, v0, d);
+  }
+  __syncthreads();
+}
+
+// qv <- H_0 ... H_{ell-1} qv with the reflectors of hhr_factor (w and the
+// tau, vhead in sh).
+template <int L, int R>
+__device__ void hhr_apply(const double (&w)[R], double (&qv)[R], int nr, int ell, HhrLds<L>& sh) {
+  const int t = threadIdx.x, j = t % L, r = t / L;
+  for (int s = ell - 1; s >= 0; --s) {
+    const double tv = sh.tau[s];
+    if (tv == 0.0) continue;  // uniform
+    const double v0 = sh.vhead[s];
+    const double p = hhr_refl<L, R, 0>(w, qv, r, s, v0, 0.0, nr);
+    hhr_totals<L>(p, sh.part, sh.tot);
+    const double d = j < ell ? tv * sh.tot[j] : 0.0;
+    hhr_refl<L, R, 1>(w, qv, r, s, v0, d, nr);
+  }
+}
+
+// w[q] = X(r0 + i, j) for own rows i < nr and j < ell, else 0
+template <int L, int R>
+__device__ __forceinline__ void hhr_load(double (&w)[R], const double* __restrict__ X, int64_t ldx, int64_t r0,
+                                         int nr, int ell) {
+  constexpr int G = 1024 / L;
+  const int j = threadIdx.x % L, r = threadIdx.x / L;
+#pragma unroll
+  for (int q = 0; q < R; ++q) {
+    const int i = r + G * q;
+    w[q] = (i < nr && j < ell) ? X[(int64_t)j * ldx + r0 + i] : 0.0;
+  }
+}
+
+// Whether the kernels of a QR run: after a Cholesky breakdown on finite data,
+// or always (force, the direct route).
+__device__ __forceinline__ bool hhr_runs(const int* status, int force) { return force || (*status & 3) == 1; }
+
+// One workgroup: X (rows x ell, column-major) -> Q (diag R >= 0, FP64 and
+// optionally a float copy), R (nullable, ell x ell column-major).  With
+// force, a non-finite R diagonal sets status bit 2.
+template <int L, int R>
+__global__ void __launch_bounds__(1024) hhr_one_kernel(const double* __restrict__ X, int64_t ldx, int64_t rows,
+                                                       int ell, double* __restrict__ Q, int64_t ldq,
+                                                       float* __restrict__ Q32, int64_t ldq32,
+                                                       double* __restrict__ Rout, int* status, int force) {
+  if (!hhr_runs(status, force)) return;
+  constexpr int G = 1024 / L;
+  __shared__ HhrLds<L> sh;
+  const double* alpha = sh.alpha;
+  const int t = threadIdx.x, j = t % L, r = t / L;
+  double w[R];
+  hhr_load<L, R>(w, X, ldx, 0, rows, ell);
+  hhr_factor<L, R>(w, rows, ell, sh);
+  if (force && t == 0) {
+    bool bad = false;
+    for (int s = 0; s < ell; ++s) bad = bad || !isfinite(alpha[s]);
+    if (bad) atomicOr(status, 2);
+  }
+  if (Rout && j < ell) {
+#pragma unroll
+    for (int q = 0; q < R; ++q) {
+      const int i = r + G * q;
+      if (i < ell) {
+        double v = i < j ? w[q] : (i == j ? alpha[i] : 0.0);
+        if (alpha[i] < 0.0) v = -v;
+        Rout[(int64_t)j * ell + i] = v;
+      }
+    }
+  }
+  double qv[R];
+#pragma unroll
+  for (int q = 0; q < R; ++q) qv[q] = (r + G * q == j && j < ell) ? 1.0 : 0.0;
+  hhr_apply<L, R>(w, qv, rows, ell, sh);
+  if (j < ell) {
+    const bool flip = alpha[j] < 0.0;
+#pragma unroll
+    for (int q = 0; q < R; ++q) {
+      const int i = r + G * q;
+      if (i < rows) {
+        const double v = flip ? -qv[q] : qv[q];
+        Q[(int64_t)j * ldq + i] = v;
+        if (Q32) Q32[(int64_t)j * ldq32 + i] = (float)v;
+      }
+    }
+  }
+}
+
+// Tree level 1: panel b (rows split evenly over P panels) reduced; its
+// reflectors (and R's entries above them) to W, its triangle to rows
+// b ell .. of Rs (ld P ell), tau and vhead to tv.
+template <int L, int R>
+__global__ void __launch_bounds__(1024) hhr_panel_kernel(const double* __restrict__ X, int64_t ldx, int64_t rows,
+                                                         int ell, int P, double* __restrict__ W, int64_t ldw,
+                                                         double* __restrict__ Rs, double* __restrict__ tv,
+                                                         const int* status, int force) {
+  if (!hhr_runs(status, force)) return;
+  constexpr int G = 1024 / L;
+  __shared__ HhrLds<L> sh;
+  const double *tau = sh.tau, *alpha = sh.alpha, *vhead = sh.vhead;
+  const int t = threadIdx.x, j = t % L, r = t / L, b = blockIdx.x;
+  const int64_t r0 = (int64_t)b * rows / P, hb = (int64_t)(b + 1) * rows / P - r0;
+  double w[R];
+  hhr_load<L, R>(w, X, ldx, r0, hb, ell);
+  hhr_factor<L, R>(w, hb, ell, sh);
+  const int64_t ldr = (int64_t)P * ell;
+  if (j < ell) {
+#pragma unroll
+    for (int q = 0; q < R; ++q) {
+      const int i = r + G * q;
+      if (i < ell) Rs[(int64_t)j * ldr + (int64_t)b * ell + i] = i < j ? w[q] : (i == j ? alpha[i] : 0.0);
+      if (i < hb) W[(int64_t)j * ldw + r0 + i] = w[q];
+    }
+  }
+  if (t < ell) {
+    tv[(int64_t)b * 2 * ell + t] = tau[t];
+    tv[(int64_t)b * 2 * ell + ell + t] = vhead[t];
+  }
+}
+
+// Tree level 2: panel b of Q = its reflectors applied to [Qr rows b ell ..; 0].
+template <int L, int R>
+__global__ void __launch_bounds__(1024) hhr_expand_kernel(const double* __restrict__ W, int64_t ldw, int64_t rows,
+                                                          int ell, int P, const double* __restrict__ Qr,
+                                                          const double* __restrict__ tv, double* __restrict__ Q,
+                                                          int64_t ldq, float* __restrict__ Q32, int64_t ldq32,
+                                                          const int* status, int force) {
+  if (!hhr_runs(status, force)) return;
+  constexpr int G = 1024 / L;
+  __shared__ HhrLds<L> sh;
+  double *tau = sh.tau, *vhead = sh.vhead;
+  const int t = threadIdx.x, j = t % L, r = t / L, b = blockIdx.x;
+  const int64_t r0 = (int64_t)b * rows / P, hb = (int64_t)(b + 1) * rows / P - r0;
+  const int64_t ldr = (int64_t)P * ell;
+  if (t < ell) {
+    tau[t] = tv[(int64_t)b * 2 * ell + t];
+    vhead[t] = tv[(int64_t)b * 2 * ell + ell + t];
+  }
+  double w[R], qv[R];
+  hhr_load<L, R>(w, W, ldw, r0, hb, ell);
+#pragma unroll
+  for (int q = 0; q < R; ++q) {
+    const int i = r + G * q;
+    qv[q] = (i < ell && j < ell) ? Qr[(int64_t)j * ldr + (int64_t)b * ell + i] : 0.0;
+  }
+  __syncthreads();
+  hhr_apply<L, R>(w, qv, hb, ell, sh);
+  if (j < ell) {
+#pragma unroll
+    for (int q = 0; q < R; ++q) {
+      const int i = r + G * q;
+      if (i < hb) {
+        Q[(int64_t)j * ldq + r0 + i] = qv[q];
+        if (Q32) Q32[(int64_t)j * ldq32 + r0 + i] = (float)qv[q];
+      }
+    }
+  }
+}
+
+// ---------------------------------------------------------------------------
 __global__ void copy_tri_kernel(const double* __restrict__ src, int ell, int trans, int upper,
                                 double* __restrict__ dst, int64_t ldd) {
   const int e = blockIdx.x * blockDim.x + threadIdx.x;
@@ -1752,16 +2146,110 @@ static HhTree hh_tree(int64_t rows, int ell) {
 
 int hh_panels(int64_t rows, int ell) { return hh_tree(rows, ell).P; }
 
+// The register-resident kernels: column width L (16, 32, 64) and rows per
+// thread (4, 8, 16) for a panel of nr rows; 0 when they do not apply.
+static int hhr_width(int ell) { return ell <= 16 ? 16 : (ell <= 32 ? 32 : (ell <= 64 ? 64 : 0)); }
+static int hhr_rows_per_thread(int L, int64_t nr) {
+  const int64_t q = (nr + 1024 / L - 1) / (1024 / L);
+  return q <= 4 ? 4 : (q <= 8 ? 8 : (q <= 16 ? 16 : 0));
+}
+// Panels of the register-resident tree: 1 (one workgroup), P >= 2, or 0
+// when rows is too large for two levels.  About sqrt(rows / ell) panels, so
+// a panel and the stacked triangles have similar heights, within: panel
+// rows <= 16 G, stacked triangles P ell <= 16 G, panel rows >= ell.
+static int hhr_panels(int64_t rows, int ell) {
+  const int L = hhr_width(ell);
+  if (L == 0) return 0;
+  const int64_t cap = 16 * (int64_t)(1024 / L);
+  if (rows <= cap) return 1;
+  const int64_t pmin = (rows + cap - 1) / cap, pmax = std::min<int64_t>(cap / ell, rows / ell);
+  if (pmin > pmax) return 0;
+  const int64_t bal = (int64_t)std::ceil(std::sqrt((double)rows / ell));
+  return (int)std::max(pmin, std::min(bal, pmax));
+}
+
+// Direct route: one workgroup (measured: for taller sketches the two-level
+// tree is slower than CholeskyQR2, whose Gram sums spread over many CUs).
+bool hhr_direct(int64_t rows, int ell) { return ell <= 16 && hhr_panels(rows, ell) == 1; }
+
 size_t hh_work_bytes(int64_t rows, int ell) {
-  const int P = hh_panels(rows, ell);
+  const int P = std::max(hh_panels(rows, ell), hhr_panels(rows, ell));
   if (P < 2) return 0;
   const size_t pe = (size_t)P * ell;
   return (3 * pe * ell + 2 * pe) * 8;
 }
 
+// Householder QR by the register-resident kernels (one workgroup, or the
+// two-level tree); false when they do not apply.
+static bool launch_hhr(const double* X, int64_t ldx, int64_t rows, int ell, double* work, int64_t ldw, double* Q,
+                       int64_t ldq, float* Q32, int64_t ldq32, double* R, int* status, double* hw, int force,
+                       hipStream_t st) {
+  const int P = hhr_panels(rows, ell);
+  const int L = hhr_width(ell);
+  if (P == 0) return false;
+#define CORUTV_HHR_ONE(LL, RR) \
+  hhr_one_kernel<LL, RR><<<dim3(1), dim3(1024), 0, st>>>(x, ldxx, nr, ell, q, ldqq, q32, ldq32x, rr, status, force)
+  auto one = [&](const double* x, int64_t ldxx, int64_t nr, double* q, int64_t ldqq, float* q32, int64_t ldq32x,
+                 double* rr) {
+    const int RP = hhr_rows_per_thread(L, nr);
+    if (L == 16 && RP == 4) CORUTV_HHR_ONE(16, 4);
+    if (L == 16 && RP == 8) CORUTV_HHR_ONE(16, 8);
+    if (L == 16 && RP == 16) CORUTV_HHR_ONE(16, 16);
+    if (L == 32 && RP == 4) CORUTV_HHR_ONE(32, 4);
+    if (L == 32 && RP == 8) CORUTV_HHR_ONE(32, 8);
+    if (L == 32 && RP == 16) CORUTV_HHR_ONE(32, 16);
+    if (L == 64 && RP == 4) CORUTV_HHR_ONE(64, 4);
+    if (L == 64 && RP == 8) CORUTV_HHR_ONE(64, 8);
+    if (L == 64 && RP == 16) CORUTV_HHR_ONE(64, 16);
+  };
+#undef CORUTV_HHR_ONE
+  if (P == 1) {
+    one(X, ldx, rows, Q, ldq, Q32, ldq32, R);
+    return true;
+  }
+  if (!hw) return false;
+  const int64_t pe = (int64_t)P * ell;
+  double* Rs = hw;                  // stacked triangles, pe x ell
+  double* Qr = Rs + 2 * pe * ell;   // the root's Q
+  double* tv = Qr + pe * ell;       // per panel: tau[ell], vhead[ell]
+  const int RP = hhr_rows_per_thread(L, (rows + P - 1) / P);
+#define CORUTV_HHR_PANEL(LL, RR)                                                                                \
+  if (L == LL && RP == RR)                                                                                     \
+    hhr_panel_kernel<LL, RR><<<dim3(P), dim3(1024), 0, st>>>(X, ldx, rows, ell, P, work, ldw, Rs, tv, status, force)
+#define CORUTV_HHR_EXPAND(LL, RR)                                                                               \
+  if (L == LL && RP == RR)                                                                                     \
+    hhr_expand_kernel<LL, RR><<<dim3(P), dim3(1024), 0, st>>>(work, ldw, rows, ell, P, Qr, tv, Q, ldq, Q32, ldq32, \
+                                                              status, force)
+  CORUTV_HHR_PANEL(16, 4);
+  CORUTV_HHR_PANEL(16, 8);
+  CORUTV_HHR_PANEL(16, 16);
+  CORUTV_HHR_PANEL(32, 4);
+  CORUTV_HHR_PANEL(32, 8);
+  CORUTV_HHR_PANEL(32, 16);
+  CORUTV_HHR_PANEL(64, 4);
+  CORUTV_HHR_PANEL(64, 8);
+  CORUTV_HHR_PANEL(64, 16);
+  one(Rs, pe, pe, Qr, pe, nullptr, 0, R);
+  CORUTV_HHR_EXPAND(16, 4);
+  CORUTV_HHR_EXPAND(16, 8);
+  CORUTV_HHR_EXPAND(16, 16);
+  CORUTV_HHR_EXPAND(32, 4);
+  CORUTV_HHR_EXPAND(32, 8);
+  CORUTV_HHR_EXPAND(32, 16);
+  CORUTV_HHR_EXPAND(64, 4);
+  CORUTV_HHR_EXPAND(64, 8);
+  CORUTV_HHR_EXPAND(64, 16);
+#undef CORUTV_HHR_PANEL
+#undef CORUTV_HHR_EXPAND
+  return true;
+}
+
 hipError_t launch_householder_qr(const double* X, int64_t ldx, int64_t rows, int ell, double* work,
                                  int64_t ldw, double* Q, int64_t ldq, float* Q32, int64_t ldq32,
-                                 double* R, const int* status, double* hw, hipStream_t st) {
+                                 double* R, int* status, double* hw, hipStream_t st, int force) {
+  if (launch_hhr(X, ldx, rows, ell, work, ldw, Q, ldq, Q32, ldq32, R, status, hw, force, st))
+    return hipGetLastError();
+  if (force) return hipErrorInvalidValue;  // the direct route needs the kernels above
   const HhTree tr = hh_tree(rows, ell);
   const int P = tr.P;
   // l <= 64: the kernels that work on all columns at once, where their LDS

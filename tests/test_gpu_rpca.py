@@ -53,6 +53,13 @@ def test_frames_shape_reduced_matches_oracle(ctx):
     assert np.linalg.norm(Lg - L) / np.linalg.norm(L) <= 1e-5
     assert abs(info["mu0"] - oinfo["mu0"]) <= 1e-5 * oinfo["mu0"]
     assert info["iters"] == 50
+    # r_j history (eq. 12): one entry per iteration, the last one the final
+    # rank; the trajectory is reported against the oracle's, not compared
+    # (a rank decision at a near-tie can fork it)
+    assert len(info["ranks"]) == 50 and info["ranks"][-1] == info["final_rank"]
+    assert all(0 <= r <= 10 for r in info["ranks"])
+    same = sum(a == b for a, b in zip(info["ranks"], oinfo["ranks"]))
+    print("r_j equal to the oracle's in %d of 50 iterations" % same)
 
 
 @pytest.mark.parametrize("m,n,layout", [(7680, 300, "row"), (300, 7680, "col"), (301, 2999, "row")])
@@ -102,6 +109,7 @@ def test_sparse_only_output_and_explicit_lambda(ctx):
     # early stop: the L of the stopping iteration
     L4, S4, i4 = ctx.rpca(Md, 5, 5, 1, seed=3, max_iter=60, tol=1e-9)
     assert i4["iters"] < 60 and i4["zeta"] < 1e-9
+    assert len(i4["ranks"]) == i4["iters"] and i4["ranks"][-1] == i4["final_rank"]
     L4, S4 = L4.cpu().numpy().astype(np.float64), S4.cpu().numpy().astype(np.float64)
     assert np.array_equal(S4 != 0, S != 0)
     assert np.linalg.norm(L4 - L) / np.linalg.norm(L) <= 1e-5
