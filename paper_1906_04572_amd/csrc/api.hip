@@ -267,9 +267,8 @@ struct Enqueued {
 };
 
 // Thin QR of the sketch held in the stream-K partials `pp` (rows x ell):
-// CholeskyQR2 with FP64 Gram and Cholesky, Householder after a breakdown;
-// sketches of at most 16 columns take Householder directly (where its
-// register-resident kernels cover the rows).
+// CholeskyQR2 with FP64 Gram and Cholesky (sketches of at most 16 columns:
+// the one- or three-launch form), Householder after a breakdown.
 // Outputs: q64 (FP64, may be scratch) and, for the F32 path, q32.
 // one_step: the first Cholesky may decide (status 4) that a second step is
 // not needed; then Q = X R1^-1 goes straight to the outputs and the kernels
@@ -290,11 +289,8 @@ hipError_t qr_from_partials(const Plan& pl, char* ws, const Partials& pp, int64_
   hipError_t e;
   // summed: the sketch is already in x0 (passes over a host-resident A)
   if (!summed && (e = launch_sum_partials(pp, ell, pl.ellp, x0, nullptr, ld, s)) != hipSuccess) return e;
-  if (hhr_direct(rows, ell))  // few columns: Householder directly, in registers
-    return launch_householder_qr(x0, ld, rows, ell, x1, ld, q64, ld, q32, ld, rfac, st, (double*)(ws + pl.o_hh),
-                                 s, 1);
   if (ell <= kQr16Max) {
-    if ((e = launch_qr16(x0, x1, ld, rows, ell, q64, q32, rfac, st, (double*)(ws + pl.o_q16),
+    if ((e = launch_qr16(x0, ld, rows, ell, q64, q32, rfac, st, (double*)(ws + pl.o_q16),
                          one_step ? kOneStepThr : 0.0, s)) != hipSuccess)
       return e;
     return launch_householder_qr(x0, ld, rows, ell, x1, ld, q64, ld, q32, ld, rfac, st,

@@ -112,32 +112,27 @@ hipError_t launch_trprod(const double* R2, const double* R1, int ell, double* R,
                          hipStream_t st);
 
 // CholeskyQR2 of X (rows x ell, ell <= 16, column-major FP64, ld) in three
-// launches: Q (FP64, columns ell..15 zero; optional float copy), R (nullable,
-// ell x ell column-major: R2 R1, or R1 when one step suffices), status bits as
-// launch_chol (1: breakdown, the caller's Householder fallback runs; 2:
-// non-finite data; 4: one step, allowed when single_thr > 0).  X1: rows x 16
-// scratch (ld).  work: qr16_work_bytes() bytes whose last 256 bytes (the
-// block counter) must be zero before the first use; the kernels leave them
-// zero.
+// launches, or one when rows <= 1024: Q (FP64, columns ell..15 zero;
+// optional float copy), R (nullable, ell x ell column-major: R2 R1, or R1
+// when one step suffices), status bits as launch_chol (1: breakdown, the
+// caller's Householder fallback runs; 2: non-finite data; 4: one step,
+// allowed when single_thr > 0).  work: qr16_work_bytes() bytes whose last 256
+// bytes (the block counter) must be zero before the first use; the kernels
+// leave them zero.
 size_t qr16_work_bytes();
-hipError_t launch_qr16(const double* X, double* X1, int64_t ld, int64_t rows, int ell, double* Q, float* Q32,
+hipError_t launch_qr16(const double* X, int64_t ld, int64_t rows, int ell, double* Q, float* Q32,
                        double* R, int* status, double* work, double single_thr, hipStream_t st);
 
 // Householder thin QR of X (rows x ell, column-major FP64) -> Q (diag R >= 0,
 // FP64 and optionally a float copy), R (nullable); runs only when
-// (*status & 3) == 1 (a Cholesky breakdown on finite data), or always with
-// force (the direct route, which sets status bit 2 on non-finite data; only
-// where hhr_direct(rows, ell) holds).  work: rows x ell (must not overlap X
-// or Q); hw: hh_work_bytes(rows, ell) bytes for the two-level tree of a tall
-// X (nullable when that is 0).
+// (*status & 3) == 1 (a Cholesky breakdown on finite data).  work: rows x ell
+// (must not overlap X or Q); hw: hh_work_bytes(rows, ell) bytes for the
+// two-level tree of a tall X (nullable when that is 0).
 hipError_t launch_householder_qr(const double* X, int64_t ldx, int64_t rows, int ell, double* work,
                                  int64_t ldw, double* Q, int64_t ldq, float* Q32, int64_t ldq32,
-                                 double* R, int* status, double* hw, hipStream_t st, int force = 0);
+                                 double* R, const int* status, double* hw, hipStream_t st);
 int hh_panels(int64_t rows, int ell);
 size_t hh_work_bytes(int64_t rows, int ell);
-// Whether a sketch of rows x ell takes Householder QR directly (ell <= 16 and
-// the register-resident kernels cover rows).
-bool hhr_direct(int64_t rows, int ell);
 hipError_t launch_fill_int(int* p, int n, int v, hipStream_t st);
 
 // Up to kZeroRanges device ranges to clear in one launch: ptr[r] 16-byte

@@ -685,27 +685,31 @@ __global__ void __launch_bounds__(1024) chol_kernel(const double* __restrict__ G
 }
 
 // ---------------------------------------------------------------------------
-// CholeskyQR2 of a sketch with l <= 16 columns in three launches (eq. 6):
+// CholeskyQR2 of a sketch with l <= 16 columns (eq. 6), in three launches:
 //   step 0: Gram of X;                      last block: R1, R1^-1 = chol(G)
 //   step 1: X1 = X R1^-1 and the Gram of X1; last block: R2, R2^-1, R = R2 R1
 //           (when the first step already suffices, status 4: Q = X R1^-1)
-//   step 2: Q = X1 R2^-1
-// The rows are split into nblk row blocks (one workgroup each); a block
-// stages 256 rows at a time in LDS and accumulates their Gram on FP64
-// matrix cores (v_mfma_f64_16x16x4f64: lane l feeds row 4t + l/16, column
-// l%16 as both operands), the four waves' sums are added in wave order and
-// written as the block's partial.  The last block to finish (a counter in
-// device memory, agent-scope fences on both sides) adds the partials in
-// block order and factors the Gram with the same one-wave 16 x 16 kernel,
-// breakdown rule and one-step rule as chol_kernel.  No block waits for
-// another.  Status bits as for chol_kernel; after bit 1 the Householder
-// fallback takes over from X.
-constexpr int kQ16MaxBlocks = 64;
-constexpr int kQ16Chunk = 256;
+//   step 2: Q = X1 R2^-1, with X1 recomputed from X (the same operations in
+//           the same order as in step 1, so the same values)
+// or, when one workgroup holds every row (at most 1024), in one launch that
+// runs the three steps back to back.  The rows are split into nblk row
+// blocks of 1024-row chunks; each thread holds one row of a chunk in
+// registers, the chunk goes to LDS and its Gram accumulates on FP64 matrix
+// cores (v_mfma_f64_16x16x4f64: lane l feeds row 4t + l/16, column l%16 as
+// both operands, 64 rows per wave); the 16 waves' sums are added in wave
+// order and written as the block's partial.  The last block to finish (a
+// counter in device memory, agent-scope fences on both sides) adds the
+// partials in block order (four quarters of the blocks in parallel, the
+// quarters then added in order) and factors the Gram with the same one-wave
+// 16 x 16 kernel, breakdown rule and one-step rule as chol_kernel.  No block
+// waits for another.  Status bits as for chol_kernel; after bit 1 the
+// Householder fallback takes over from X.
+constexpr int kQ16Rows = 1024;      // rows of a chunk (one per thread)
+constexpr int kQ16MaxBlocks = 256;
+constexpr int kQ16Pad = 17;         // LDS row stride of a chunk (doubles)
 
 struct Q16Args {
   const double* x0;   // the sketch X (rows x l, column-major, ld)
-  double* x1;         // X1 (rows x 16, ld)
   int64_t ld, rows;
   int ell, nblk;
   double* gpart;      // nblk x 256 partial Grams (row-major 16 x 16)
@@ -718,21 +722,179 @@ struct Q16Args {
   double single_thr;
 };
 
+struct Q16Lds {
+  double tile[kQ16Rows * kQ16Pad];  // a chunk, then the waves' Gram sums
+  double ra[256], rb[256];          // R^-1 factors the launch applies
+  double gm[256], ex[256], xs[256];
+  double red[8];
+  int flag;
+};
+
+// row i of X (zeros beyond l and for rows not in the block); every load
+// unconditional, from a clamped address (ic: a row of the block)
+__device__ __forceinline__ void q16_row(const Q16Args& a, int64_t i, int64_t ic, bool in, double (&x)[16]) {
+#pragma unroll
+  for (int k = 0; k < 16; ++k) {
+    const double v = a.x0[(int64_t)(k < a.ell ? k : a.ell - 1) * a.ld + ic];
+    x[k] = (in && k < a.ell) ? v : 0.0;
+  }
+}
+
+// The chunk in LDS (row-major, stride kQ16Pad): each thread writes and reads
+// its own row; a wave's matrix-core products touch only its 64 rows, so
+// these steps need no barrier between them.
+__device__ __forceinline__ void q16_put(Q16Lds& sh, const double (&x)[16]) {
+#pragma unroll
+  for (int j = 0; j < 16; ++j) sh.tile[threadIdx.x * kQ16Pad + j] = x[j];
+}
+
+__device__ __forceinline__ void q16_get(const Q16Lds& sh, double (&y)[16]) {
+#pragma unroll
+  for (int j = 0; j < 16; ++j) y[j] = sh.tile[threadIdx.x * kQ16Pad + j];
+}
+
+// the wave's rows <- rows x M (M row-major 16 x 16 in LDS: an upper
+// triangular R^-1 with the identity in the padding, so columns >= l stay
+// zero), 16 rows at a time on FP64 matrix cores (operand A: lane l feeds row
+// l%16, column 4s + l/16; operand B: row 4s + l/16 of M, column l%16)
+__device__ __forceinline__ void q16_tile_mul(Q16Lds& sh, const double* M, int64_t nvalid) {
+  const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6, g = lane >> 4, c = lane & 15;
+  if (wave * 64 >= nvalid) return;  // the wave's rows are all padding (zeros)
+  double b[4];
+#pragma unroll
+  for (int ks = 0; ks < 4; ++ks) b[ks] = M[(4 * ks + g) * 16 + c];
+#pragma unroll
+  for (int rb = 0; rb < 4; ++rb) {
+    const int row0 = wave * 64 + rb * 16;
+    d4c acc = {0.0, 0.0, 0.0, 0.0};
+#pragma unroll
+    for (int ks = 0; ks < 4; ++ks)
+      acc = __builtin_amdgcn_mfma_f64_16x16x4f64(sh.tile[(row0 + c) * kQ16Pad + 4 * ks + g], b[ks], acc, 0, 0, 0);
+#pragma unroll
+    for (int q = 0; q < 4; ++q) sh.tile[(row0 + g + 4 * q) * kQ16Pad + c] = acc[q];
+  }
+}
+
+// the Gram of the wave's 64 rows into its accumulator (lane l feeds row
+// 4t + l/16, column l%16 as both operands); nvalid: rows of the chunk that
+// hold data (the others are zeros and add nothing)
+__device__ __forceinline__ void q16_tile_gram(const Q16Lds& sh, d4c& acc, int64_t nvalid) {
+  const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+  if (wave * 64 >= nvalid) return;
+#pragma unroll
+  for (int t = 0; t < 16; ++t) {
+    const double v = sh.tile[(wave * 64 + 4 * t + (lane >> 4)) * kQ16Pad + (lane & 15)];
+    acc = __builtin_amdgcn_mfma_f64_16x16x4f64(v, v, acc, 0, 0, 0);
+  }
+}
+
+// the 16 waves' accumulators added in wave order: entry e of the block's
+// Gram for threads e < 256 (ends with a barrier)
+__device__ __forceinline__ double q16_gram_block(Q16Lds& sh, const d4c& acc) {
+  const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
+  __syncthreads();  // every wave is done with its rows of the chunk
+#pragma unroll
+  for (int q = 0; q < 4; ++q) sh.tile[wave * 256 + ((lane >> 4) + 4 * q) * 16 + (lane & 15)] = acc[q];
+  __syncthreads();
+  double g = 0.0;
+  if (tid < 256) {
+#pragma unroll
+    for (int w = 0; w < 16; ++w) g += sh.tile[w * 256 + tid];
+  }
+  __syncthreads();
+  return g;
+}
+
+// Cholesky of the Gram in sh.gm (identity in the padding) by wave 0: R to
+// sh.gm (row-major, upper), R^-1 to sh.xs (row-major).  Returns, for wave 0,
+// the status bits: 1 breakdown, 2 non-finite data, 4 one step suffices
+// (when one_thr > 0).  The caller's barrier publishes the results.
+__device__ __forceinline__ int q16_chol(Q16Lds& sh, int ell, double one_thr) {
+  const int lane = threadIdx.x & 63;
+  const double d = lane < ell ? sh.gm[lane * 17] : 0.0;
+  double mx = isfinite(d) ? d : -1.0;
+  double bad = isfinite(d) ? 0.0 : 1.0;
+#pragma unroll
+  for (int off = 32; off > 0; off >>= 1) {
+    mx = fmax(mx, __shfl_xor(mx, off, 64));
+    bad = fmax(bad, __shfl_xor(bad, off, 64));
+  }
+  if (bad != 0.0) return 2;
+  // breakdown threshold 4 l u max_i G_ii
+  const double thr = 4.0 * ell * 2.220446049250313e-16 * mx;
+  if (!chol_diag16(sh.gm, 0, ell, thr, sh.gm, sh.ex, sh.xs, lane)) return 1;
+  if (one_thr > 0.0) {
+    // one CholeskyQR step leaves Q^T Q - I of order u kappa(X)^2, and
+    // kappa_2(R) <= ||R||_F ||R^-1||_F
+    double ssr = 0.0, ssi = 0.0;
+#pragma unroll
+    for (int q = 0; q < 4; ++q) {
+      const int e = lane + 64 * q, r = e >> 4, c = e & 15;
+      if (r < ell && c < ell) {
+        ssr += sh.gm[e] * sh.gm[e];
+        ssi += sh.xs[e] * sh.xs[e];
+      }
+    }
+    ssr = wave_sum_f64(ssr);
+    ssi = wave_sum_f64(ssi);
+    if (2.220446049250313e-16 * ell * ssr * ssi <= one_thr) return 4;
+  }
+  return 0;
+}
+
+// Q rows from the thread's row y (already the basis), FP64 and float copy
+__device__ __forceinline__ void q16_store(const Q16Args& a, int64_t i, bool in, const double (&y)[16]) {
+  if (!in) return;
+#pragma unroll
+  for (int j = 0; j < 16; ++j) {
+    a.q64[(int64_t)j * a.ld + i] = y[j];
+    if (a.q32) a.q32[(int64_t)j * a.ld + i] = (float)y[j];
+  }
+}
+
+// R = R2 R1 (column-major l x l) from row-major R2 (r2) and R1 (r1)
+__device__ __forceinline__ void q16_rfac(double* out, const double* r2, const double* r1, int ell, int from,
+                                         int step) {
+  for (int e = from; e < ell * ell; e += step) {
+    const int i = e % ell, j = e / ell;
+    double v = 0.0;
+    for (int t = i; t <= j; ++t) v = fma(r2[i * 16 + t], r1[t * 16 + j], v);
+    out[e] = i <= j ? v : 0.0;
+  }
+}
+
+// The Gram held by threads e < 256 into sh.gm with the identity in the
+// padding, then factored by wave 0.  Returns the status bits to every
+// thread (sh.flag); R and R^-1 stay in sh.gm / sh.xs.
+__device__ __forceinline__ int q16_factor(Q16Lds& sh, double g, int ell, double one_thr) {
+  const int tid = threadIdx.x;
+  if (tid < 256) {
+    const int r = tid >> 4, c = tid & 15;
+    sh.gm[tid] = (r < ell && c < ell) ? g : (r == c ? 1.0 : 0.0);
+  }
+  __syncthreads();
+  if (tid < 64) {
+    const int f = q16_chol(sh, ell, one_thr);
+    if (tid == 0) sh.flag = f;
+  }
+  __syncthreads();
+  return sh.flag;
+}
+
+// steps 0 and 1 of the three-launch form, and step 2
 template <int STEP>
-__global__ void __launch_bounds__(256) q16_kernel(Q16Args a) {
-  __shared__ double tile[kQ16Chunk * 16];
-  __shared__ double rinv[256];
-  __shared__ double wacc[4][256];
-  __shared__ double gm[256], ex[256], xs[256];
-  __shared__ double red[8];
-  __shared__ int is_last;
+__global__ void __launch_bounds__(1024) q16_kernel(Q16Args a) {
+  __shared__ Q16Lds sh;
   const int sw = *a.status;
   if (STEP >= 1 && (sw & 3)) return;  // breakdown or non-finite data: nothing to do here
   if (STEP == 2 && (sw & 4)) return;  // the first step already wrote Q
   const bool final1 = STEP == 1 && (sw & 4);
-  const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
+  const int tid = threadIdx.x;
   const int ell = a.ell;
-  if (STEP >= 1) rinv[tid] = a.tiles[(STEP == 1 ? 1 : 3) * 256 + tid];
+  if (STEP >= 1 && tid < 256) {
+    sh.ra[tid] = a.tiles[256 + tid];                // R1^-1
+    if (STEP == 2) sh.rb[tid] = a.tiles[768 + tid];  // R2^-1
+  }
   if (final1 && blockIdx.x == 0 && a.rfac && tid < ell * ell) {  // R = R1
     const int i = tid % ell, j = tid / ell;
     a.rfac[tid] = a.tiles[i * 16 + j];
@@ -740,152 +902,115 @@ __global__ void __launch_bounds__(256) q16_kernel(Q16Args a) {
   __syncthreads();
   const int64_t r0 = (int64_t)blockIdx.x * a.rows / a.nblk;
   const int64_t r1 = (int64_t)(blockIdx.x + 1) * a.rows / a.nblk;
-  const double* src = STEP == 2 ? a.x1 : a.x0;
   const bool gram = !(STEP == 2 || final1);
   d4c acc = {0.0, 0.0, 0.0, 0.0};
-  // row i of the input from a clamped address (every load unconditional); the
-  // next chunk's row is loaded before the current one is used
-  auto load_row = [&](int64_t i, double* x) {
-    const int64_t ic = i < r1 ? i : r1 - 1;
-#pragma unroll
-    for (int k = 0; k < 16; ++k) x[k] = src[(int64_t)(k < ell ? k : ell - 1) * a.ld + ic];
-  };
-  double xn[16];
-  load_row(r0 + tid, xn);
-  for (int64_t c0 = r0; c0 < r1; c0 += kQ16Chunk) {
+  for (int64_t c0 = r0; c0 < r1; c0 += kQ16Rows) {
     const int64_t i = c0 + tid;
+    const bool in = i < r1;
     double x[16];
-#pragma unroll
-    for (int k = 0; k < 16; ++k) x[k] = k < ell ? xn[k] : 0.0;
-    if (c0 + kQ16Chunk < r1) load_row(i + kQ16Chunk, xn);
-    double y[16];
-    if (i < r1) {
-      if (STEP == 0) {
-#pragma unroll
-        for (int j = 0; j < 16; ++j) y[j] = x[j];
-      } else {
-#pragma unroll
-        for (int j = 0; j < 16; ++j) {
-          double v = 0.0;
-#pragma unroll
-          for (int k = 0; k <= j; ++k) v = fma(x[k], rinv[k * 16 + j], v);
-          y[j] = j < ell ? v : 0.0;
-        }
-      }
-      if (STEP == 1 && !final1) {
-#pragma unroll
-        for (int j = 0; j < 16; ++j) a.x1[(int64_t)j * a.ld + i] = y[j];
-      } else if (STEP >= 1) {
-#pragma unroll
-        for (int j = 0; j < 16; ++j) {
-          a.q64[(int64_t)j * a.ld + i] = y[j];
-          if (a.q32) a.q32[(int64_t)j * a.ld + i] = (float)y[j];
-        }
-      }
+    q16_row(a, i, in ? i : r1 - 1, in, x);
+    q16_put(sh, x);
+    const int64_t nv = r1 - c0;
+    if (STEP >= 1) q16_tile_mul(sh, sh.ra, nv);  // X1 (or Q when one step suffices)
+    if (STEP == 2) q16_tile_mul(sh, sh.rb, nv);  // Q
+    if (gram) {
+      q16_tile_gram(sh, acc, nv);
     } else {
-#pragma unroll
-      for (int j = 0; j < 16; ++j) y[j] = 0.0;
+      q16_get(sh, x);
+      q16_store(a, i, in, x);
     }
-    if (!gram) continue;
-#pragma unroll
-    for (int j = 0; j < 16; ++j) tile[tid * 16 + j] = y[j];
-    __syncthreads();
-#pragma unroll
-    for (int t = 0; t < 16; ++t) {
-      const double v = tile[(wave * 64 + 4 * t + (lane >> 4)) * 16 + (lane & 15)];
-      acc = __builtin_amdgcn_mfma_f64_16x16x4f64(v, v, acc, 0, 0, 0);
-    }
-    __syncthreads();
   }
   if (!gram) return;
-  // block partial: the four waves' sums in wave order
-#pragma unroll
-  for (int q = 0; q < 4; ++q) wacc[wave][((lane >> 4) + 4 * q) * 16 + (lane & 15)] = acc[q];
-  __syncthreads();
-  if (wave == 0) {
-#pragma unroll
-    for (int q = 0; q < 4; ++q) {
-      const int e = lane + 64 * q;
-      a.gpart[(int64_t)blockIdx.x * 256 + e] = ((wacc[0][e] + wacc[1][e]) + wacc[2][e]) + wacc[3][e];
-    }
+  const double g = q16_gram_block(sh, acc);
+  if (tid == 0) sh.flag = 0;
+  if (tid < 256) {
+    a.gpart[(int64_t)blockIdx.x * 256 + tid] = g;
     __threadfence();  // the partial is visible device-wide before the count
-    if (lane == 0) is_last = atomicAdd(a.counter, 1) == a.nblk - 1;
   }
   __syncthreads();
-  if (!is_last) return;
+  if (tid == 0) sh.flag = atomicAdd(a.counter, 1) == a.nblk - 1;
+  __syncthreads();
+  if (!sh.flag) return;
   __threadfence();  // every other block's partial is visible from here on
-  {
-    // every partial in flight at once (clamped addresses), then added in
-    // block order; the clamped extra terms are not added
-    double parts[kQ16MaxBlocks];
+  // the partials in block order: quarter u = tid / 256 adds blocks
+  // [u nq, (u + 1) nq) of entry tid % 256, its loads in flight in groups of
+  // 16 (clamped addresses; the clamped terms are not added); then the
+  // quarters in order
+  const int e = tid & 255, u = tid >> 8;
+  const int nq = (a.nblk + 3) / 4;
+  const int b0 = u * nq, b1 = min(a.nblk, b0 + nq);
+  double gq = 0.0;
+  for (int bb = b0; bb < b1; bb += 16) {
+    double v[16];
 #pragma unroll
-    for (int b = 0; b < kQ16MaxBlocks; ++b) parts[b] = a.gpart[(int64_t)(b < a.nblk ? b : 0) * 256 + tid];
-    double g = 0.0;
+    for (int k = 0; k < 16; ++k) v[k] = a.gpart[(int64_t)min(bb + k, b1 - 1) * 256 + e];
 #pragma unroll
-    for (int b = 0; b < kQ16MaxBlocks; ++b)
-      if (b < a.nblk) g += parts[b];
-    const int r = tid >> 4, c = tid & 15;
-    // identity in the padding, as chol_kernel
-    gm[tid] = (r < ell && c < ell) ? g : (r == c ? 1.0 : 0.0);
+    for (int k = 0; k < 16; ++k)
+      if (bb + k < b1) gq += v[k];
   }
-  // breakdown threshold 4 l u max_i G_ii; a non-finite diagonal is bit 2
-  if (wave == 0) {
-    const double d = lane < ell ? gm[lane * 17] : 0.0;
-    double mx = isfinite(d) ? d : -1.0;
-    double bad = isfinite(d) ? 0.0 : 1.0;
-#pragma unroll
-    for (int off = 32; off > 0; off >>= 1) {
-      mx = fmax(mx, __shfl_xor(mx, off, 64));
-      bad = fmax(bad, __shfl_xor(bad, off, 64));
-    }
-    if (lane == 0) {
-      red[0] = mx;
-      red[1] = bad;
-    }
-  }
+  sh.tile[u * 256 + e] = gq;
   __syncthreads();
-  if (wave == 0) {
-    bool ok = false;
-    if (red[1] != 0.0) {
-      if (lane == 0) atomicOr(a.status, 2);
-    } else {
-      const double thr = 4.0 * ell * 2.220446049250313e-16 * red[0];
-      ok = chol_diag16(gm, 0, ell, thr, gm, ex, xs, lane);
-      if (!ok && lane == 0) atomicOr(a.status, 1);
-    }
-    if (ok) {
-      // R (upper, row-major) and R^-1 (xs, row-major) for the next launch
-      double* Rt = a.tiles + (STEP == 0 ? 0 : 2) * 256;
-      double* Ri = a.tiles + (STEP == 0 ? 1 : 3) * 256;
-      double ssr = 0.0, ssi = 0.0;
-#pragma unroll
-      for (int q = 0; q < 4; ++q) {
-        const int e = lane + 64 * q, r = e >> 4, c = e & 15;
-        const double vr = gm[e], vi = xs[e];
-        Rt[e] = vr;
-        Ri[e] = vi;
-        if (r < ell && c < ell) {
-          ssr += vr * vr;
-          ssi += vi * vi;
-        }
-      }
-      if (STEP == 0 && a.single_thr > 0.0) {
-        ssr = wave_sum_f64(ssr);
-        ssi = wave_sum_f64(ssi);
-        if (lane == 0 && 2.220446049250313e-16 * ell * ssr * ssi <= a.single_thr) atomicOr(a.status, 4);
-      }
-      if (STEP == 1 && a.rfac) {  // R = R2 R1, column-major l x l
-        const double* R1 = a.tiles;
-        for (int e = lane; e < ell * ell; e += 64) {
-          const int i = e % ell, j = e / ell;
-          double v = 0.0;
-          for (int t = i; t <= j; ++t) v = fma(gm[i * 16 + t], R1[t * 16 + j], v);
-          a.rfac[e] = i <= j ? v : 0.0;
-        }
-      }
-    }
-    if (lane == 0) atomicExch(a.counter, 0);  // ready for the next launch
+  const double gt = ((sh.tile[e] + sh.tile[256 + e]) + sh.tile[512 + e]) + sh.tile[768 + e];
+  const int f = q16_factor(sh, gt, ell, STEP == 0 ? a.single_thr : 0.0);
+  if (tid == 0) {
+    if (f & 3) atomicOr(a.status, f & 3);
+    if (f == 4) atomicOr(a.status, 4);
   }
+  if (!(f & 3) && tid < 256) {
+    // R (upper, row-major) and R^-1 for the next launch
+    a.tiles[(STEP == 0 ? 0 : 512) + tid] = sh.gm[tid];
+    a.tiles[(STEP == 0 ? 256 : 768) + tid] = sh.xs[tid];
+  }
+  if (STEP == 1 && !(f & 3) && a.rfac) q16_rfac(a.rfac, sh.gm, a.tiles, ell, tid, 1024);
+  if (tid == 0) atomicExch(a.counter, 0);  // ready for the next launch
+}
+
+// The three steps in one workgroup (rows <= 1024, X kept in registers).
+__global__ void __launch_bounds__(1024) q16_one_kernel(Q16Args a) {
+  __shared__ Q16Lds sh;
+  const int tid = threadIdx.x, ell = a.ell;
+  const bool in = tid < a.rows;
+  double x[16];
+  q16_row(a, tid, in ? tid : a.rows - 1, in, x);
+  q16_put(sh, x);
+  d4c acc = {0.0, 0.0, 0.0, 0.0};
+  q16_tile_gram(sh, acc, a.rows);
+  int f = q16_factor(sh, q16_gram_block(sh, acc), ell, a.single_thr);
+  if (f & 3) {
+    if (tid == 0) atomicOr(a.status, f & 3);
+    return;
+  }
+  if (tid < 256) {
+    sh.ra[tid] = sh.xs[tid];  // R1^-1
+    sh.rb[tid] = sh.gm[tid];  // R1
+  }
+  q16_put(sh, x);  // the Gram sums used the tile
+  __syncthreads();
+  q16_tile_mul(sh, sh.ra, a.rows);  // X1
+  if (f == 4) {  // one step suffices: Q = X R1^-1, R = R1
+    if (tid == 0) atomicOr(a.status, 4);
+    q16_get(sh, x);
+    q16_store(a, tid, in, x);
+    if (a.rfac && tid < ell * ell) {
+      const int i = tid % ell, j = tid / ell;
+      a.rfac[tid] = sh.rb[i * 16 + j];
+    }
+    return;
+  }
+  acc = d4c{0.0, 0.0, 0.0, 0.0};
+  q16_tile_gram(sh, acc, a.rows);
+  f = q16_factor(sh, q16_gram_block(sh, acc), ell, 0.0);
+  if (f & 3) {
+    if (tid == 0) atomicOr(a.status, f & 3);
+    return;
+  }
+  // X1 again (the Gram sums used the tile), then Q = X1 R2^-1
+  q16_put(sh, x);
+  q16_tile_mul(sh, sh.ra, a.rows);
+  q16_tile_mul(sh, sh.xs, a.rows);
+  q16_get(sh, x);
+  q16_store(a, tid, in, x);
+  if (a.rfac) q16_rfac(a.rfac, sh.gm, sh.rb, ell, tid, 1024);
 }
 
 // ---------------------------------------------------------------------------
@@ -1724,19 +1849,17 @@ __device__ __forceinline__ void hhr_load(double (&w)[R], const double* __restric
   }
 }
 
-// Whether the kernels of a QR run: after a Cholesky breakdown on finite data,
-// or always (force, the direct route).
-__device__ __forceinline__ bool hhr_runs(const int* status, int force) { return force || (*status & 3) == 1; }
+// The kernels of a QR run after a Cholesky breakdown on finite data.
+__device__ __forceinline__ bool hhr_runs(const int* status) { return (*status & 3) == 1; }
 
 // One workgroup: X (rows x ell, column-major) -> Q (diag R >= 0, FP64 and
-// optionally a float copy), R (nullable, ell x ell column-major).  With
-// force, a non-finite R diagonal sets status bit 2.
+// optionally a float copy), R (nullable, ell x ell column-major).
 template <int L, int R>
 __global__ void __launch_bounds__(1024) hhr_one_kernel(const double* __restrict__ X, int64_t ldx, int64_t rows,
                                                        int ell, double* __restrict__ Q, int64_t ldq,
                                                        float* __restrict__ Q32, int64_t ldq32,
-                                                       double* __restrict__ Rout, int* status, int force) {
-  if (!hhr_runs(status, force)) return;
+                                                       double* __restrict__ Rout, const int* status) {
+  if (!hhr_runs(status)) return;
   constexpr int G = 1024 / L;
   __shared__ HhrLds<L> sh;
   const double* alpha = sh.alpha;
@@ -1744,11 +1867,6 @@ __global__ void __launch_bounds__(1024) hhr_one_kernel(const double* __restrict_
   double w[R];
   hhr_load<L, R>(w, X, ldx, 0, rows, ell);
   hhr_factor<L, R>(w, rows, ell, sh);
-  if (force && t == 0) {
-    bool bad = false;
-    for (int s = 0; s < ell; ++s) bad = bad || !isfinite(alpha[s]);
-    if (bad) atomicOr(status, 2);
-  }
   if (Rout && j < ell) {
 #pragma unroll
     for (int q = 0; q < R; ++q) {
@@ -1785,8 +1903,8 @@ template <int L, int R>
 __global__ void __launch_bounds__(1024) hhr_panel_kernel(const double* __restrict__ X, int64_t ldx, int64_t rows,
                                                          int ell, int P, double* __restrict__ W, int64_t ldw,
                                                          double* __restrict__ Rs, double* __restrict__ tv,
-                                                         const int* status, int force) {
-  if (!hhr_runs(status, force)) return;
+                                                         const int* status) {
+  if (!hhr_runs(status)) return;
   constexpr int G = 1024 / L;
   __shared__ HhrLds<L> sh;
   const double *tau = sh.tau, *alpha = sh.alpha, *vhead = sh.vhead;
@@ -1816,8 +1934,8 @@ __global__ void __launch_bounds__(1024) hhr_expand_kernel(const double* __restri
                                                           int ell, int P, const double* __restrict__ Qr,
                                                           const double* __restrict__ tv, double* __restrict__ Q,
                                                           int64_t ldq, float* __restrict__ Q32, int64_t ldq32,
-                                                          const int* status, int force) {
-  if (!hhr_runs(status, force)) return;
+                                                          const int* status) {
+  if (!hhr_runs(status)) return;
   constexpr int G = 1024 / L;
   __shared__ HhrLds<L> sh;
   double *tau = sh.tau, *vhead = sh.vhead;
@@ -1990,18 +2108,17 @@ hipError_t launch_add_cols(double* y, const double* x, int64_t rows, int cols, i
 }
 
 int qr16_blocks(int64_t rows) {
-  const int64_t b = (rows + 1023) / 1024;
+  const int64_t b = (rows + kQ16Rows - 1) / kQ16Rows;
   return (int)std::max<int64_t>(1, std::min<int64_t>(kQ16MaxBlocks, b));
 }
 
 size_t qr16_work_bytes() { return ((size_t)kQ16MaxBlocks * 256 + 4 * 256) * 8 + 256; }
 
-hipError_t launch_qr16(const double* X, double* X1, int64_t ld, int64_t rows, int ell, double* Q, float* Q32,
-                       double* R, int* status, double* work, double single_thr, hipStream_t st) {
+hipError_t launch_qr16(const double* X, int64_t ld, int64_t rows, int ell, double* Q, float* Q32, double* R,
+                       int* status, double* work, double single_thr, hipStream_t st) {
   if (ell < 1 || ell > 16 || rows < ell) return hipErrorInvalidValue;
   Q16Args a;
   a.x0 = X;
-  a.x1 = X1;
   a.ld = ld;
   a.rows = rows;
   a.ell = ell;
@@ -2014,10 +2131,14 @@ hipError_t launch_qr16(const double* X, double* X1, int64_t ld, int64_t rows, in
   a.q32 = Q32;
   a.status = status;
   a.single_thr = single_thr;
+  if (rows <= kQ16Rows) {
+    q16_one_kernel<<<dim3(1), dim3(1024), 0, st>>>(a);
+    return hipGetLastError();
+  }
   const dim3 grid((unsigned)a.nblk);
-  q16_kernel<0><<<grid, dim3(256), 0, st>>>(a);
-  q16_kernel<1><<<grid, dim3(256), 0, st>>>(a);
-  q16_kernel<2><<<grid, dim3(256), 0, st>>>(a);
+  q16_kernel<0><<<grid, dim3(1024), 0, st>>>(a);
+  q16_kernel<1><<<grid, dim3(1024), 0, st>>>(a);
+  q16_kernel<2><<<grid, dim3(1024), 0, st>>>(a);
   return hipGetLastError();
 }
 
@@ -2168,9 +2289,6 @@ static int hhr_panels(int64_t rows, int ell) {
   return (int)std::max(pmin, std::min(bal, pmax));
 }
 
-// Direct route: one workgroup (measured: for taller sketches the two-level
-// tree is slower than CholeskyQR2, whose Gram sums spread over many CUs).
-bool hhr_direct(int64_t rows, int ell) { return ell <= 16 && hhr_panels(rows, ell) == 1; }
 
 size_t hh_work_bytes(int64_t rows, int ell) {
   const int P = std::max(hh_panels(rows, ell), hhr_panels(rows, ell));
@@ -2182,13 +2300,13 @@ size_t hh_work_bytes(int64_t rows, int ell) {
 // Householder QR by the register-resident kernels (one workgroup, or the
 // two-level tree); false when they do not apply.
 static bool launch_hhr(const double* X, int64_t ldx, int64_t rows, int ell, double* work, int64_t ldw, double* Q,
-                       int64_t ldq, float* Q32, int64_t ldq32, double* R, int* status, double* hw, int force,
+                       int64_t ldq, float* Q32, int64_t ldq32, double* R, const int* status, double* hw,
                        hipStream_t st) {
   const int P = hhr_panels(rows, ell);
   const int L = hhr_width(ell);
   if (P == 0) return false;
 #define CORUTV_HHR_ONE(LL, RR) \
-  hhr_one_kernel<LL, RR><<<dim3(1), dim3(1024), 0, st>>>(x, ldxx, nr, ell, q, ldqq, q32, ldq32x, rr, status, force)
+  hhr_one_kernel<LL, RR><<<dim3(1), dim3(1024), 0, st>>>(x, ldxx, nr, ell, q, ldqq, q32, ldq32x, rr, status)
   auto one = [&](const double* x, int64_t ldxx, int64_t nr, double* q, int64_t ldqq, float* q32, int64_t ldq32x,
                  double* rr) {
     const int RP = hhr_rows_per_thread(L, nr);
@@ -2215,11 +2333,11 @@ static bool launch_hhr(const double* X, int64_t ldx, int64_t rows, int ell, doub
   const int RP = hhr_rows_per_thread(L, (rows + P - 1) / P);
 #define CORUTV_HHR_PANEL(LL, RR)                                                                                \
   if (L == LL && RP == RR)                                                                                     \
-    hhr_panel_kernel<LL, RR><<<dim3(P), dim3(1024), 0, st>>>(X, ldx, rows, ell, P, work, ldw, Rs, tv, status, force)
+    hhr_panel_kernel<LL, RR><<<dim3(P), dim3(1024), 0, st>>>(X, ldx, rows, ell, P, work, ldw, Rs, tv, status)
 #define CORUTV_HHR_EXPAND(LL, RR)                                                                               \
   if (L == LL && RP == RR)                                                                                     \
     hhr_expand_kernel<LL, RR><<<dim3(P), dim3(1024), 0, st>>>(work, ldw, rows, ell, P, Qr, tv, Q, ldq, Q32, ldq32, \
-                                                              status, force)
+                                                              status)
   CORUTV_HHR_PANEL(16, 4);
   CORUTV_HHR_PANEL(16, 8);
   CORUTV_HHR_PANEL(16, 16);
@@ -2246,10 +2364,8 @@ static bool launch_hhr(const double* X, int64_t ldx, int64_t rows, int ell, doub
 
 hipError_t launch_householder_qr(const double* X, int64_t ldx, int64_t rows, int ell, double* work,
                                  int64_t ldw, double* Q, int64_t ldq, float* Q32, int64_t ldq32,
-                                 double* R, int* status, double* hw, hipStream_t st, int force) {
-  if (launch_hhr(X, ldx, rows, ell, work, ldw, Q, ldq, Q32, ldq32, R, status, hw, force, st))
-    return hipGetLastError();
-  if (force) return hipErrorInvalidValue;  // the direct route needs the kernels above
+                                 double* R, const int* status, double* hw, hipStream_t st) {
+  if (launch_hhr(X, ldx, rows, ell, work, ldw, Q, ldq, Q32, ldq32, R, status, hw, st)) return hipGetLastError();
   const HhTree tr = hh_tree(rows, ell);
   const int P = tr.P;
   // l <= 64: the kernels that work on all columns at once, where their LDS
