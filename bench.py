@@ -424,7 +424,7 @@ def rpca_leg(cu, torch, runs=3):
            "final_rank": info["final_rank"], "zeta": info["zeta"],
            "ms_per_run": round(float(np.median(wall)), 3), "gpu_ms_per_run": round(float(np.median(gpu)), 3),
            "ms_per_iteration": round(float(np.median(gpu)) / iters, 4),
-           "step_kernel": {"kernel": "rpca_step_kernel", "bound": "hbm",
+           "step_kernel": {"kernel": "rpca_step2_kernel", "bound": "hbm",
                            "avg_ms": round(step_ms / iters, 4), "achieved": round(achieved, 1),
                            "peak": HBM_PEAK_GBS, "unit": "GB/s", "frac": round(achieved / HBM_PEAK_GBS, 4),
                            "algorithmic_bytes_per_run": step_bytes,

@@ -136,6 +136,100 @@ __global__ void __launch_bounds__(256) rpca_step_kernel(RpcaArgs a) {
   if (threadIdx.x == 0) a.part[blockIdx.x] = red[0];
 }
 
+// The same step with two neighbouring elements of a storage line per thread
+// (8-byte loads and stores of M, S and L, 16-byte ones of Y, B and the
+// along-line factor), for lines of even length whose leading dimensions are
+// even and whose bases are aligned, with S and L in M's layout.  The
+// arithmetic of each element is the scalar kernel's, in the same order.
+__global__ void __launch_bounds__(256) rpca_step2_kernel(RpcaArgs a) {
+  __shared__ int rs;
+  __shared__ double red[256];
+  if (threadIdx.x == 0) rs = 0;
+  __syncthreads();
+  if ((int)threadIdx.x < a.ell && a.T[(int64_t)threadIdx.x * a.ldt + threadIdx.x] > a.inv_mu)
+    atomicAdd(&rs, 1);
+  __syncthreads();
+  const int r = rs;
+  if (blockIdx.x == 0 && threadIdx.x == 0) {
+    if (a.sticky) {
+      int acc = *a.sticky;
+      for (int i = 0; i < a.nst; ++i) acc |= a.st[i];
+      *a.sticky = acc;
+    }
+    if (a.rank_out) *a.rank_out = r;
+  }
+  const bool colmaj = a.lay_m == CORUTV_COL_MAJOR;
+  const int64_t len = colmaj ? a.m : a.n;  // even
+  const int64_t nlines = colmaj ? a.n : a.m;
+  const double* Fa = colmaj ? a.P : a.Q;
+  const int64_t ldfa = colmaj ? a.ldp : a.ldq;
+  const double* Fb = colmaj ? a.Q : a.P;
+  const int64_t ldfb = colmaj ? a.ldq : a.ldp;
+  const int64_t ta = (len + 511) / 512, tb = (nlines + kLines - 1) / kLines;
+  double z2 = 0.0;
+  for (int64_t t = blockIdx.x; t < ta * tb; t += gridDim.x) {
+    const int64_t p0 = (t % ta) * 512 + 2 * threadIdx.x;
+    const int64_t b0 = (t / ta) * kLines;
+    const bool pin = p0 < len;  // both elements (len is even)
+    const int64_t pc = pin ? p0 : len - 2;
+    int64_t bl[kLines];
+    double l0[kLines], l1[kLines];
+    float2 mv[kLines];
+    double2 yv[kLines];
+#pragma unroll
+    for (int u = 0; u < kLines; ++u) {
+      bl[u] = b0 + u < nlines ? b0 + u : nlines - 1;
+      l0[u] = 0.0;
+      l1[u] = 0.0;
+    }
+#pragma unroll
+    for (int u = 0; u < kLines; ++u) {
+      mv[u] = *(const float2*)(a.M + bl[u] * a.ldm + pc);
+      yv[u] = *(const double2*)(a.Y + bl[u] * a.ldy + pc);
+    }
+    for (int c = 0; c < r; ++c) {
+      const double2 fa = *(const double2*)(Fa + (int64_t)c * ldfa + pc);
+#pragma unroll
+      for (int u = 0; u < kLines; ++u) {
+        const double fb = Fb[(int64_t)c * ldfb + bl[u]];
+        l0[u] = fma(fa.x, fb, l0[u]);
+        l1[u] = fma(fa.y, fb, l1[u]);
+      }
+    }
+#pragma unroll
+    for (int u = 0; u < kLines; ++u) {
+      const double m2[2] = {(double)mv[u].x, (double)mv[u].y};
+      const double y2[2] = {yv[u].x, yv[u].y};
+      const double lv[2] = {l0[u], l1[u]};
+      double sv[2], yn[2], bn[2];
+#pragma unroll
+      for (int e = 0; e < 2; ++e) {
+        const double x = m2[e] - lv[e] + y2[e] / a.mu;
+        const double ax = fabs(x) - a.thresh;
+        sv[e] = ax > 0.0 ? copysign(ax, x) : 0.0;
+        const double z = m2[e] - lv[e] - sv[e];
+        yn[e] = y2[e] + a.mu * z;
+        bn[e] = m2[e] - sv[e] + yn[e] / a.mu_next;
+        if (pin && b0 + u < nlines) z2 += z * z;
+      }
+      if (pin && b0 + u < nlines) {
+        const int64_t off = bl[u] * a.lds + p0;  // S, L share M's layout here
+        *(float2*)(a.S + off) = make_float2((float)sv[0], (float)sv[1]);
+        *(double2*)(a.Y + bl[u] * a.ldy + p0) = make_double2(yn[0], yn[1]);
+        if (a.B) *(double2*)(a.B + bl[u] * a.ldb + p0) = make_double2(bn[0], bn[1]);
+        if (a.L) *(float2*)(a.L + bl[u] * a.ldl + p0) = make_float2((float)lv[0], (float)lv[1]);
+      }
+    }
+  }
+  red[threadIdx.x] = z2;
+  __syncthreads();
+  for (int off = 128; off > 0; off >>= 1) {
+    if ((int)threadIdx.x < off) red[threadIdx.x] += red[threadIdx.x + off];
+    __syncthreads();
+  }
+  if (threadIdx.x == 0) a.part[blockIdx.x] = red[0];
+}
+
 // B = M (FP32 -> FP64, exact), same layout
 __global__ void widen_kernel(const float* X, int lay, int64_t ld, int64_t m, int64_t n, double* B,
                              int64_t ldb) {
@@ -213,7 +307,18 @@ hipError_t launch_rpca_elementwise(const float* M, int lay_m, int64_t ldm, float
   a.nst = nstatus;
   a.sticky = sticky;
   a.rank_out = rank_out;
-  rpca_step_kernel<<<dim3(kRpcaBlocks), dim3(256), 0, st>>>(a);
+  // the paired form: even lines, even leading dimensions, aligned bases, S
+  // and L stored like M
+  const int64_t len = lay_m == CORUTV_COL_MAJOR ? m : n;
+  auto al = [](const void* p, int b) { return p == nullptr || ((uintptr_t)p % b) == 0; };
+  const bool pair = len % 2 == 0 && ldm % 2 == 0 && lds % 2 == 0 && ldy % 2 == 0 && ldb % 2 == 0 &&
+                    (L == nullptr || (ldl % 2 == 0 && lay_l == lay_m)) && lay_s == lay_m && al(M, 8) &&
+                    al(S, 8) && al(L, 8) && al(Y, 16) && al(B, 16) && ldp % 2 == 0 && ldq % 2 == 0 &&
+                    al(lay_m == CORUTV_COL_MAJOR ? (const void*)P : (const void*)Q, 16);
+  if (pair)
+    rpca_step2_kernel<<<dim3(kRpcaBlocks), dim3(256), 0, st>>>(a);
+  else
+    rpca_step_kernel<<<dim3(kRpcaBlocks), dim3(256), 0, st>>>(a);
   return hipGetLastError();
 }
 

@@ -473,7 +473,7 @@ __device__ __forceinline__ double readlane_f64(double v, int l) {
 // pivot d_s and the multipliers D[r][s]/d_s of the rows below: column s,
 // broadcast from lane s with v_readlane (a uniform lane index); the pivot
 // row is each lane's own x[s], so rows r > s update as
-// x[r] -= (D[r][s]/d_s) x[s].  The row scaling by 1/sqrt(d_r) that turns
+// x[r] -= D[r][s] (x[s]/d_s).  The row scaling by 1/sqrt(d_r) that turns
 // [L D' | L^-1] into [U | U^{-T}] is done once at the end.  Returns false on
 // breakdown (the same on every lane: the pivot is a broadcast).
 __device__ __forceinline__ bool chol_diag16(const double* src, int base, int ell, double thr,
@@ -492,12 +492,10 @@ __device__ __forceinline__ bool chol_diag16(const double* src, int base, int ell
     double rd = __builtin_amdgcn_rcp(d);
     rd = fma(rd, fma(-d, rd, 1.0), rd);
     rd = fma(rd, fma(-d, rd, 1.0), rd);
-    const double piv_row = x[s];
+    // x[r] -= (D[r][s] / d_s) x[s], with x[s] / d_s formed once per lane
+    const double piv_row = x[s] * rd;
 #pragma unroll
-    for (int r = s + 1; r < 16; ++r) {
-      const double m = readlane_f64(x[r], s) * rd;  // D[r][s] / d_s
-      x[r] -= m * piv_row;
-    }
+    for (int r = s + 1; r < 16; ++r) x[r] = fma(-readlane_f64(x[r], s), piv_row, x[r]);
   }
   if (lane < 32) {
 #pragma unroll
