@@ -31,27 +31,49 @@ __global__ void __launch_bounds__(256) sum_partials_kernel(Partials p, const T* 
                                                            float* __restrict__ out32, int64_t ld, int tpe,
                                                            int reps) {
   __shared__ int wg[kSegMax], wslot[kSegMax], seg[kSegMax];
-  __shared__ int nwg;
+  __shared__ int wcount[4];
   __shared__ double acc[256];
   const int t = blockIdx.x;
-  if (threadIdx.x == 0) {
+  // the workgroups whose unit ranges meet this tile's units, in ascending
+  // order: 256 candidates at a time, one per thread, placed by a prefix
+  // count (ballot within a wave, then the waves in order)
+  {
     const int64_t U = (int64_t)p.tiles * p.nkx;
     const int64_t lo = (int64_t)t * p.nkx, hi = lo + p.nkx;
-    int n = 0;
-    for (int j = (int)(lo * p.gx / U); j < p.gx; ++j) {
-      const int64_t u0 = (int64_t)j * U / p.gx;
-      if (u0 >= hi) break;
-      const int64_t u1 = (int64_t)(j + 1) * U / p.gx;
-      if ((u0 > lo ? u0 : lo) >= (u1 < hi ? u1 : hi)) continue;
-      if (n < kSegMax) {
-        wg[n] = j;
-        wslot[n] = t - (int)(u0 / p.nkx);
+    const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+    int base = 0;
+    for (int64_t jb = lo * p.gx / U; jb < p.gx; jb += 256) {
+      const int64_t j = jb + threadIdx.x;
+      bool valid = false, past = false;
+      int slot = 0;
+      if (j < p.gx) {
+        const int64_t u0 = j * U / p.gx;
+        if (u0 >= hi) {
+          past = true;
+        } else {
+          const int64_t u1 = (j + 1) * U / p.gx;
+          valid = (u0 > lo ? u0 : lo) < (u1 < hi ? u1 : hi);
+          slot = t - (int)(u0 / p.nkx);
+        }
       }
-      ++n;
+      const unsigned long long m = __ballot(valid);
+      const int pos = __popcll(m & ((1ull << lane) - 1ull));
+      if (lane == 0) wcount[wave] = __popcll(m);
+      __syncthreads();
+      int off = base;
+      for (int w = 0; w < wave; ++w) off += wcount[w];
+      if (valid && off + pos < kSegMax) {
+        wg[off + pos] = (int)j;
+        wslot[off + pos] = slot;
+      }
+      base += wcount[0] + wcount[1] + wcount[2] + wcount[3];
+      const int any_past = __syncthreads_or(past);  // also orders the wcount reuse
+      if (any_past) break;  // every later candidate starts past this tile
     }
-    nwg = n < kSegMax ? n : kSegMax;
+    if (threadIdx.x == 0) wcount[0] = base < kSegMax ? base : kSegMax;
   }
   __syncthreads();
+  const int nwg = wcount[0];
   const int nw = nwg, ns = p.nchunk * nw;
   for (int k = threadIdx.x; k < ns; k += blockDim.x) {
     const int x = k / nw, q = k - x * nw;
@@ -272,6 +294,54 @@ __global__ void __launch_bounds__(256) gather_cols_kernel(const double* __restri
   } else {
     if (o1.ptr && pad1) store_out(o1, r, c, 0.0);
     if (o2.ptr && pad2) store_out(o2, r, c, 0.0);
+  }
+}
+
+// Y = X B for l <= 16: one thread per row, B (zero outside l x l) in LDS
+// where every thread reads the same entry at a time; y_c accumulates its
+// terms in increasing k (with b_upper, k <= c only).  Same outputs, padding
+// and status gate as rowmat_mfma_kernel.
+__global__ void __launch_bounds__(256) rowmat16_kernel(const double* __restrict__ X, int64_t ldx, int64_t rows,
+                                                       int ell, const double* __restrict__ B, int64_t ldb,
+                                                       MatOut o1, int pad1, MatOut o2, int pad2, int b_upper,
+                                                       const int* skip, int run_val, MatOut oa, int pada,
+                                                       int alt_val) {
+  if (skip) {
+    const int sv = *skip;
+    if (sv == alt_val) {
+      o1 = oa;
+      pad1 = pada;
+      o2 = MatOut();
+      pad2 = 0;
+    } else if (sv != run_val) {
+      return;
+    }
+  }
+  __shared__ double sb[256];  // sb[k * 16 + c] = B[k][c]
+  const int tid = threadIdx.x;
+  {
+    const int k = tid >> 4, c = tid & 15;
+    sb[tid] = (k < ell && c < ell) ? B[(int64_t)c * ldb + k] : 0.0;
+  }
+  __syncthreads();
+  const int64_t r = (int64_t)blockIdx.x * 256 + tid;
+  if (r >= rows) return;
+  double x[16];
+#pragma unroll
+  for (int k = 0; k < 16; ++k) x[k] = k < ell ? X[(int64_t)k * ldx + r] : 0.0;
+#pragma unroll
+  for (int c = 0; c < 16; ++c) {
+    if (c < ell) {
+      double v = 0.0;
+#pragma unroll
+      for (int k = 0; k < 16; ++k)
+        if (k < ell && (!b_upper || k <= c)) v = fma(x[k], sb[k * 16 + c], v);
+      if (o1.ptr) store_out(o1, r, c, v);
+      if (o2.ptr) store_out(o2, r, c, v);
+    } else {
+      if (o1.ptr && pad1) store_out(o1, r, c, 0.0);
+      if (o2.ptr && pad2) store_out(o2, r, c, 0.0);
+    }
   }
 }
 
@@ -2157,9 +2227,12 @@ hipError_t launch_sum_partials(const Partials& p, int ell, int ncols, double* ou
   int tpe = 1;
   while (tpe < 16 && slots / (2 * tpe) >= 8) tpe *= 2;
   // a block covers reps x 256 / tpe entries (16 columns when one thread sums
-  // each entry: the slot list is built once per block)
+  // each entry and the output has tiles enough to fill the device: the slot
+  // list is built once per block; a short output takes one block per 256
+  // entries instead, so its slot sums spread over more CUs)
   const int epb = 256 / tpe;
-  const int reps = tpe == 1 ? 16 * p.tw / 256 : 1;
+  const int64_t blocks1 = (int64_t)p.tiles * (((int64_t)ncols * p.tw + epb - 1) / epb);
+  const int reps = (tpe == 1 && blocks1 >= 1024) ? 16 * p.tw / 256 : 1;
   dim3 grid((unsigned)p.tiles, (unsigned)(((int64_t)ncols * p.tw + epb * reps - 1) / (epb * reps)));
   if (p.elem == 8)
     sum_partials_kernel<double><<<grid, dim3(256), 0, st>>>(p, (const double*)p.ptr, ell, ncols, out64,
@@ -2204,6 +2277,9 @@ hipError_t launch_rowmat(const double* X, int64_t ldx, int64_t rows, int ell, co
     const dim3 grid((unsigned)((rows + 255) / 256), (unsigned)ellp);
     gather_cols_kernel<<<grid, dim3(256), 0, st>>>(X, ldx, rows, ell, perm, o1, pad1, o2, pad2, skip,
                                                    run_val);
+  } else if (ell <= 16) {
+    rowmat16_kernel<<<dim3((unsigned)((rows + 255) / 256)), dim3(256), 0, st>>>(
+        X, ldx, rows, ell, B, ldb, o1, pad1, o2, pad2, b_upper ? 1 : 0, skip, run_val, oa, pada, alt_val);
   } else {
     const dim3 grid((unsigned)((rows + 31) / 32), (unsigned)((ellp + 127) / 128));
     rowmat_mfma_kernel<<<grid, dim3(256), 0, st>>>(X, ldx, rows, ell, B, ldb, o1, pad1, o2, pad2,
