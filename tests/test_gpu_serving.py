@@ -61,6 +61,36 @@ def test_mix_is_bitwise_equal_to_alone():
     ctx.close()
 
 
+def test_served_results_match_the_oracle():
+    """Every request of a mixed stream served concurrently on three slots
+    against the float64 oracle on the same data (Sec. 3.1, Algorithm 1): F64
+    |e - e_oracle| <= 1e-10 and ||A_served - A_oracle||_F <= 1e-10 ||A||_F
+    (A_x = U T V^T), F32 |e - e_oracle| <= 1e-5."""
+    import paper_1906_04572_amd as cu
+    from oracle.corutv import corutv, rel_err
+
+    _say("serving vs oracle")
+    streams = [torch.cuda.current_stream()] + [torch.cuda.Stream() for _ in range(3)]
+    ws = 3 * max(cu.workspace_bytes(m, n, k, p, q, pr) for m, n, k, p, q, pr in REQS)
+    ctx = cu.Context(workspace_bytes=ws, streams=streams)
+    As = _inputs()
+    tickets = [ctx.submit(A, k, p, q, seed=47, prec=prec, want_err=True)
+               for (m, n, k, p, q, prec), A in zip(REQS, As)]
+    results = [ctx.wait(t) for t in tickets]
+    ctx.close()
+    for (m, n, k, p, q, prec), A, res in zip(REQS, As, results):
+        A64 = A.cpu().double().numpy()
+        ref = corutv(A64, k, p, q, seed=47)
+        e_ref = rel_err(A64, ref["U"], ref["T"], ref["V"])
+        U, T, V = (x.cpu().double().numpy() for x in res[:3])
+        if prec == "f64":
+            assert abs(res[4]["rel_err"] - e_ref) <= 1e-10, (m, n, res[4]["rel_err"], e_ref)
+            d = np.linalg.norm(U @ T @ V.T - ref["U"] @ ref["T"] @ ref["V"].T) / np.linalg.norm(A64)
+            assert d <= 1e-10, (m, n, d)
+        else:
+            assert abs(res[4]["rel_err"] - e_ref) <= 1e-5, (m, n, res[4]["rel_err"], e_ref)
+
+
 def test_admission_queueing_nomem_cancel():
     import paper_1906_04572_amd as cu
 
