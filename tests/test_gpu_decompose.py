@@ -126,6 +126,7 @@ def test_f32_cases(ctx, m, n, k, p, q, layout):
     (3000, 20000, 10, 5, 2, "auto", "col", "bf16x3"),
     (100003, 200, 12, 4, 1, "auto", "col", "f64"),
     (100003, 200, 12, 4, 1, "auto", "row", "f32"),  # one CholeskyQR step in FP32 storage
+    (300001, 40, 5, 5, 1, "auto", "col", "f64"),    # more than one 1024-row chunk per block
 ])
 def test_small_sketch_qr_against_oracle(ctx, m, n, k, p, q, tri, layout, prec):
     """Sketches with l <= 16 columns take the CholeskyQR2 for at most 16

@@ -94,13 +94,15 @@ def test_tsqr_matches_householder(ctx, rows, ell):
 
 
 @pytest.mark.parametrize("rows,ell,rank", [(3000, 30, 12), (2000, 64, 1), (500, 17, 16), (76800, 10, 5),
-                                           (20037, 110, 60)])
+                                           (20037, 110, 60), (200, 48, 10), (250, 40, 5), (700, 16, 3)])
 def test_tsqr_rank_deficient_falls_back(ctx, rows, ell, rank):
-    """Cholesky breaks down; the Householder tree (panels in LDS with the rows
-    split evenly: 3000x30, 500x17, 76800x10; device-memory panels of
-    max(256, 4 ell, sqrt(rows ell)) rows, the last one ragged: 2000x64,
-    20037x110) gives an orthonormal Q with X = QR.  The first `rank` columns of X are independent,
-    so Q[:, :rank] and R[:rank] are unique and equal the oracle's."""
+    """Cholesky breaks down; Householder QR gives an orthonormal Q with X = QR:
+    the register-resident kernels (one workgroup: 500x17, 200x48, 250x40,
+    700x16; the two-level tree with the rows split evenly: 3000x30,
+    76800x10), the device-memory tree (panels of max(256, 4 ell,
+    sqrt(rows ell)) rows, the last one ragged: 2000x64, 20037x110).  The
+    first `rank` columns of X are independent, so Q[:, :rank] and R[:rank]
+    are unique and equal the oracle's."""
     _say("tsqr-deficient", rows, ell, rank)
     rng = np.random.default_rng(rows)
     X = rng.standard_normal((rows, rank)) @ rng.standard_normal((rank, ell))
