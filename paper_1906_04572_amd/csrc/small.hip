@@ -1675,6 +1675,23 @@ __device__ __forceinline__ void hhr_bc16(const double (&w)[R], double (&x)[R]) {
   for (int q = 0; q < R; ++q) x[q] = hhr_bc16_one<S>(w[q]);
 }
 
+// the value of lane 16 * odd + S of the thread's 32-lane row group
+template <int S>
+__device__ __forceinline__ double hhr_bc32_one(double v, bool odd) {
+  const long long b = __builtin_amdgcn_update_dpp(0LL, __double_as_longlong(v), 0x150 + S, 0xF, 0xF, false);
+  // (b, b) swapped: [0] holds the even row of each pair in both rows, [1] the odd one
+  const auto lo = __builtin_amdgcn_permlane16_swap((unsigned)b, (unsigned)b, false, false);
+  const auto hi = __builtin_amdgcn_permlane16_swap((unsigned)(b >> 32), (unsigned)(b >> 32), false, false);
+  const unsigned l = odd ? lo[1] : lo[0], h = odd ? hi[1] : hi[0];
+  return __longlong_as_double(((long long)h << 32) | l);
+}
+
+template <int S, int R>
+__device__ __forceinline__ void hhr_bc32(const double (&w)[R], double (&x)[R], bool odd) {
+#pragma unroll
+  for (int q = 0; q < R; ++q) x[q] = hhr_bc32_one<S>(w[q], odd);
+}
+
 // x[q] = the value of column s (uniform) in w[q] of the thread's row group
 template <int L, int R>
 __device__ __forceinline__ void hhr_col(const double (&w)[R], double (&x)[R], int s) {
@@ -1698,11 +1715,26 @@ __device__ __forceinline__ void hhr_col(const double (&w)[R], double (&x)[R], in
       default: hhr_bc16<15, R>(w, x); break;
     }
   } else if constexpr (L == 32) {
-    const bool upper = (threadIdx.x & 63) >= 32;
-#pragma unroll
-    for (int q = 0; q < R; ++q) {
-      const double a = readlane_f64(w[q], s), b = readlane_f64(w[q], s + 32);
-      x[q] = upper ? b : a;
+    // a row group is two DPP rows: broadcast lane s % 16 inside each row,
+    // then v_permlane16_swap hands the row holding column s to its partner
+    const bool odd = s >= 16;
+    switch (s & 15) {
+      case 0: hhr_bc32<0, R>(w, x, odd); break;
+      case 1: hhr_bc32<1, R>(w, x, odd); break;
+      case 2: hhr_bc32<2, R>(w, x, odd); break;
+      case 3: hhr_bc32<3, R>(w, x, odd); break;
+      case 4: hhr_bc32<4, R>(w, x, odd); break;
+      case 5: hhr_bc32<5, R>(w, x, odd); break;
+      case 6: hhr_bc32<6, R>(w, x, odd); break;
+      case 7: hhr_bc32<7, R>(w, x, odd); break;
+      case 8: hhr_bc32<8, R>(w, x, odd); break;
+      case 9: hhr_bc32<9, R>(w, x, odd); break;
+      case 10: hhr_bc32<10, R>(w, x, odd); break;
+      case 11: hhr_bc32<11, R>(w, x, odd); break;
+      case 12: hhr_bc32<12, R>(w, x, odd); break;
+      case 13: hhr_bc32<13, R>(w, x, odd); break;
+      case 14: hhr_bc32<14, R>(w, x, odd); break;
+      default: hhr_bc32<15, R>(w, x, odd); break;
     }
   } else {
 #pragma unroll
@@ -1747,13 +1779,19 @@ __device__ __forceinline__ double hhr_refl(const double (&w)[R], double (&y)[R],
         return hhr_refl_rows<L, R, MODE>([](double v) { return hhr_bc16_one<15>(v); }, w, y, r, s, v0, d, nr);
     }
   } else if constexpr (L == 32) {
-    const bool upper = (threadIdx.x & 63) >= 32;
-    return hhr_refl_rows<L, R, MODE>(
-        [s, upper](double v) {
-          const double a = readlane_f64(v, s), b = readlane_f64(v, s + 32);
-          return upper ? b : a;
-        },
-        w, y, r, s, v0, d, nr);
+    const bool odd = s >= 16;
+    switch (s & 15) {
+#define CORUTV_RF32(S)                                                                         \
+  case S:                                                                                      \
+    return hhr_refl_rows<L, R, MODE>([odd](double v) { return hhr_bc32_one<S>(v, odd); }, w, y, r, s, v0, d, nr);
+      CORUTV_RF32(0) CORUTV_RF32(1) CORUTV_RF32(2) CORUTV_RF32(3) CORUTV_RF32(4) CORUTV_RF32(5) CORUTV_RF32(6)
+      CORUTV_RF32(7) CORUTV_RF32(8) CORUTV_RF32(9) CORUTV_RF32(10) CORUTV_RF32(11) CORUTV_RF32(12)
+      CORUTV_RF32(13) CORUTV_RF32(14)
+#undef CORUTV_RF32
+      default:
+        return hhr_refl_rows<L, R, MODE>([odd](double v) { return hhr_bc32_one<15>(v, odd); }, w, y, r, s, v0, d,
+                                         nr);
+    }
   } else {
     return hhr_refl_rows<L, R, MODE>([s](double v) { return readlane_f64(v, s); }, w, y, r, s, v0, d, nr);
   }
@@ -1897,10 +1935,30 @@ __device__ void hhr_apply(const double (&w)[R], double (&qv)[R], int nr, int ell
     const double tv = sh.tau[s];
     if (tv == 0.0) continue;  // uniform
     const double v0 = sh.vhead[s];
-    const double p = hhr_refl<L, R, 0>(w, qv, r, s, v0, 0.0, nr);
-    hhr_totals<L>(p, sh.part, sh.tot);
-    const double d = j < ell ? tv * sh.tot[j] : 0.0;
-    hhr_refl<L, R, 1>(w, qv, r, s, v0, d, nr);
+    if constexpr (R <= 8) {
+      // the column broadcast once per step into registers (they fit)
+      double x[R];
+      hhr_col<L, R>(w, x, s);
+      constexpr int G = 1024 / L, QM = (L + G - 1) / G;
+      double a[4] = {0.0, 0.0, 0.0, 0.0};
+#pragma unroll
+      for (int q = 0; q < R; ++q) {
+        double v = x[q];
+        if (q < QM) {
+          const int i = r + G * q;
+          v = i == s ? v0 : (i > s ? v : 0.0);
+        }
+        a[q & 3] = fma(v, qv[q], a[q & 3]);
+      }
+      hhr_totals<L>((a[0] + a[1]) + (a[2] + a[3]), sh.part, sh.tot);
+      const double d = j < ell ? tv * sh.tot[j] : 0.0;
+      hhr_axpy<L, R>(x, qv, r, s, v0, d);
+    } else {
+      const double p = hhr_refl<L, R, 0>(w, qv, r, s, v0, 0.0, nr);
+      hhr_totals<L>(p, sh.part, sh.tot);
+      const double d = j < ell ? tv * sh.tot[j] : 0.0;
+      hhr_refl<L, R, 1>(w, qv, r, s, v0, d, nr);
+    }
   }
 }
 
