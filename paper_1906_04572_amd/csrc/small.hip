@@ -2407,9 +2407,10 @@ static int hhr_rows_per_thread(int L, int64_t nr) {
   return q <= 4 ? 4 : (q <= 8 ? 8 : (q <= 16 ? 16 : 0));
 }
 // Panels of the register-resident tree: 1 (one workgroup), P >= 2, or 0
-// when rows is too large for two levels.  About sqrt(rows / ell) panels, so
-// a panel and the stacked triangles have similar heights, within: panel
-// rows <= 16 G, stacked triangles P ell <= 16 G, panel rows >= ell.
+// when rows is too large for two levels.  Within panel rows <= 16 G, stacked
+// triangles P ell <= 16 G and panel rows >= ell, the P whose panel and root
+// need the fewest rows per thread in all (the kernels are instantiated for 4,
+// 8 and 16), the smallest such P.
 static int hhr_panels(int64_t rows, int ell) {
   const int L = hhr_width(ell);
   if (L == 0) return 0;
@@ -2417,8 +2418,16 @@ static int hhr_panels(int64_t rows, int ell) {
   if (rows <= cap) return 1;
   const int64_t pmin = (rows + cap - 1) / cap, pmax = std::min<int64_t>(cap / ell, rows / ell);
   if (pmin > pmax) return 0;
-  const int64_t bal = (int64_t)std::ceil(std::sqrt((double)rows / ell));
-  return (int)std::max(pmin, std::min(bal, pmax));
+  int64_t best = pmin;
+  int best_cost = 1 << 30;
+  for (int64_t P = pmin; P <= pmax; ++P) {
+    const int cost = hhr_rows_per_thread(L, (rows + P - 1) / P) + hhr_rows_per_thread(L, P * ell);
+    if (cost < best_cost) {
+      best_cost = cost;
+      best = P;
+    }
+  }
+  return (int)best;
 }
 
 
