@@ -1650,151 +1650,69 @@ __global__ void __launch_bounds__(1024) hh_expand_s_kernel(const double* __restr
 
 // ---------------------------------------------------------------------------
 // Householder QR with the working matrix in registers (l <= 64, panels of at
-// most 16 rows per thread).  Thread t serves column j = t % L and the rows
-// i = r + G q (r = t / L, G = 1024 / L, q < R) of its panel, holding W(i, j)
-// in w[q].  One step s needs column s at every thread of a row group (the
-// row group's lane s holds it): a DPP row broadcast for L = 16, register
-// reads of the one or two row groups of a wave otherwise.  Each step takes a
-// single sum over the rows: p_j = x^T W(:, j) over rows >= s, x = column s,
-// gives both ||x||^2 (j = s) and, with the pivot row W(s, :), the reflector
-// products v^T W(:, j) = p_j - alpha W(s, j) (v = x - alpha e_s).  A sum
-// over the rows adds each thread's partial sum (rows in increasing order, in
-// four partial sums) over the row groups of a wave by a butterfly; then the
-// first wave adds the waves' sums in wave order and publishes the column
-// totals (two barriers; every thread reading all the waves' sums would cost
-// more LDS bandwidth than the second barrier).
+// most 1024 / M rows).  The columns are taken in M sets of 16 (M = 1, 2, 4):
+// thread t serves columns c + 16 m (c = t % 16, m < M) of the rows
+// i = r + 64 q (r = t / 16, q < R), holding W(i, c + 16 m) in w[m][q], so
+// the 16 lanes of a row group (one DPP row) hold one row.  A step s needs
+// column s at every thread of a row group: a DPP row broadcast (row_newbcast,
+// an immediate lane, hence one code path per s % 16) from set s / 16.  Each
+// step takes a single sum over the rows: p_j = x^T W(:, j) over rows >= s,
+// x = column s, gives both ||x||^2 (j = s) and, with the pivot row W(s, :),
+// the reflector products v^T W(:, j) = p_j - alpha W(s, j)
+// (v = x - alpha e_s).  A sum over the rows adds each thread's partial sum
+// (rows in increasing order, in four partial sums) over the four row groups
+// of a wave by two v_permlane swaps, then the first wave adds the waves'
+// sums in wave order and publishes the column totals (two barriers; every
+// thread reading all the waves' sums would cost more LDS bandwidth than the
+// second barrier).  Rows below s occur only among the first 64 (s < l <= 64),
+// and rows at or beyond the panel's height hold zeros, so only q = 0 takes a
+// mask.
 template <int S>
 __device__ __forceinline__ double hhr_bc16_one(double v) {
   // v_mov_b64_dpp row_newbcast:S
   return __longlong_as_double(__builtin_amdgcn_update_dpp(0LL, __double_as_longlong(v), 0x150 + S, 0xF, 0xF, false));
 }
 
-template <int S, int R>
-__device__ __forceinline__ void hhr_bc16(const double (&w)[R], double (&x)[R]) {
+template <int S, int M, int R>
+__device__ __forceinline__ void hhr_bcm(const double (&w)[M][R], double (&x)[R], int ms) {
 #pragma unroll
-  for (int q = 0; q < R; ++q) x[q] = hhr_bc16_one<S>(w[q]);
-}
-
-// the value of lane 16 * odd + S of the thread's 32-lane row group
-template <int S>
-__device__ __forceinline__ double hhr_bc32_one(double v, bool odd) {
-  const long long b = __builtin_amdgcn_update_dpp(0LL, __double_as_longlong(v), 0x150 + S, 0xF, 0xF, false);
-  // (b, b) swapped: [0] holds the even row of each pair in both rows, [1] the odd one
-  const auto lo = __builtin_amdgcn_permlane16_swap((unsigned)b, (unsigned)b, false, false);
-  const auto hi = __builtin_amdgcn_permlane16_swap((unsigned)(b >> 32), (unsigned)(b >> 32), false, false);
-  const unsigned l = odd ? lo[1] : lo[0], h = odd ? hi[1] : hi[0];
-  return __longlong_as_double(((long long)h << 32) | l);
-}
-
-template <int S, int R>
-__device__ __forceinline__ void hhr_bc32(const double (&w)[R], double (&x)[R], bool odd) {
+  for (int m = 0; m < M; ++m)
+    if (m == ms) {  // uniform
 #pragma unroll
-  for (int q = 0; q < R; ++q) x[q] = hhr_bc32_one<S>(w[q], odd);
-}
-
-// x[q] = the value of column s (uniform) in w[q] of the thread's row group
-template <int L, int R>
-__device__ __forceinline__ void hhr_col(const double (&w)[R], double (&x)[R], int s) {
-  if constexpr (L == 16) {
-    switch (s) {
-      case 0: hhr_bc16<0, R>(w, x); break;
-      case 1: hhr_bc16<1, R>(w, x); break;
-      case 2: hhr_bc16<2, R>(w, x); break;
-      case 3: hhr_bc16<3, R>(w, x); break;
-      case 4: hhr_bc16<4, R>(w, x); break;
-      case 5: hhr_bc16<5, R>(w, x); break;
-      case 6: hhr_bc16<6, R>(w, x); break;
-      case 7: hhr_bc16<7, R>(w, x); break;
-      case 8: hhr_bc16<8, R>(w, x); break;
-      case 9: hhr_bc16<9, R>(w, x); break;
-      case 10: hhr_bc16<10, R>(w, x); break;
-      case 11: hhr_bc16<11, R>(w, x); break;
-      case 12: hhr_bc16<12, R>(w, x); break;
-      case 13: hhr_bc16<13, R>(w, x); break;
-      case 14: hhr_bc16<14, R>(w, x); break;
-      default: hhr_bc16<15, R>(w, x); break;
+      for (int q = 0; q < R; ++q) x[q] = hhr_bc16_one<S>(w[m][q]);
     }
-  } else if constexpr (L == 32) {
-    // a row group is two DPP rows: broadcast lane s % 16 inside each row,
-    // then v_permlane16_swap hands the row holding column s to its partner
-    const bool odd = s >= 16;
-    switch (s & 15) {
-      case 0: hhr_bc32<0, R>(w, x, odd); break;
-      case 1: hhr_bc32<1, R>(w, x, odd); break;
-      case 2: hhr_bc32<2, R>(w, x, odd); break;
-      case 3: hhr_bc32<3, R>(w, x, odd); break;
-      case 4: hhr_bc32<4, R>(w, x, odd); break;
-      case 5: hhr_bc32<5, R>(w, x, odd); break;
-      case 6: hhr_bc32<6, R>(w, x, odd); break;
-      case 7: hhr_bc32<7, R>(w, x, odd); break;
-      case 8: hhr_bc32<8, R>(w, x, odd); break;
-      case 9: hhr_bc32<9, R>(w, x, odd); break;
-      case 10: hhr_bc32<10, R>(w, x, odd); break;
-      case 11: hhr_bc32<11, R>(w, x, odd); break;
-      case 12: hhr_bc32<12, R>(w, x, odd); break;
-      case 13: hhr_bc32<13, R>(w, x, odd); break;
-      case 14: hhr_bc32<14, R>(w, x, odd); break;
-      default: hhr_bc32<15, R>(w, x, odd); break;
-    }
-  } else {
-#pragma unroll
-    for (int q = 0; q < R; ++q) x[q] = readlane_f64(w[q], s);
+}
+
+// x[q] = the value of column s (uniform) in row q of the thread's row group
+template <int M, int R>
+__device__ __forceinline__ void hhr_col(const double (&w)[M][R], double (&x)[R], int s) {
+  const int ms = s >> 4;
+  switch (s & 15) {
+    case 0: hhr_bcm<0, M, R>(w, x, ms); break;
+    case 1: hhr_bcm<1, M, R>(w, x, ms); break;
+    case 2: hhr_bcm<2, M, R>(w, x, ms); break;
+    case 3: hhr_bcm<3, M, R>(w, x, ms); break;
+    case 4: hhr_bcm<4, M, R>(w, x, ms); break;
+    case 5: hhr_bcm<5, M, R>(w, x, ms); break;
+    case 6: hhr_bcm<6, M, R>(w, x, ms); break;
+    case 7: hhr_bcm<7, M, R>(w, x, ms); break;
+    case 8: hhr_bcm<8, M, R>(w, x, ms); break;
+    case 9: hhr_bcm<9, M, R>(w, x, ms); break;
+    case 10: hhr_bcm<10, M, R>(w, x, ms); break;
+    case 11: hhr_bcm<11, M, R>(w, x, ms); break;
+    case 12: hhr_bcm<12, M, R>(w, x, ms); break;
+    case 13: hhr_bcm<13, M, R>(w, x, ms); break;
+    case 14: hhr_bcm<14, M, R>(w, x, ms); break;
+    default: hhr_bcm<15, M, R>(w, x, ms); break;
   }
 }
 
-// The one reflector step of hhr_apply with the broadcast taken per row
-// instead of into a register array (the apply holds two arrays already):
-// MODE 0 returns the partial sum of v_i y_i over own rows i >= s (< nr),
-// MODE 1 applies y_i -= d v_i; v_i = column s of w, v_s = v0.
-template <int L, int R, int MODE, typename BC>
-__device__ __forceinline__ double hhr_refl_rows(BC bc, const double (&w)[R], double (&y)[R], int r, int s,
-                                                double v0, double d, int nr) {
-  constexpr int G = 1024 / L, QM = (L + G - 1) / G;
-  double a[4] = {0.0, 0.0, 0.0, 0.0};
-#pragma unroll
-  for (int q = 0; q < R; ++q) {
-    double v = bc(w[q]);
-    if (q < QM) {  // rows below L: the head and the rows above it
-      const int i = r + G * q;
-      v = i == s ? v0 : (i > s ? v : 0.0);
-    }
-    if (MODE == 0) a[q & 3] = fma(v, y[q], a[q & 3]);
-    else y[q] = fma(-d, v, y[q]);
-  }
-  return (a[0] + a[1]) + (a[2] + a[3]);
-}
-
-template <int L, int R, int MODE>
-__device__ __forceinline__ double hhr_refl(const double (&w)[R], double (&y)[R], int r, int s, double v0, double d,
-                                           int nr) {
-  if constexpr (L == 16) {
-    switch (s) {
-#define CORUTV_RF(S) \
-  case S:            \
-    return hhr_refl_rows<L, R, MODE>([](double v) { return hhr_bc16_one<S>(v); }, w, y, r, s, v0, d, nr);
-      CORUTV_RF(0) CORUTV_RF(1) CORUTV_RF(2) CORUTV_RF(3) CORUTV_RF(4) CORUTV_RF(5) CORUTV_RF(6) CORUTV_RF(7)
-      CORUTV_RF(8) CORUTV_RF(9) CORUTV_RF(10) CORUTV_RF(11) CORUTV_RF(12) CORUTV_RF(13) CORUTV_RF(14)
-#undef CORUTV_RF
-      default:
-        return hhr_refl_rows<L, R, MODE>([](double v) { return hhr_bc16_one<15>(v); }, w, y, r, s, v0, d, nr);
-    }
-  } else if constexpr (L == 32) {
-    const bool odd = s >= 16;
-    switch (s & 15) {
-#define CORUTV_RF32(S)                                                                         \
-  case S:                                                                                      \
-    return hhr_refl_rows<L, R, MODE>([odd](double v) { return hhr_bc32_one<S>(v, odd); }, w, y, r, s, v0, d, nr);
-      CORUTV_RF32(0) CORUTV_RF32(1) CORUTV_RF32(2) CORUTV_RF32(3) CORUTV_RF32(4) CORUTV_RF32(5) CORUTV_RF32(6)
-      CORUTV_RF32(7) CORUTV_RF32(8) CORUTV_RF32(9) CORUTV_RF32(10) CORUTV_RF32(11) CORUTV_RF32(12)
-      CORUTV_RF32(13) CORUTV_RF32(14)
-#undef CORUTV_RF32
-      default:
-        return hhr_refl_rows<L, R, MODE>([odd](double v) { return hhr_bc32_one<15>(v, odd); }, w, y, r, s, v0, d,
-                                         nr);
-    }
-  } else {
-    return hhr_refl_rows<L, R, MODE>([s](double v) { return readlane_f64(v, s); }, w, y, r, s, v0, d, nr);
-  }
+// The reflector's entry in the thread's row q: x, with v0 at row s and zero
+// above it (only q = 0 can hold rows <= s)
+template <int R>
+__device__ __forceinline__ double hhr_v(const double (&x)[R], int q, int r, int s, double v0) {
+  if (q > 0) return x[q];
+  return r == s ? v0 : (r > s ? x[0] : 0.0);
 }
 
 // a + b with a, b the two halves that v_permlane16_swap (rows of 16 lanes)
@@ -1819,94 +1737,64 @@ __device__ __forceinline__ double hhr_swap_add(double v) {
   return x + y;  // (even row or lower half) + (odd row or upper half)
 }
 
-// sum over the row groups of a wave (lane bits >= log2 L), in the same
-// order in every lane
-template <int L>
-__device__ __forceinline__ double hhr_wave_rows(double p) {
-  if constexpr (L <= 16) p = hhr_swap_add<false>(p);
-  if constexpr (L <= 32) p = hhr_swap_add<true>(p);
-  return p;
-}
+// LDS of the register-resident kernels (L = 16 M columns)
+template <int M>
+struct HhrLds {
+  double part[16 * 16 * M], tot[16 * M], prow[2 * 16 * M];
+  double tau[16 * M], alpha[16 * M], vhead[16 * M];
+};
 
-// sum over own rows i >= lo of x_i y_i.  Rows at or beyond the panel's
-// height hold zeros, and rows below lo occur only among the first L rows
-// (lo < ell <= L), so only those take a mask.
-template <int L, int R>
-__device__ __forceinline__ double hhr_dot(const double (&x)[R], const double (&y)[R], int r, int lo) {
-  constexpr int G = 1024 / L, QM = (L + G - 1) / G;
-  double a[4] = {0.0, 0.0, 0.0, 0.0};
-#pragma unroll
-  for (int q = 0; q < R; ++q) {
-    const double xv = (q < QM && r + G * q < lo) ? 0.0 : x[q];
-    a[q & 3] = fma(xv, y[q], a[q & 3]);
-  }
-  return (a[0] + a[1]) + (a[2] + a[3]);
-}
-
-// y_i -= d v_i over own rows i >= s, v_i = x[q], v_s = v0
-template <int L, int R>
-__device__ __forceinline__ void hhr_axpy(const double (&x)[R], double (&y)[R], int r, int s, double v0, double d) {
-  constexpr int G = 1024 / L, QM = (L + G - 1) / G;
-#pragma unroll
-  for (int q = 0; q < R; ++q) {
-    double v = x[q];
-    if (q < QM) {
-      const int i = r + G * q;
-      v = i == s ? v0 : (i > s ? v : 0.0);
-    }
-    y[q] = fma(-d, v, y[q]);
-  }
-}
-
-// Column totals of the per-thread partial sums p: the row groups of each
-// wave, then (first wave) the 16 waves in order.  Barrier 1 publishes the
-// waves' sums (and whatever the caller wrote before it), barrier 2 the
-// totals.  part: 16 L doubles, tot: L doubles (LDS).
-template <int L>
-__device__ __forceinline__ void hhr_totals(double p, double* part, double* tot) {
+// Column totals of the per-thread partial sums p[m] (column c + 16 m): the
+// row groups of each wave, then (first wave) the 16 waves in order.  Barrier
+// 1 publishes the waves' sums (and whatever the caller wrote before it),
+// barrier 2 the totals in sh.tot.
+template <int M>
+__device__ __forceinline__ void hhr_totals(const double (&p)[M], HhrLds<M>& sh) {
+  constexpr int L = 16 * M;
   const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
-  p = hhr_wave_rows<L>(p);
-  if (lane < L) part[wave * L + lane] = p;
+#pragma unroll
+  for (int m = 0; m < M; ++m) {
+    const double v = hhr_swap_add<true>(hhr_swap_add<false>(p[m]));
+    if (lane < 16) sh.part[wave * L + 16 * m + lane] = v;
+  }
   __syncthreads();
   if (wave == 0 && lane < L) {
     double a = 0.0;
 #pragma unroll
-    for (int w = 0; w < 16; ++w) a += part[w * L + lane];
-    tot[lane] = a;
+    for (int w = 0; w < 16; ++w) a += sh.part[w * L + lane];
+    sh.tot[lane] = a;
   }
   __syncthreads();
 }
-
-// LDS of the register-resident kernels
-template <int L>
-struct HhrLds {
-  double part[16 * L], tot[L], prow[2 * L];
-  double tau[L], alpha[L], vhead[L];
-};
 
 // Householder reduction of the nr x ell panel held in w (zeros outside it).
 // Afterwards w holds R above the diagonal, the reflector tails below it and
 // the original x_s on the diagonal; tau, alpha (R's diagonal) and vhead (the
 // first entry of each reflector) go to LDS.  Ends with a barrier.
-template <int L, int R>
-__device__ void hhr_factor(double (&w)[R], int nr, int ell, HhrLds<L>& sh) {
-  constexpr int G = 1024 / L;
-  const int t = threadIdx.x, j = t % L, r = t / L;
+template <int M, int R>
+__device__ void hhr_factor(double (&w)[M][R], int ell, HhrLds<M>& sh) {
+  const int t = threadIdx.x, c = t & 15, r = t >> 4;
   for (int s = 0; s < ell; ++s) {
     double x[R];
-    hhr_col<L, R>(w, x, s);
-    const double p = hhr_dot<L, R>(x, w, r, s);
-    double* prow = sh.prow + (s & 1) * L;
-    if (s % G == r) {  // this row group holds the pivot row s
-      double pv = 0.0;
+    hhr_col<M, R>(w, x, s);
+    double p[M];
 #pragma unroll
-      for (int q = 0; q < R; ++q)
-        if (q == s / G) pv = w[q];
-      prow[j] = pv;
+    for (int m = 0; m < M; ++m) {
+      double a[4] = {0.0, 0.0, 0.0, 0.0};
+#pragma unroll
+      for (int q = 0; q < R; ++q) {
+        const double xv = (q == 0 && r < s) ? 0.0 : x[q];
+        a[q & 3] = fma(xv, w[m][q], a[q & 3]);
+      }
+      p[m] = (a[0] + a[1]) + (a[2] + a[3]);
     }
-    hhr_totals<L>(p, sh.part, sh.tot);
-    const double ts = sh.tot[s], tj = sh.tot[j];
-    const double x0 = prow[s], wsj = prow[j];
+    double* prow = sh.prow + (s & 1) * 16 * M;
+    if (r == s) {  // this row group holds the pivot row s (in q = 0)
+#pragma unroll
+      for (int m = 0; m < M; ++m) prow[c + 16 * m] = w[m][0];
+    }
+    hhr_totals<M>(p, sh);
+    const double ts = sh.tot[s], x0 = prow[s];
     const double nrm = sqrt(ts);
     double tv = 0.0, v0 = 0.0, a = 0.0;
     if (nrm != 0.0) {
@@ -1919,60 +1807,102 @@ __device__ void hhr_factor(double (&w)[R], int nr, int ell, HhrLds<L>& sh) {
       sh.alpha[s] = a;
       sh.vhead[s] = v0;
     }
-    // column s itself keeps x (the reflector's tail): d = 0 there
-    const double d = (tv != 0.0 && j > s && j < ell) ? tv * (tj - a * wsj) : 0.0;
-    hhr_axpy<L, R>(x, w, r, s, v0, d);
+    // columns at or left of s are left as they are: d = 0 there
+#pragma unroll
+    for (int m = 0; m < M; ++m) {
+      const int j = c + 16 * m;
+      const double d = (tv != 0.0 && j > s && j < ell) ? tv * (sh.tot[j] - a * prow[j]) : 0.0;
+#pragma unroll
+      for (int q = 0; q < R; ++q) w[m][q] = fma(-d, hhr_v(x, q, r, s, v0), w[m][q]);
+    }
   }
   __syncthreads();
 }
 
+// One reflector of hhr_apply for one set of 16 columns with the broadcast
+// taken row by row instead of into a register array (R = 16: the apply
+// holds two arrays already): MODE 0 returns the partial sum of v_i y_i,
+// MODE 1 applies y_i -= d v_i.
+template <int S, int R, int MODE>
+__device__ __forceinline__ double hhr_refl_s(const double (&w)[R], double (&y)[R], int r, int s, double v0, double d) {
+  double a[4] = {0.0, 0.0, 0.0, 0.0};
+#pragma unroll
+  for (int q = 0; q < R; ++q) {
+    double v = hhr_bc16_one<S>(w[q]);
+    if (q == 0) v = r == s ? v0 : (r > s ? v : 0.0);
+    if (MODE == 0) a[q & 3] = fma(v, y[q], a[q & 3]);
+    else y[q] = fma(-d, v, y[q]);
+  }
+  return (a[0] + a[1]) + (a[2] + a[3]);
+}
+
+template <int R, int MODE>
+__device__ __forceinline__ double hhr_refl(const double (&w)[R], double (&y)[R], int r, int s, double v0, double d) {
+  switch (s & 15) {
+#define CORUTV_RF(S) \
+  case S:            \
+    return hhr_refl_s<S, R, MODE>(w, y, r, s, v0, d);
+    CORUTV_RF(0) CORUTV_RF(1) CORUTV_RF(2) CORUTV_RF(3) CORUTV_RF(4) CORUTV_RF(5) CORUTV_RF(6) CORUTV_RF(7)
+    CORUTV_RF(8) CORUTV_RF(9) CORUTV_RF(10) CORUTV_RF(11) CORUTV_RF(12) CORUTV_RF(13) CORUTV_RF(14)
+#undef CORUTV_RF
+    default:
+      return hhr_refl_s<15, R, MODE>(w, y, r, s, v0, d);
+  }
+}
+
 // qv <- H_0 ... H_{ell-1} qv with the reflectors of hhr_factor (w and the
 // tau, vhead in sh).
-template <int L, int R>
-__device__ void hhr_apply(const double (&w)[R], double (&qv)[R], int nr, int ell, HhrLds<L>& sh) {
-  const int t = threadIdx.x, j = t % L, r = t / L;
+template <int M, int R>
+__device__ void hhr_apply(const double (&w)[M][R], double (&qv)[M][R], int ell, HhrLds<M>& sh) {
+  const int t = threadIdx.x, c = t & 15, r = t >> 4;
   for (int s = ell - 1; s >= 0; --s) {
     const double tv = sh.tau[s];
     if (tv == 0.0) continue;  // uniform
     const double v0 = sh.vhead[s];
-    if constexpr (R <= 8) {
-      // the column broadcast once per step into registers (they fit)
-      double x[R];
-      hhr_col<L, R>(w, x, s);
-      constexpr int G = 1024 / L, QM = (L + G - 1) / G;
+    if constexpr (R == 16) {  // one set of columns (M R <= 16)
+      static_assert(M == 1, "16 rows per thread with one set of columns only");
+      double p[1] = {hhr_refl<R, 0>(w[0], qv[0], r, s, v0, 0.0)};
+      hhr_totals<M>(p, sh);
+      const double d = c < ell ? tv * sh.tot[c] : 0.0;
+      hhr_refl<R, 1>(w[0], qv[0], r, s, v0, d);
+      continue;
+    }
+    double x[R];
+    hhr_col<M, R>(w, x, s);
+    double p[M];
+#pragma unroll
+    for (int m = 0; m < M; ++m) {
       double a[4] = {0.0, 0.0, 0.0, 0.0};
 #pragma unroll
-      for (int q = 0; q < R; ++q) {
-        double v = x[q];
-        if (q < QM) {
-          const int i = r + G * q;
-          v = i == s ? v0 : (i > s ? v : 0.0);
-        }
-        a[q & 3] = fma(v, qv[q], a[q & 3]);
-      }
-      hhr_totals<L>((a[0] + a[1]) + (a[2] + a[3]), sh.part, sh.tot);
-      const double d = j < ell ? tv * sh.tot[j] : 0.0;
-      hhr_axpy<L, R>(x, qv, r, s, v0, d);
-    } else {
-      const double p = hhr_refl<L, R, 0>(w, qv, r, s, v0, 0.0, nr);
-      hhr_totals<L>(p, sh.part, sh.tot);
-      const double d = j < ell ? tv * sh.tot[j] : 0.0;
-      hhr_refl<L, R, 1>(w, qv, r, s, v0, d, nr);
+      for (int q = 0; q < R; ++q) a[q & 3] = fma(hhr_v(x, q, r, s, v0), qv[m][q], a[q & 3]);
+      p[m] = (a[0] + a[1]) + (a[2] + a[3]);
+    }
+    hhr_totals<M>(p, sh);
+#pragma unroll
+    for (int m = 0; m < M; ++m) {
+      const double d = c + 16 * m < ell ? tv * sh.tot[c + 16 * m] : 0.0;
+#pragma unroll
+      for (int q = 0; q < R; ++q) qv[m][q] = fma(-d, hhr_v(x, q, r, s, v0), qv[m][q]);
     }
   }
 }
 
-// w[q] = X(r0 + i, j) for own rows i < nr and j < ell, else 0
-template <int L, int R>
-__device__ __forceinline__ void hhr_load(double (&w)[R], const double* __restrict__ X, int64_t ldx, int64_t r0,
+// w[m][q] = X(r0 + i, c + 16 m) for own rows i < nr and columns < ell, else
+// 0.  Every load is unconditional, from a clamped address, and masked
+// afterwards: loads under per-lane branches are waited for one by one.
+template <int M, int R>
+__device__ __forceinline__ void hhr_load(double (&w)[M][R], const double* __restrict__ X, int64_t ldx, int64_t r0,
                                          int nr, int ell) {
-  constexpr int G = 1024 / L;
-  const int j = threadIdx.x % L, r = threadIdx.x / L;
+  const int c = threadIdx.x & 15, r = threadIdx.x >> 4;
 #pragma unroll
-  for (int q = 0; q < R; ++q) {
-    const int i = r + G * q;
-    w[q] = (i < nr && j < ell) ? X[(int64_t)j * ldx + r0 + i] : 0.0;
-  }
+  for (int m = 0; m < M; ++m)
+#pragma unroll
+    for (int q = 0; q < R; ++q) {
+      const int i = r + 64 * q, j = c + 16 * m;
+      const int ic = i < nr ? i : nr - 1, jc = j < ell ? j : ell - 1;
+      const double v = X[(int64_t)jc * ldx + r0 + ic];
+      w[m][q] = (i < nr && j < ell) ? v : 0.0;
+    }
 }
 
 // The kernels of a QR run after a Cholesky breakdown on finite data.
@@ -1980,41 +1910,44 @@ __device__ __forceinline__ bool hhr_runs(const int* status) { return (*status & 
 
 // One workgroup: X (rows x ell, column-major) -> Q (diag R >= 0, FP64 and
 // optionally a float copy), R (nullable, ell x ell column-major).
-template <int L, int R>
+template <int M, int R>
 __global__ void __launch_bounds__(1024) hhr_one_kernel(const double* __restrict__ X, int64_t ldx, int64_t rows,
                                                        int ell, double* __restrict__ Q, int64_t ldq,
                                                        float* __restrict__ Q32, int64_t ldq32,
                                                        double* __restrict__ Rout, const int* status) {
   if (!hhr_runs(status)) return;
-  constexpr int G = 1024 / L;
-  __shared__ HhrLds<L> sh;
-  const double* alpha = sh.alpha;
-  const int t = threadIdx.x, j = t % L, r = t / L;
-  double w[R];
-  hhr_load<L, R>(w, X, ldx, 0, rows, ell);
-  hhr_factor<L, R>(w, rows, ell, sh);
-  if (Rout && j < ell) {
+  __shared__ HhrLds<M> sh;
+  const int t = threadIdx.x, c = t & 15, r = t >> 4;
+  double w[M][R];
+  hhr_load<M, R>(w, X, ldx, 0, (int)rows, ell);
+  hhr_factor<M, R>(w, ell, sh);
+  if (Rout && r < ell) {  // rows i < ell are the first 64 (q = 0)
 #pragma unroll
-    for (int q = 0; q < R; ++q) {
-      const int i = r + G * q;
-      if (i < ell) {
-        double v = i < j ? w[q] : (i == j ? alpha[i] : 0.0);
-        if (alpha[i] < 0.0) v = -v;
-        Rout[(int64_t)j * ell + i] = v;
+    for (int m = 0; m < M; ++m) {
+      const int j = c + 16 * m;
+      if (j < ell) {
+        double v = r < j ? w[m][0] : (r == j ? sh.alpha[r] : 0.0);
+        if (sh.alpha[r] < 0.0) v = -v;
+        Rout[(int64_t)j * ell + r] = v;
       }
     }
   }
-  double qv[R];
+  double qv[M][R];
 #pragma unroll
-  for (int q = 0; q < R; ++q) qv[q] = (r + G * q == j && j < ell) ? 1.0 : 0.0;
-  hhr_apply<L, R>(w, qv, rows, ell, sh);
-  if (j < ell) {
-    const bool flip = alpha[j] < 0.0;
+  for (int m = 0; m < M; ++m)
+#pragma unroll
+    for (int q = 0; q < R; ++q) qv[m][q] = (q == 0 && r == c + 16 * m && r < ell) ? 1.0 : 0.0;
+  hhr_apply<M, R>(w, qv, ell, sh);
+#pragma unroll
+  for (int m = 0; m < M; ++m) {
+    const int j = c + 16 * m;
+    if (j >= ell) continue;
+    const bool flip = sh.alpha[j] < 0.0;
 #pragma unroll
     for (int q = 0; q < R; ++q) {
-      const int i = r + G * q;
+      const int i = r + 64 * q;
       if (i < rows) {
-        const double v = flip ? -qv[q] : qv[q];
+        const double v = flip ? -qv[m][q] : qv[m][q];
         Q[(int64_t)j * ldq + i] = v;
         if (Q32) Q32[(int64_t)j * ldq32 + i] = (float)v;
       }
@@ -2025,69 +1958,79 @@ __global__ void __launch_bounds__(1024) hhr_one_kernel(const double* __restrict_
 // Tree level 1: panel b (rows split evenly over P panels) reduced; its
 // reflectors (and R's entries above them) to W, its triangle to rows
 // b ell .. of Rs (ld P ell), tau and vhead to tv.
-template <int L, int R>
+template <int M, int R>
 __global__ void __launch_bounds__(1024) hhr_panel_kernel(const double* __restrict__ X, int64_t ldx, int64_t rows,
                                                          int ell, int P, double* __restrict__ W, int64_t ldw,
                                                          double* __restrict__ Rs, double* __restrict__ tv,
                                                          const int* status) {
   if (!hhr_runs(status)) return;
-  constexpr int G = 1024 / L;
-  __shared__ HhrLds<L> sh;
-  const double *tau = sh.tau, *alpha = sh.alpha, *vhead = sh.vhead;
-  const int t = threadIdx.x, j = t % L, r = t / L, b = blockIdx.x;
+  __shared__ HhrLds<M> sh;
+  const int t = threadIdx.x, c = t & 15, r = t >> 4, b = blockIdx.x;
   const int64_t r0 = (int64_t)b * rows / P, hb = (int64_t)(b + 1) * rows / P - r0;
-  double w[R];
-  hhr_load<L, R>(w, X, ldx, r0, hb, ell);
-  hhr_factor<L, R>(w, hb, ell, sh);
+  double w[M][R];
+  hhr_load<M, R>(w, X, ldx, r0, (int)hb, ell);
+  hhr_factor<M, R>(w, ell, sh);
   const int64_t ldr = (int64_t)P * ell;
-  if (j < ell) {
+#pragma unroll
+  for (int m = 0; m < M; ++m) {
+    const int j = c + 16 * m;
+    if (j >= ell) continue;
+    if (r < ell) Rs[(int64_t)j * ldr + (int64_t)b * ell + r] = r < j ? w[m][0] : (r == j ? sh.alpha[r] : 0.0);
 #pragma unroll
     for (int q = 0; q < R; ++q) {
-      const int i = r + G * q;
-      if (i < ell) Rs[(int64_t)j * ldr + (int64_t)b * ell + i] = i < j ? w[q] : (i == j ? alpha[i] : 0.0);
-      if (i < hb) W[(int64_t)j * ldw + r0 + i] = w[q];
+      const int i = r + 64 * q;
+      if (i < hb) W[(int64_t)j * ldw + r0 + i] = w[m][q];
     }
   }
   if (t < ell) {
-    tv[(int64_t)b * 2 * ell + t] = tau[t];
-    tv[(int64_t)b * 2 * ell + ell + t] = vhead[t];
+    tv[(int64_t)b * 2 * ell + t] = sh.tau[t];
+    tv[(int64_t)b * 2 * ell + ell + t] = sh.vhead[t];
   }
 }
 
 // Tree level 2: panel b of Q = its reflectors applied to [Qr rows b ell ..; 0].
-template <int L, int R>
+template <int M, int R>
 __global__ void __launch_bounds__(1024) hhr_expand_kernel(const double* __restrict__ W, int64_t ldw, int64_t rows,
                                                           int ell, int P, const double* __restrict__ Qr,
                                                           const double* __restrict__ tv, double* __restrict__ Q,
                                                           int64_t ldq, float* __restrict__ Q32, int64_t ldq32,
                                                           const int* status) {
   if (!hhr_runs(status)) return;
-  constexpr int G = 1024 / L;
-  __shared__ HhrLds<L> sh;
-  double *tau = sh.tau, *vhead = sh.vhead;
-  const int t = threadIdx.x, j = t % L, r = t / L, b = blockIdx.x;
+  __shared__ HhrLds<M> sh;
+  const int t = threadIdx.x, c = t & 15, r = t >> 4, b = blockIdx.x;
   const int64_t r0 = (int64_t)b * rows / P, hb = (int64_t)(b + 1) * rows / P - r0;
   const int64_t ldr = (int64_t)P * ell;
   if (t < ell) {
-    tau[t] = tv[(int64_t)b * 2 * ell + t];
-    vhead[t] = tv[(int64_t)b * 2 * ell + ell + t];
+    sh.tau[t] = tv[(int64_t)b * 2 * ell + t];
+    sh.vhead[t] = tv[(int64_t)b * 2 * ell + ell + t];
   }
-  double w[R], qv[R];
-  hhr_load<L, R>(w, W, ldw, r0, hb, ell);
+  double w[M][R], qv[M][R];
+  hhr_load<M, R>(w, W, ldw, r0, (int)hb, ell);
 #pragma unroll
-  for (int q = 0; q < R; ++q) {
-    const int i = r + G * q;
-    qv[q] = (i < ell && j < ell) ? Qr[(int64_t)j * ldr + (int64_t)b * ell + i] : 0.0;
+  for (int m = 0; m < M; ++m) {
+    const int j = c + 16 * m;
+    const int jc = j < ell ? j : ell - 1, rc = r < ell ? r : ell - 1;
+    const double v = Qr[(int64_t)jc * ldr + (int64_t)b * ell + rc];  // unconditional, as in hhr_load
+#pragma unroll
+    for (int q = 0; q < R; ++q) qv[m][q] = (q == 0 && r < ell && j < ell) ? v : 0.0;
   }
   __syncthreads();
-  hhr_apply<L, R>(w, qv, hb, ell, sh);
-  if (j < ell) {
+  hhr_apply<M, R>(w, qv, ell, sh);
+  // the output addresses are formed here, not kept in registers across the
+  // loop above (the empty asm hides where the bases come from)
+  double* Qo = Q + r0;
+  float* Q32o = Q32 ? Q32 + r0 : nullptr;
+  asm volatile("" : "+s"(Qo), "+s"(Q32o));
+#pragma unroll
+  for (int m = 0; m < M; ++m) {
+    const int j = c + 16 * m;
+    if (j >= ell) continue;
 #pragma unroll
     for (int q = 0; q < R; ++q) {
-      const int i = r + G * q;
+      const int i = r + 64 * q;
       if (i < hb) {
-        Q[(int64_t)j * ldq + r0 + i] = qv[q];
-        if (Q32) Q32[(int64_t)j * ldq32 + r0 + i] = (float)qv[q];
+        Qo[(int64_t)j * ldq + i] = qv[m][q];
+        if (Q32o) Q32o[(int64_t)j * ldq32 + i] = (float)qv[m][q];
       }
     }
   }
@@ -2399,29 +2342,30 @@ static HhTree hh_tree(int64_t rows, int ell) {
 
 int hh_panels(int64_t rows, int ell) { return hh_tree(rows, ell).P; }
 
-// The register-resident kernels: column width L (16, 32, 64) and rows per
-// thread (4, 8, 16) for a panel of nr rows; 0 when they do not apply.
-static int hhr_width(int ell) { return ell <= 16 ? 16 : (ell <= 32 ? 32 : (ell <= 64 ? 64 : 0)); }
-static int hhr_rows_per_thread(int L, int64_t nr) {
-  const int64_t q = (nr + 1024 / L - 1) / (1024 / L);
-  return q <= 4 ? 4 : (q <= 8 ? 8 : (q <= 16 ? 16 : 0));
+// The register-resident kernels: M sets of 16 columns (1, 2 or 4) and R rows
+// per thread (4, 8, 16 with M R <= 16) for a panel of nr rows; 0 when they
+// do not apply.
+static int hhr_sets(int ell) { return ell <= 16 ? 1 : (ell <= 32 ? 2 : (ell <= 64 ? 4 : 0)); }
+static int hhr_rows_per_thread(int M, int64_t nr) {
+  const int64_t q = (nr + 63) / 64;
+  const int r = q <= 4 ? 4 : (q <= 8 ? 8 : (q <= 16 ? 16 : 0));
+  return M * r <= 16 ? r : 0;
 }
 // Panels of the register-resident tree: 1 (one workgroup), P >= 2, or 0
-// when rows is too large for two levels.  Within panel rows <= 16 G, stacked
-// triangles P ell <= 16 G and panel rows >= ell, the P whose panel and root
-// need the fewest rows per thread in all (the kernels are instantiated for 4,
-// 8 and 16), the smallest such P.
+// when rows is too large for two levels.  Within panel rows <= 1024 / M,
+// stacked triangles P ell <= 1024 / M and panel rows >= ell, the P whose
+// panel and root need the fewest rows per thread in all, the smallest such P.
 static int hhr_panels(int64_t rows, int ell) {
-  const int L = hhr_width(ell);
-  if (L == 0) return 0;
-  const int64_t cap = 16 * (int64_t)(1024 / L);
+  const int M = hhr_sets(ell);
+  if (M == 0) return 0;
+  const int64_t cap = 1024 / M;
   if (rows <= cap) return 1;
   const int64_t pmin = (rows + cap - 1) / cap, pmax = std::min<int64_t>(cap / ell, rows / ell);
   if (pmin > pmax) return 0;
   int64_t best = pmin;
   int best_cost = 1 << 30;
   for (int64_t P = pmin; P <= pmax; ++P) {
-    const int cost = hhr_rows_per_thread(L, (rows + P - 1) / P) + hhr_rows_per_thread(L, P * ell);
+    const int cost = hhr_rows_per_thread(M, (rows + P - 1) / P) + hhr_rows_per_thread(M, P * ell);
     if (cost < best_cost) {
       best_cost = cost;
       best = P;
@@ -2429,7 +2373,6 @@ static int hhr_panels(int64_t rows, int ell) {
   }
   return (int)best;
 }
-
 
 size_t hh_work_bytes(int64_t rows, int ell) {
   const int P = std::max(hh_panels(rows, ell), hhr_panels(rows, ell));
@@ -2444,22 +2387,20 @@ static bool launch_hhr(const double* X, int64_t ldx, int64_t rows, int ell, doub
                        int64_t ldq, float* Q32, int64_t ldq32, double* R, const int* status, double* hw,
                        hipStream_t st) {
   const int P = hhr_panels(rows, ell);
-  const int L = hhr_width(ell);
+  const int M = hhr_sets(ell);
   if (P == 0) return false;
-#define CORUTV_HHR_ONE(LL, RR) \
-  hhr_one_kernel<LL, RR><<<dim3(1), dim3(1024), 0, st>>>(x, ldxx, nr, ell, q, ldqq, q32, ldq32x, rr, status)
+#define CORUTV_HHR_ONE(MM, RR)                                                                                \
+  if (M == MM && RP == RR)                                                                                    \
+  hhr_one_kernel<MM, RR><<<dim3(1), dim3(1024), 0, st>>>(x, ldxx, nr, ell, q, ldqq, q32, ldq32x, rr, status)
   auto one = [&](const double* x, int64_t ldxx, int64_t nr, double* q, int64_t ldqq, float* q32, int64_t ldq32x,
                  double* rr) {
-    const int RP = hhr_rows_per_thread(L, nr);
-    if (L == 16 && RP == 4) CORUTV_HHR_ONE(16, 4);
-    if (L == 16 && RP == 8) CORUTV_HHR_ONE(16, 8);
-    if (L == 16 && RP == 16) CORUTV_HHR_ONE(16, 16);
-    if (L == 32 && RP == 4) CORUTV_HHR_ONE(32, 4);
-    if (L == 32 && RP == 8) CORUTV_HHR_ONE(32, 8);
-    if (L == 32 && RP == 16) CORUTV_HHR_ONE(32, 16);
-    if (L == 64 && RP == 4) CORUTV_HHR_ONE(64, 4);
-    if (L == 64 && RP == 8) CORUTV_HHR_ONE(64, 8);
-    if (L == 64 && RP == 16) CORUTV_HHR_ONE(64, 16);
+    const int RP = hhr_rows_per_thread(M, nr);
+    CORUTV_HHR_ONE(1, 4);
+    CORUTV_HHR_ONE(1, 8);
+    CORUTV_HHR_ONE(1, 16);
+    CORUTV_HHR_ONE(2, 4);
+    CORUTV_HHR_ONE(2, 8);
+    CORUTV_HHR_ONE(4, 4);
   };
 #undef CORUTV_HHR_ONE
   if (P == 1) {
@@ -2471,33 +2412,27 @@ static bool launch_hhr(const double* X, int64_t ldx, int64_t rows, int ell, doub
   double* Rs = hw;                  // stacked triangles, pe x ell
   double* Qr = Rs + 2 * pe * ell;   // the root's Q
   double* tv = Qr + pe * ell;       // per panel: tau[ell], vhead[ell]
-  const int RP = hhr_rows_per_thread(L, (rows + P - 1) / P);
-#define CORUTV_HHR_PANEL(LL, RR)                                                                                \
-  if (L == LL && RP == RR)                                                                                     \
-    hhr_panel_kernel<LL, RR><<<dim3(P), dim3(1024), 0, st>>>(X, ldx, rows, ell, P, work, ldw, Rs, tv, status)
-#define CORUTV_HHR_EXPAND(LL, RR)                                                                               \
-  if (L == LL && RP == RR)                                                                                     \
-    hhr_expand_kernel<LL, RR><<<dim3(P), dim3(1024), 0, st>>>(work, ldw, rows, ell, P, Qr, tv, Q, ldq, Q32, ldq32, \
+  const int RP = hhr_rows_per_thread(M, (rows + P - 1) / P);
+#define CORUTV_HHR_PANEL(MM, RR)                                                                                \
+  if (M == MM && RP == RR)                                                                                     \
+    hhr_panel_kernel<MM, RR><<<dim3(P), dim3(1024), 0, st>>>(X, ldx, rows, ell, P, work, ldw, Rs, tv, status)
+#define CORUTV_HHR_EXPAND(MM, RR)                                                                               \
+  if (M == MM && RP == RR)                                                                                     \
+    hhr_expand_kernel<MM, RR><<<dim3(P), dim3(1024), 0, st>>>(work, ldw, rows, ell, P, Qr, tv, Q, ldq, Q32, ldq32, \
                                                               status)
-  CORUTV_HHR_PANEL(16, 4);
-  CORUTV_HHR_PANEL(16, 8);
-  CORUTV_HHR_PANEL(16, 16);
-  CORUTV_HHR_PANEL(32, 4);
-  CORUTV_HHR_PANEL(32, 8);
-  CORUTV_HHR_PANEL(32, 16);
-  CORUTV_HHR_PANEL(64, 4);
-  CORUTV_HHR_PANEL(64, 8);
-  CORUTV_HHR_PANEL(64, 16);
+  CORUTV_HHR_PANEL(1, 4);
+  CORUTV_HHR_PANEL(1, 8);
+  CORUTV_HHR_PANEL(1, 16);
+  CORUTV_HHR_PANEL(2, 4);
+  CORUTV_HHR_PANEL(2, 8);
+  CORUTV_HHR_PANEL(4, 4);
   one(Rs, pe, pe, Qr, pe, nullptr, 0, R);
-  CORUTV_HHR_EXPAND(16, 4);
-  CORUTV_HHR_EXPAND(16, 8);
-  CORUTV_HHR_EXPAND(16, 16);
-  CORUTV_HHR_EXPAND(32, 4);
-  CORUTV_HHR_EXPAND(32, 8);
-  CORUTV_HHR_EXPAND(32, 16);
-  CORUTV_HHR_EXPAND(64, 4);
-  CORUTV_HHR_EXPAND(64, 8);
-  CORUTV_HHR_EXPAND(64, 16);
+  CORUTV_HHR_EXPAND(1, 4);
+  CORUTV_HHR_EXPAND(1, 8);
+  CORUTV_HHR_EXPAND(1, 16);
+  CORUTV_HHR_EXPAND(2, 4);
+  CORUTV_HHR_EXPAND(2, 8);
+  CORUTV_HHR_EXPAND(4, 4);
 #undef CORUTV_HHR_PANEL
 #undef CORUTV_HHR_EXPAND
   return true;
