@@ -90,7 +90,12 @@ __global__ void __launch_bounds__(64 * WG) __attribute__((amdgpu_waves_per_eu(si
   constexpr int NT = 64 * WG;           // threads
   constexpr int VPR = KC / E16;         // vectors per skinny row per stage
   constexpr int SPASS = (ELLP * VPR + NT - 1) / NT;
-  __shared__ __attribute__((aligned(16))) T lds_s[2][ELLP * LDK];
+  // staged rows: every thread stores all SPASS of its vectors (rows past
+  // ELLP are never read), so no store waits under a per-lane branch
+  constexpr int ELLS = SPASS * NT / VPR;
+  // two-buffer stage pipeline, except in the wide FP32 kernels
+  constexpr bool kPipe2 = sizeof(T) == 8 || MB <= 8;
+  __shared__ __attribute__((aligned(16))) T lds_s[2][ELLS * LDK];
 
   const int tid = threadIdx.x;
   const int lane = tid & 63, wave = tid >> 6;
@@ -143,14 +148,13 @@ __global__ void __launch_bounds__(64 * WG) __attribute__((amdgpu_waves_per_eu(si
         for (int p = 0; p < SPASS; ++p) {
           const int v = tid + NT * p;
           const int c = v / VPR, kv = v % VPR;
-          if (c < ELLP) *(v16*)&lds_s[buf][c * LDK + kv * E16] = sreg[p];
+          *(v16*)&lds_s[buf][c * LDK + kv * E16] = sreg[p];
         }
       };
-      // raw loads + a validity bit per element; the bits are applied when the
-      // prefetched set becomes current, so nothing waits on the loaded data
-      // until the next chunk's compute
-      auto load_b = [&](int kb, T* b, uint32_t& mask) {
-        mask = 0;
+      // raw loads from clamped addresses.  Only the last k-block of the
+      // reduction reaches past K (zero_tail clears those elements); rows past
+      // N give output rows that are never read.
+      auto load_b = [&](int kb, T* b) {
         if constexpr (!TRANS) {
 #pragma unroll
           for (int nb = 0; nb < NB; ++nb) {
@@ -160,10 +164,7 @@ __global__ void __launch_bounds__(64 * WG) __attribute__((amdgpu_waves_per_eu(si
 #pragma unroll
             for (int h = 0; h < KG; ++h) {
               const int64_t k = (int64_t)kb * KC + 16 * h + 4 * g;
-              const int base = (nb * KG + h) * 4;
-              T* d = b + base;
-#pragma unroll
-              for (int e = 0; e < 4; ++e) mask |= (uint32_t)(nok && k + e < a.K) << (base + e);
+              T* d = b + (nb * KG + h) * 4;
               if constexpr (VEC) {
                 // rows are 16-byte aligned and K (the row length) is a
                 // multiple of 4, so the 4-vector at k < K stays in the row
@@ -191,10 +192,7 @@ __global__ void __launch_bounds__(64 * WG) __attribute__((amdgpu_waves_per_eu(si
               const bool kok = k < a.K;
               const int64_t kc = kok ? k : a.K - 1;
               const int64_t n0 = nbase + NB * qd;
-              const int base = (h * 4 + tt) * NB;
-              T* d = b + base;
-#pragma unroll
-              for (int e = 0; e < NB; ++e) mask |= (uint32_t)(kok && n0 + e < a.N) << (base + e);
+              T* d = b + (h * 4 + tt) * NB;
               if constexpr (NB == 2 && VEC) {
                 // n0 is even and N (the row length) a multiple of 4: the
                 // pair at n0 < N stays in the row
@@ -214,23 +212,22 @@ __global__ void __launch_bounds__(64 * WG) __attribute__((amdgpu_waves_per_eu(si
         }
       };
 
-      T bcur[NB * KG * 4], bnext[NB * KG * 4];
-      uint32_t mcur, mnext;
-      load_skinny(gk0);
-      load_b(gk0, bcur, mcur);
+      auto zero_tail = [&](int kb, T* b) {
 #pragma unroll
-      for (int e = 0; e < NB * KG * 4; ++e) bcur[e] = ((mcur >> e) & 1u) ? bcur[e] : T(0);
-      for (int kb = gk0; kb < gk1; ++kb, ++iter) {
-        const int buf = iter & 1;
-        store_skinny(buf);
-        __syncthreads();
-        // prefetch the next chunk (the last chunk reloads itself: harmless)
-        const int kn = kb + 1 < gk1 ? kb + 1 : kb;
-        load_skinny(kn);
-        load_b(kn, bnext, mnext);
-        // FP32: issue those loads here, ahead of the products (the scheduler
-        // would sink them towards their use at the end of the chunk)
-        if constexpr (sizeof(T) == 4) __builtin_amdgcn_sched_barrier(0);
+        for (int h = 0; h < KG; ++h)
+#pragma unroll
+          for (int e = 0; e < 4; ++e) {
+            const bool ok = (int64_t)kb * KC + 16 * h + 4 * g + e < a.K;
+#pragma unroll
+            for (int nb = 0; nb < NB; ++nb) {
+              T& v = TRANS ? b[(h * 4 + e) * NB + nb] : b[(nb * KG + h) * 4 + e];
+              v = ok ? v : T(0);
+            }
+          }
+      };
+
+      // products of one stage of A (bc) with the staged skinny block buf
+      auto products = [&](const T* bc, int buf) {
         const T* ls = &lds_s[buf][0];
 #pragma unroll
         for (int h = 0; h < KG; ++h) {
@@ -252,18 +249,63 @@ __global__ void __launch_bounds__(64 * WG) __attribute__((amdgpu_waves_per_eu(si
             for (int tt = 0; tt < 4; ++tt)
 #pragma unroll
               for (int nb = 0; nb < NB; ++nb) {
-                const T bv = TRANS ? bcur[(h * 4 + tt) * NB + nb] : bcur[(nb * KG + h) * 4 + tt];
+                const T bv = TRANS ? bc[(h * 4 + tt) * NB + nb] : bc[(nb * KG + h) * 4 + tt];
                 acc[mb][nb] = M::op(sf[tt], bv, acc[mb][nb]);
               }
           }
         }
-        // FP32: keep the next chunk's masking behind this chunk's products:
-        // the scheduler would otherwise hoist it between them and wait there
-        // for the loads just issued.  (The FP64 kernel is faster without the
-        // barrier, which costs it registers.)
-        if constexpr (sizeof(T) == 4) __builtin_amdgcn_sched_barrier(0);
+      };
+      if constexpr (kPipe2) {
+        // two A buffers alternating by stage parity (the stage is written
+        // twice), so no register copy waits for a load in flight; the next
+        // stage's skinny block is loaded ahead of the products
+        T ba[NB * KG * 4], bb[NB * KG * 4];
+        load_skinny(gk0);
+        load_b(gk0, ba);
+        auto stage = [&](int kb, T* bc, T* bn) {
+          const int buf = iter & 1;
+          store_skinny(buf);
+          if (kb == a.nk - 1) zero_tail(kb, bc);
+          __syncthreads();
+          // prefetch the next chunk (the last chunk reloads itself: harmless)
+          const int kn = kb + 1 < gk1 ? kb + 1 : kb;
+          load_skinny(kn);
+          load_b(kn, bn);
+          __builtin_amdgcn_sched_barrier(0);
+          products(bc, buf);
+          // the next stage's stores wait for the loads just issued: keep
+          // them behind these products
+          __builtin_amdgcn_sched_barrier(0);
+          ++iter;
+        };
+        // pairs of stages with no branch between them (a load whose only
+        // use sits behind a branch is moved down to it and then waited for)
+        int kb = gk0;
+        for (; kb + 1 < gk1; kb += 2) {
+          stage(kb, ba, bb);
+          stage(kb + 1, bb, ba);
+        }
+        if (kb < gk1) stage(kb, ba, bb);
+      } else {
+        // the wide FP32 kernels (8 waves, up to 256 sketch columns): one A
+        // buffer copied forward, which their registers allow
+        T bcur[NB * KG * 4], bnext[NB * KG * 4];
+        load_skinny(gk0);
+        load_b(gk0, bcur);
+        for (int kb = gk0; kb < gk1; ++kb, ++iter) {
+          const int buf = iter & 1;
+          store_skinny(buf);
+          if (kb == a.nk - 1) zero_tail(kb, bcur);
+          __syncthreads();
+          const int kn = kb + 1 < gk1 ? kb + 1 : kb;
+          load_skinny(kn);
+          load_b(kn, bnext);
+          __builtin_amdgcn_sched_barrier(0);
+          products(bcur, buf);
+          __builtin_amdgcn_sched_barrier(0);
 #pragma unroll
-        for (int e = 0; e < NB * KG * 4; ++e) bcur[e] = ((mnext >> e) & 1u) ? bnext[e] : T(0);
+          for (int e = 0; e < NB * KG * 4; ++e) bcur[e] = bnext[e];
+        }
       }
     }
 
