@@ -365,8 +365,9 @@ __global__ void __launch_bounds__(64 * WG) __attribute__((amdgpu_waves_per_eu(MB
   constexpr int NT = 64 * WG;
   constexpr int VPR = KC / 8;            // 16-byte vectors per skinny row per stage
   constexpr int SPASS = (ELLP * VPR + NT - 1) / NT;
+  constexpr int ELLS = SPASS * NT / VPR;  // staged rows (past ELLP never read)
   constexpr int NPART = X3 ? 2 : 1;
-  __shared__ __attribute__((aligned(16))) __bf16 lds_s[NPART][2][ELLP * LDKB];
+  __shared__ __attribute__((aligned(16))) __bf16 lds_s[NPART][2][ELLS * LDKB];
 
   const int tid = threadIdx.x;
   const int lane = tid & 63, wave = tid >> 6;
@@ -417,24 +418,22 @@ __global__ void __launch_bounds__(64 * WG) __attribute__((amdgpu_waves_per_eu(MB
           for (int p = 0; p < SPASS; ++p) {
             const int v = tid + NT * p;
             const int c = v / VPR, kv = v % VPR;
-            if (c < ELLP) *(f4*)&lds_s[h][buf][c * LDKB + kv * 8] = sreg[h][p];
+            *(f4*)&lds_s[h][buf][c * LDKB + kv * 8] = sreg[h][p];
           }
       };
-      auto load_b = [&](int kb, float* b, uint32_t& mask) {
-        mask = 0;
+      // raw loads from clamped addresses; only the last k-block of the
+      // reduction reaches past K (zero_tail), rows past N give output rows
+      // that are never read
+      auto load_b = [&](int kb, float* b) {
         if constexpr (!TRANS) {
 #pragma unroll
           for (int nb = 0; nb < NB; ++nb) {
             const int64_t n = nbase + nb * 16 + qd;
-            const bool nok = n < a.N;
-            const int64_t nc = nok ? n : a.N - 1;
+            const int64_t nc = n < a.N ? n : a.N - 1;
 #pragma unroll
             for (int kk = 0; kk < KB; ++kk) {
               const int64_t k = (int64_t)kb * KC + 32 * kk + 8 * g;
-              const int base = (nb * KB + kk) * 8;
-              float* d = b + base;
-#pragma unroll
-              for (int e = 0; e < 8; ++e) mask |= (uint32_t)(nok && k + e < a.K) << (base + e);
+              float* d = b + (nb * KB + kk) * 8;
               if constexpr (VEC) {
                 // K is a multiple of 4: both 4-vectors at k < K stay in the row
                 const float* src = A + nc * a.lda + (k < a.K ? k : 0);
@@ -455,12 +454,8 @@ __global__ void __launch_bounds__(64 * WG) __attribute__((amdgpu_waves_per_eu(MB
 #pragma unroll
             for (int tt = 0; tt < 8; ++tt) {
               const int64_t k = (int64_t)kb * KC + 32 * kk + 8 * g + tt;
-              const bool kok = k < a.K;
-              const int64_t kc = kok ? k : a.K - 1;
+              const int64_t kc = k < a.K ? k : a.K - 1;
               const int64_t n0 = nbase + NB * qd;
-#pragma unroll
-              for (int e = 0; e < NB; ++e)
-                mask |= (uint32_t)(kok && n0 + e < a.N) << ((e * KB + kk) * 8 + tt);
               if constexpr (NB == 2 && VEC) {
                 const f2 vv = *(const f2*)(A + kc * a.lda + (n0 < a.N ? n0 : 0));
                 b[kk * 8 + tt] = vv[0];
@@ -473,18 +468,26 @@ __global__ void __launch_bounds__(64 * WG) __attribute__((amdgpu_waves_per_eu(MB
         }
       };
 
-      uint32_t mcur, mnext;
-      load_skinny(gk0);
-      load_b(gk0, bcur, mcur);
+      auto zero_tail = [&](int kb, float* b) {
 #pragma unroll
-      for (int e = 0; e < NB * KB * 8; ++e) bcur[e] = ((mcur >> e) & 1u) ? bcur[e] : 0.f;
-      // products of one stage of A (bcur) with the staged skinny block buf
-      auto products = [&](int buf) {
+        for (int kk = 0; kk < KB; ++kk)
+#pragma unroll
+          for (int e = 0; e < 8; ++e) {
+            const bool ok = (int64_t)kb * KC + 32 * kk + 8 * g + e < a.K;
+#pragma unroll
+            for (int nb = 0; nb < NB; ++nb) {
+              float& v = b[(nb * KB + kk) * 8 + e];
+              v = ok ? v : 0.f;
+            }
+          }
+      };
+      // products of one stage of A (bc) with the staged skinny block buf
+      auto products = [&](const float* bc, int buf) {
 #pragma unroll
         for (int kk = 0; kk < KB; ++kk) {
           bf8 bh[NB], bl[NB];
 #pragma unroll
-          for (int nb = 0; nb < NB; ++nb) split8(bcur + (nb * KB + kk) * 8, bh[nb], bl[nb], X3);
+          for (int nb = 0; nb < NB; ++nb) split8(bc + (nb * KB + kk) * 8, bh[nb], bl[nb], X3);
 #pragma unroll
           for (int mb = 0; mb < MB; ++mb) {
             const int off = (mb * 16 + qd) * LDKB + 32 * kk + 8 * g;
@@ -502,6 +505,8 @@ __global__ void __launch_bounds__(64 * WG) __attribute__((amdgpu_waves_per_eu(MB
           }
         }
       };
+      load_skinny(gk0);
+      load_b(gk0, bcur);
       if constexpr (MB > 8 && !X3) {
         // wide sketches in plain BF16 (one 32-k block per stage): two stages
         // of A in flight (measured slower for BF16X3, whose products fill
@@ -509,38 +514,49 @@ __global__ void __launch_bounds__(64 * WG) __attribute__((amdgpu_waves_per_eu(MB
         // The two prefetch buffers alternate by stage parity (the loop body
         // is written twice), so no register copy waits for a load in flight.
         float bna[NB * KB * 8], bnb[NB * KB * 8];
-        uint32_t ma, mb2;
-        load_b(gk0 + 1 < gk1 ? gk0 + 1 : gk1 - 1, bna, ma);
-        load_b(gk0 + 2 < gk1 ? gk0 + 2 : gk1 - 1, bnb, mb2);
-        auto body = [&](int kb, float* bnx, uint32_t& mx) {
+        load_b(gk0 + 1 < gk1 ? gk0 + 1 : gk1 - 1, bna);
+        load_b(gk0 + 2 < gk1 ? gk0 + 2 : gk1 - 1, bnb);
+        auto body = [&](int kb, float* bnx) {
           const int buf = iter & 1;
           store_skinny(buf);
+          if (kb == a.nk - 1) zero_tail(kb, bcur);
           __syncthreads();
           load_skinny(kb + 1 < gk1 ? kb + 1 : kb);
           __builtin_amdgcn_sched_barrier(0);
-          products(buf);
+          products(bcur, buf);
 #pragma unroll
-          for (int e = 0; e < NB * KB * 8; ++e) bcur[e] = ((mx >> e) & 1u) ? bnx[e] : 0.f;
-          load_b(kb + 3 < gk1 ? kb + 3 : gk1 - 1, bnx, mx);
+          for (int e = 0; e < NB * KB * 8; ++e) bcur[e] = bnx[e];
+          load_b(kb + 3 < gk1 ? kb + 3 : gk1 - 1, bnx);
           ++iter;
         };
         for (int kb = gk0; kb < gk1; kb += 2) {
-          body(kb, bna, ma);
-          if (kb + 1 < gk1) body(kb + 1, bnb, mb2);
+          body(kb, bna);
+          if (kb + 1 < gk1) body(kb + 1, bnb);
         }
       } else {
-        for (int kb = gk0; kb < gk1; ++kb, ++iter) {
+        // two A buffers alternating by stage parity (the stage is written
+        // twice), so no register copy waits for a load in flight; the loads
+        // of the next stage are issued ahead of the products and nothing
+        // waits for them before the next stage
+        auto stage = [&](int kb, float* bc, float* bn) {
           const int buf = iter & 1;
           store_skinny(buf);
+          if (kb == a.nk - 1) zero_tail(kb, bc);
           __syncthreads();
           const int kn = kb + 1 < gk1 ? kb + 1 : kb;
           load_skinny(kn);
-          load_b(kn, bnext, mnext);
-          __builtin_amdgcn_sched_barrier(0);  // loads ahead of the products
-          products(buf);
-#pragma unroll
-          for (int e = 0; e < NB * KB * 8; ++e) bcur[e] = ((mnext >> e) & 1u) ? bnext[e] : 0.f;
+          load_b(kn, bn);
+          __builtin_amdgcn_sched_barrier(0);
+          products(bc, buf);
+          __builtin_amdgcn_sched_barrier(0);
+          ++iter;
+        };
+        int kb = gk0;
+        for (; kb + 1 < gk1; kb += 2) {
+          stage(kb, bcur, bnext);
+          stage(kb + 1, bnext, bcur);
         }
+        if (kb < gk1) stage(kb, bcur, bnext);
       }
     }
     const int64_t slot = ((int64_t)x * a.gx + jw) * a.maxslot + (t - tfirst);
