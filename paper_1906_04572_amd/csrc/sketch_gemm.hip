@@ -398,7 +398,7 @@ __global__ void __launch_bounds__(64 * WG) __attribute__((amdgpu_waves_per_eu(MB
 
     if (gk0 < gk1) {
       f4 sreg[NPART][SPASS];  // raw 16-byte vectors of 8 bf16
-      float bcur[NB * KB * 8], bnext[NB * KB * 8];  // [nb][block][8 k values]
+      float bcur[NB * KB * 8];  // [nb][block][8 k values]
       // unconditional loads from clamped addresses; validity bits applied
       // when the prefetched chunk becomes current (see the FP32/FP64 kernel)
       auto load_skinny = [&](int kb) {
@@ -506,7 +506,6 @@ __global__ void __launch_bounds__(64 * WG) __attribute__((amdgpu_waves_per_eu(MB
         }
       };
       load_skinny(gk0);
-      load_b(gk0, bcur);
       if constexpr (MB > 8 && !X3) {
         // wide sketches in plain BF16 (one 32-k block per stage): two stages
         // of A in flight (measured slower for BF16X3, whose products fill
@@ -514,6 +513,7 @@ __global__ void __launch_bounds__(64 * WG) __attribute__((amdgpu_waves_per_eu(MB
         // The two prefetch buffers alternate by stage parity (the loop body
         // is written twice), so no register copy waits for a load in flight.
         float bna[NB * KB * 8], bnb[NB * KB * 8];
+        load_b(gk0, bcur);
         load_b(gk0 + 1 < gk1 ? gk0 + 1 : gk1 - 1, bna);
         load_b(gk0 + 2 < gk1 ? gk0 + 2 : gk1 - 1, bnb);
         auto body = [&](int kb, float* bnx) {
@@ -534,10 +534,15 @@ __global__ void __launch_bounds__(64 * WG) __attribute__((amdgpu_waves_per_eu(MB
           if (kb + 1 < gk1) body(kb + 1, bnb);
         }
       } else {
-        // two A buffers alternating by stage parity (the stage is written
-        // twice), so no register copy waits for a load in flight; the loads
-        // of the next stage are issued ahead of the products and nothing
-        // waits for them before the next stage
+        // DEPTH A buffers in rotation (the stage is written DEPTH times), so
+        // no register copy waits for a load in flight; the A loads run
+        // DEPTH - 1 stages ahead, issued ahead of the products, and nothing
+        // waits for them before their own stage (a third buffer, loads two
+        // stages ahead, measured no faster for plain BF16 at 112 columns)
+        constexpr int DEPTH = 2;
+        float bq[DEPTH][NB * KB * 8];
+#pragma unroll
+        for (int d = 0; d < DEPTH - 1; ++d) load_b(gk0 + d < gk1 ? gk0 + d : gk1 - 1, bq[d]);
         auto stage = [&](int kb, float* bc, float* bn) {
           const int buf = iter & 1;
           store_skinny(buf);
@@ -545,18 +550,20 @@ __global__ void __launch_bounds__(64 * WG) __attribute__((amdgpu_waves_per_eu(MB
           __syncthreads();
           const int kn = kb + 1 < gk1 ? kb + 1 : kb;
           load_skinny(kn);
-          load_b(kn, bn);
+          load_b(kb + DEPTH - 1 < gk1 ? kb + DEPTH - 1 : gk1 - 1, bn);
           __builtin_amdgcn_sched_barrier(0);
           products(bc, buf);
           __builtin_amdgcn_sched_barrier(0);
           ++iter;
         };
         int kb = gk0;
-        for (; kb + 1 < gk1; kb += 2) {
-          stage(kb, bcur, bnext);
-          stage(kb + 1, bnext, bcur);
+        for (; kb + DEPTH - 1 < gk1; kb += DEPTH) {
+#pragma unroll
+          for (int d = 0; d < DEPTH; ++d) stage(kb + d, bq[d], bq[(d + DEPTH - 1) % DEPTH]);
         }
-        if (kb < gk1) stage(kb, bcur, bnext);
+#pragma unroll
+        for (int d = 0; d < DEPTH - 1; ++d)
+          if (kb + d < gk1) stage(kb + d, bq[d], bq[(d + DEPTH - 1) % DEPTH]);
       }
     }
     const int64_t slot = ((int64_t)x * a.gx + jw) * a.maxslot + (t - tfirst);
