@@ -448,7 +448,7 @@ int enqueue_decompose(corutv_ctx* ctx, const Plan& pl, char* ws, const DecArgs& 
     mark();
     hipError_t e = host_a ? stream_pass(tA, opnd, ldn, ldm)
                           : launch_sketch(pr, tA, d.A.ptr, d.A.ld, Rb, Cb, opnd, ldn, ellp, part,
-                                          pl.part_elems, &pp, ctx->num_cu, s, ws + pl.o_sbf);
+                                          pl.part_elems, &pp, ctx->num_cu, s, ws + pl.o_sbf, x0, ldm, ell);
     mark();
     return e;
   };
@@ -456,7 +456,7 @@ int enqueue_decompose(corutv_ctx* ctx, const Plan& pl, char* ws, const DecArgs& 
     mark();
     hipError_t e = host_a ? stream_pass(tAt, opnd, ldm, ldn)
                           : launch_sketch(pr, tAt, d.A.ptr, d.A.ld, Rb, Cb, opnd, ldm, ellp, part,
-                                          pl.part_elems, &pp, ctx->num_cu, s, ws + pl.o_sbf);
+                                          pl.part_elems, &pp, ctx->num_cu, s, ws + pl.o_sbf, x0, ldn, ell);
     mark();
     return e;
   };

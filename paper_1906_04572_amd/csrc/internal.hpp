@@ -34,6 +34,7 @@ struct Partials {
   int gx = 0;             // workgroups per chunk
   int maxslot = 0;
   int64_t n = 0;          // output length
+  bool direct = false;    // the pass wrote its output itself (nothing to sum)
 };
 
 
@@ -48,9 +49,15 @@ hipError_t launch_omega(int64_t n, int ell, int ellp, uint64_t seed, uint32_t su
 // part_elems: capacity of part_buf in elements; the grid shrinks to fit.
 // sbf: for the bf16 forms, scratch of sketch_bf16_bytes(ellp, lds) bytes that
 // receives the bf16 hi/lo split of S (unused otherwise, may be null).
+// out (optional): where launch_sum_partials(part, ell, ellp, out, nullptr,
+// ldo) would put the result.  When the reduction is short (one K chunk) and
+// the output has at least num_cu tiles, each workgroup then takes one whole
+// tile and writes it there (FP64, columns ell..ellp-1 zero); part->direct
+// is set and launch_sum_partials does nothing.
 hipError_t launch_sketch(int prec, int trans, const void* A, int64_t lda, int64_t R, int64_t C,
                          const void* S, int64_t lds, int ellp, void* part_buf, int64_t part_elems,
-                         Partials* part, int num_cu, hipStream_t st, void* sbf);
+                         Partials* part, int num_cu, hipStream_t st, void* sbf, double* out = nullptr,
+                         int64_t ldo = 0, int ell = 0);
 inline size_t sketch_bf16_bytes(int ellp, int64_t lds) { return 2 * (size_t)ellp * lds * 2; }
 // Capacity (elements) that covers every grid launch_sketch may pick on a
 // 256-CU device.

@@ -24,7 +24,9 @@
 //    8 g / tiles + 1 partial tiles instead of 8 (g / tiles + 1).
 //    Each workgroup writes one partial tile per output tile it touches; the
 //    consumer kernel sums them in a fixed order, so results are
-//    deterministic (no atomics).
+//    deterministic (no atomics).  An FP64 pass over a short reduction (one
+//    chunk) whose output has at least one tile per CU instead gives each
+//    workgroup one whole tile, written straight to the output.
 #include <algorithm>
 #include <map>
 #include <mutex>
@@ -68,6 +70,9 @@ struct SketchArgs {
   int64_t lds;
   void* P;
   int tiles, nk, nkx, gx, maxslot, nchunk;
+  double* out;  // direct output (one whole tile per workgroup), or null
+  int64_t ldo;
+  int ell;      // columns of out that take the sums (the rest of ELLP: zero)
 };
 
 // VEC: A rows 16-byte aligned (address and leading dimension), so vector
@@ -95,6 +100,9 @@ __global__ void __launch_bounds__(64 * WG) __attribute__((amdgpu_waves_per_eu(si
   constexpr int ELLS = SPASS * NT / VPR;
   // two-buffer stage pipeline, except in the wide FP32 kernels
   constexpr bool kPipe2 = sizeof(T) == 8 || MB <= 8;
+  // direct output (one whole tile per workgroup) in the narrow FP64 kernels
+  // only: the others have no registers to spare for it
+  constexpr bool kDirect = sizeof(T) == 8 && MB <= 8;
   __shared__ __attribute__((aligned(16))) T lds_s[2][ELLS * LDK];
 
   const int tid = threadIdx.x;
@@ -309,24 +317,43 @@ __global__ void __launch_bounds__(64 * WG) __attribute__((amdgpu_waves_per_eu(si
       }
     }
 
-    // partial tile (x, jw, t - tfirst): [ELLP][TW]
-    const int64_t slot = ((int64_t)x * a.gx + jw) * a.maxslot + (t - tfirst);
-    T* dst = P + slot * (int64_t)ELLP * TW;
+    if (kDirect && a.out) {
+      // the whole reduction of this tile: straight to the output (lane
+      // base: row n0, column g (FP64) or 4g (FP32); then uniform offsets)
+      const int64_t n0 = (int64_t)t * TW + wave * 16 * NB + (TRANS ? NB * qd : qd);
+      const int cg = sizeof(T) == 4 ? 4 * g : g;
+      double* ob = a.out + (int64_t)cg * a.ldo + n0;
 #pragma unroll
-    for (int mb = 0; mb < MB; ++mb)
+      for (int mb = 0; mb < MB; ++mb)
 #pragma unroll
-      for (int i = 0; i < 4; ++i) {
-        // accumulator slot i of lane (g, qd) holds row 4g + i of the 16 x 16
-        // block for the FP32 instruction and row g + 4i for the FP64 one
-        const int c = mb * 16 + (sizeof(T) == 4 ? 4 * g + i : g + 4 * i);
-        if constexpr (!TRANS) {
+        for (int i = 0; i < 4; ++i) {
+          const int dc = mb * 16 + (sizeof(T) == 4 ? i : 4 * i);
 #pragma unroll
-          for (int nb = 0; nb < NB; ++nb) dst[(int64_t)c * TW + wave * 16 * NB + nb * 16 + qd] = acc[mb][nb][i];
-        } else {
-#pragma unroll
-          for (int nb = 0; nb < NB; ++nb) dst[(int64_t)c * TW + wave * 16 * NB + NB * qd + nb] = acc[mb][nb][i];
+          for (int nb = 0; nb < NB; ++nb) {
+            const int dn = TRANS ? nb : nb * 16;
+            if (n0 + dn < a.N) ob[(int64_t)dc * a.ldo + dn] = cg + dc < a.ell ? (double)acc[mb][nb][i] : 0.0;
+          }
         }
-      }
+    } else {
+      // partial tile (x, jw, t - tfirst): [ELLP][TW]
+      const int64_t slot = ((int64_t)x * a.gx + jw) * a.maxslot + (t - tfirst);
+      T* dst = P + slot * (int64_t)ELLP * TW;
+#pragma unroll
+      for (int mb = 0; mb < MB; ++mb)
+#pragma unroll
+        for (int i = 0; i < 4; ++i) {
+          // accumulator slot i of lane (g, qd) holds row 4g + i of the 16 x 16
+          // block for the FP32 instruction and row g + 4i for the FP64 one
+          const int c = mb * 16 + (sizeof(T) == 4 ? 4 * g + i : g + 4 * i);
+          if constexpr (!TRANS) {
+#pragma unroll
+            for (int nb = 0; nb < NB; ++nb) dst[(int64_t)c * TW + wave * 16 * NB + nb * 16 + qd] = acc[mb][nb][i];
+          } else {
+#pragma unroll
+            for (int nb = 0; nb < NB; ++nb) dst[(int64_t)c * TW + wave * 16 * NB + NB * qd + nb] = acc[mb][nb][i];
+          }
+        }
+    }
     u += kb1 - kb0;
   }
 }
@@ -566,21 +593,23 @@ __global__ void __launch_bounds__(64 * WG) __attribute__((amdgpu_waves_per_eu(MB
           if (kb + d < gk1) stage(kb + d, bq[d], bq[(d + DEPTH - 1) % DEPTH]);
       }
     }
-    const int64_t slot = ((int64_t)x * a.gx + jw) * a.maxslot + (t - tfirst);
-    float* dst = P + slot * (int64_t)ELLP * TW;
+    {
+      const int64_t slot = ((int64_t)x * a.gx + jw) * a.maxslot + (t - tfirst);
+      float* dst = P + slot * (int64_t)ELLP * TW;
 #pragma unroll
-    for (int mb = 0; mb < MB; ++mb)
+      for (int mb = 0; mb < MB; ++mb)
 #pragma unroll
-      for (int i = 0; i < 4; ++i) {
-        const int c = mb * 16 + 4 * g + i;
-        if constexpr (!TRANS) {
+        for (int i = 0; i < 4; ++i) {
+          const int c = mb * 16 + 4 * g + i;
+          if constexpr (!TRANS) {
 #pragma unroll
-          for (int nb = 0; nb < NB; ++nb) dst[(int64_t)c * TW + wave * 16 * NB + nb * 16 + qd] = acc[mb][nb][i];
-        } else {
+            for (int nb = 0; nb < NB; ++nb) dst[(int64_t)c * TW + wave * 16 * NB + nb * 16 + qd] = acc[mb][nb][i];
+          } else {
 #pragma unroll
-          for (int nb = 0; nb < NB; ++nb) dst[(int64_t)c * TW + wave * 16 * NB + NB * qd + nb] = acc[mb][nb][i];
+            for (int nb = 0; nb < NB; ++nb) dst[(int64_t)c * TW + wave * 16 * NB + NB * qd + nb] = acc[mb][nb][i];
+          }
         }
-      }
+    }
     u += kb1 - kb0;
   }
 }
@@ -751,7 +780,8 @@ int64_t partials_capacity(int64_t n_out, int64_t k_len, int ellp, int prec) {
 
 hipError_t launch_sketch(int prec, int trans, const void* A, int64_t lda, int64_t R, int64_t C,
                          const void* S, int64_t lds, int ellp, void* part_buf, int64_t part_elems,
-                         Partials* part, int num_cu, hipStream_t st, void* sbf) {
+                         Partials* part, int num_cu, hipStream_t st, void* sbf, double* out, int64_t ldo,
+                         int ell) {
   const bool f64 = prec == P_F64;
   const int mb = ellp / 16;
   const int elem = f64 ? 8 : 4;
@@ -780,11 +810,20 @@ hipError_t launch_sketch(int prec, int trans, const void* A, int64_t lda, int64_
   if (gx < 1) gx = 1;
   const int kc = kc_of(prec, mb);
   geometry(N, K, ellp, elem, kc, gx, wg, part);
-  while (need_elems(*part) > part_elems && gx > 1) {
-    gx = gx > 8 ? gx - 8 : gx - 1;
-    geometry(N, K, ellp, elem, kc, gx, wg, part);
+  // a short reduction over an output of many tiles: one whole tile per
+  // workgroup, written straight to the output (no partial tiles to sum)
+  const bool direct = out && f64 && mb <= 8 && part->nchunk == 1 && part->tiles >= num_cu;
+  if (direct) {
+    part->gx = part->tiles;
+    part->maxslot = 1;
+  } else {
+    while (need_elems(*part) > part_elems && gx > 1) {
+      gx = gx > 8 ? gx - 8 : gx - 1;
+      geometry(N, K, ellp, elem, kc, gx, wg, part);
+    }
+    if (need_elems(*part) > part_elems) return hipErrorInvalidValue;
   }
-  if (need_elems(*part) > part_elems) return hipErrorInvalidValue;
+  part->direct = direct;
   part->ptr = part_buf;
   SketchArgs a;
   a.A = A;
@@ -813,6 +852,9 @@ hipError_t launch_sketch(int prec, int trans, const void* A, int64_t lda, int64_
   a.nchunk = part->nchunk;
   a.gx = part->gx;
   a.maxslot = part->maxslot;
+  a.out = direct ? out : nullptr;
+  a.ldo = ldo;
+  a.ell = ell;
   void* args[] = {&a};
   return hipLaunchKernel((const void*)fn, dim3(part->nchunk * part->gx), dim3(64 * wg), args, 0, st);
 }

@@ -2220,7 +2220,7 @@ hipError_t launch_trprod(const double* R2, const double* R1, int ell, double* R,
 // ---------------------------------------------------------------------------
 hipError_t launch_sum_partials(const Partials& p, int ell, int ncols, double* out64, float* out32,
                                int64_t ld, hipStream_t st) {
-  if (p.n == 0 || ncols == 0) return hipSuccess;
+  if (p.direct || p.n == 0 || ncols == 0) return hipSuccess;
   // every segment list must fit: at most 8 * (gx + 1) entries per tile
   if (p.nchunk < 1 || (int64_t)p.nchunk * (p.gx + 1) > kSegMax) return hipErrorInvalidValue;
   // about nchunk (gx / tiles + 1) slots feed a tile; give each thread at least 8

@@ -88,6 +88,11 @@ def test_plain_config_2000x1500_rank20_lower(ctx):
     (700, 700, 100, 28, 1, "auto", "row"),
     (2100, 1900, 150, 50, 0, "upper", "row"),
     (1800, 1500, 120, 20, 1, "lower", "row"),
+    # tall and thin: the passes with the long output (313 tiles of 128 rows,
+    # a 300-long reduction, ragged last tile) write it from one workgroup
+    # per tile, no partial sums; row-major and the transposed wide problem
+    (40000, 300, 8, 4, 1, "auto", "row"),
+    (300, 40000, 8, 4, 1, "auto", "col"),
 ])
 def test_f64_cases(ctx, m, n, k, p, q, tri, layout):
     _say("f64", m, n, k, p, q, tri, layout)
