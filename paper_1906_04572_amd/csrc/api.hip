@@ -290,9 +290,11 @@ hipError_t qr_from_partials(const Plan& pl, char* ws, const Partials& pp, int64_
   // summed: the sketch is already in x0 (passes over a host-resident A)
   if (!summed && (e = launch_sum_partials(pp, ell, pl.ellp, x0, nullptr, ld, s)) != hipSuccess) return e;
   if (ell <= kQr16Max) {
+    bool covered = false;
     if ((e = launch_qr16(x0, ld, rows, ell, q64, q32, rfac, st, (double*)(ws + pl.o_q16),
-                         one_step ? kOneStepThr : 0.0, s)) != hipSuccess)
+                         one_step ? kOneStepThr : 0.0, s, x1, ld, (double*)(ws + pl.o_hh), &covered)) != hipSuccess)
       return e;
+    if (covered) return hipSuccess;
     return launch_householder_qr(x0, ld, rows, ell, x1, ld, q64, ld, q32, ld, rfac, st,
                                  (double*)(ws + pl.o_hh), s);
   }

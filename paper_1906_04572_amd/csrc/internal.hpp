@@ -126,9 +126,15 @@ hipError_t launch_trprod(const double* R2, const double* R1, int ell, double* R,
 // allowed when single_thr > 0).  work: qr16_work_bytes() bytes whose last 256
 // bytes (the block counter) must be zero before the first use; the kernels
 // leave them zero.
+// covered (nullable): when given, the launches also run the Householder
+// fallback after a breakdown where its register-resident form fits (W: rows
+// x ell scratch with ld ldw for the panel reflectors; hw: the tree's
+// workspace as for launch_householder_qr), and *covered tells whether they
+// did; if not, the caller runs launch_householder_qr as before.
 size_t qr16_work_bytes();
 hipError_t launch_qr16(const double* X, int64_t ld, int64_t rows, int ell, double* Q, float* Q32,
-                       double* R, int* status, double* work, double single_thr, hipStream_t st);
+                       double* R, int* status, double* work, double single_thr, hipStream_t st,
+                       double* W = nullptr, int64_t ldw = 0, double* hw = nullptr, bool* covered = nullptr);
 
 // Householder thin QR of X (rows x ell, column-major FP64) -> Q (diag R >= 0,
 // FP64 and optionally a float copy), R (nullable); runs only when

@@ -949,11 +949,10 @@ __device__ __forceinline__ int q16_factor(Q16Lds& sh, double g, int ell, double 
   return sh.flag;
 }
 
-// steps 0 and 1 of the three-launch form, and step 2
+// steps 0 and 1 of the three-launch form, and step 2 (sw: the status word
+// as the launch found it)
 template <int STEP>
-__global__ void __launch_bounds__(1024) q16_kernel(Q16Args a) {
-  __shared__ Q16Lds sh;
-  const int sw = *a.status;
+__device__ __forceinline__ void q16_body(const Q16Args& a, Q16Lds& sh, int sw) {
   if (STEP >= 1 && (sw & 3)) return;  // breakdown or non-finite data: nothing to do here
   if (STEP == 2 && (sw & 4)) return;  // the first step already wrote Q
   const bool final1 = STEP == 1 && (sw & 4);
@@ -1033,9 +1032,16 @@ __global__ void __launch_bounds__(1024) q16_kernel(Q16Args a) {
   if (tid == 0) atomicExch(a.counter, 0);  // ready for the next launch
 }
 
-// The three steps in one workgroup (rows <= 1024, X kept in registers).
-__global__ void __launch_bounds__(1024) q16_one_kernel(Q16Args a) {
+template <int STEP>
+__global__ void __launch_bounds__(1024) q16_kernel(Q16Args a) {
   __shared__ Q16Lds sh;
+  q16_body<STEP>(a, sh, *a.status);
+}
+
+// The three steps in one workgroup (rows <= 1024, X kept in registers).
+// Returns the status bits of the factorization that ended it (bit 1
+// breakdown and bit 2 non-finite data, already recorded; else 0 or 4).
+__device__ __forceinline__ int q16_one_body(const Q16Args& a, Q16Lds& sh) {
   const int tid = threadIdx.x, ell = a.ell;
   const bool in = tid < a.rows;
   double x[16];
@@ -1046,7 +1052,7 @@ __global__ void __launch_bounds__(1024) q16_one_kernel(Q16Args a) {
   int f = q16_factor(sh, q16_gram_block(sh, acc), ell, a.single_thr);
   if (f & 3) {
     if (tid == 0) atomicOr(a.status, f & 3);
-    return;
+    return f & 3;
   }
   if (tid < 256) {
     sh.ra[tid] = sh.xs[tid];  // R1^-1
@@ -1063,14 +1069,14 @@ __global__ void __launch_bounds__(1024) q16_one_kernel(Q16Args a) {
       const int i = tid % ell, j = tid / ell;
       a.rfac[tid] = sh.rb[i * 16 + j];
     }
-    return;
+    return 4;
   }
   acc = d4c{0.0, 0.0, 0.0, 0.0};
   q16_tile_gram(sh, acc, a.rows);
   f = q16_factor(sh, q16_gram_block(sh, acc), ell, 0.0);
   if (f & 3) {
     if (tid == 0) atomicOr(a.status, f & 3);
-    return;
+    return f & 3;
   }
   // X1 again (the Gram sums used the tile), then Q = X1 R2^-1
   q16_put(sh, x);
@@ -1079,6 +1085,12 @@ __global__ void __launch_bounds__(1024) q16_one_kernel(Q16Args a) {
   q16_get(sh, x);
   q16_store(a, tid, in, x);
   if (a.rfac) q16_rfac(a.rfac, sh.gm, sh.rb, ell, tid, 1024);
+  return 0;
+}
+
+__global__ void __launch_bounds__(1024) q16_one_kernel(Q16Args a) {
+  __shared__ Q16Lds sh;
+  q16_one_body(a, sh);
 }
 
 // ---------------------------------------------------------------------------
@@ -1900,7 +1912,18 @@ __device__ __forceinline__ void hhr_load(double (&w)[M][R], const double* __rest
     for (int q = 0; q < R; ++q) {
       const int i = r + 64 * q, j = c + 16 * m;
       const int ic = i < nr ? i : nr - 1, jc = j < ell ? j : ell - 1;
-      const double v = X[(int64_t)jc * ldx + r0 + ic];
+      w[m][q] = X[(int64_t)jc * ldx + r0 + ic];
+    }
+  // every load issued first; each value made opaque before its mask (a
+  // select between a loaded value and a constant is otherwise turned into a
+  // branch around the load, which then waits for each load in turn)
+#pragma unroll
+  for (int m = 0; m < M; ++m)
+#pragma unroll
+    for (int q = 0; q < R; ++q) {
+      const int i = r + 64 * q, j = c + 16 * m;
+      double v = w[m][q];
+      asm volatile("" : "+v"(v));
       w[m][q] = (i < nr && j < ell) ? v : 0.0;
     }
 }
@@ -1911,12 +1934,9 @@ __device__ __forceinline__ bool hhr_runs(const int* status) { return (*status & 
 // One workgroup: X (rows x ell, column-major) -> Q (diag R >= 0, FP64 and
 // optionally a float copy), R (nullable, ell x ell column-major).
 template <int M, int R>
-__global__ void __launch_bounds__(1024) hhr_one_kernel(const double* __restrict__ X, int64_t ldx, int64_t rows,
-                                                       int ell, double* __restrict__ Q, int64_t ldq,
-                                                       float* __restrict__ Q32, int64_t ldq32,
-                                                       double* __restrict__ Rout, const int* status) {
-  if (!hhr_runs(status)) return;
-  __shared__ HhrLds<M> sh;
+__device__ __forceinline__ void hhr_one_body(HhrLds<M>& sh, const double* __restrict__ X, int64_t ldx,
+                                             int64_t rows, int ell, double* __restrict__ Q, int64_t ldq,
+                                             float* __restrict__ Q32, int64_t ldq32, double* __restrict__ Rout) {
   const int t = threadIdx.x, c = t & 15, r = t >> 4;
   double w[M][R];
   hhr_load<M, R>(w, X, ldx, 0, (int)rows, ell);
@@ -1955,17 +1975,24 @@ __global__ void __launch_bounds__(1024) hhr_one_kernel(const double* __restrict_
   }
 }
 
+template <int M, int R>
+__global__ void __launch_bounds__(1024) hhr_one_kernel(const double* __restrict__ X, int64_t ldx, int64_t rows,
+                                                       int ell, double* __restrict__ Q, int64_t ldq,
+                                                       float* __restrict__ Q32, int64_t ldq32,
+                                                       double* __restrict__ Rout, const int* status) {
+  if (!hhr_runs(status)) return;
+  __shared__ HhrLds<M> sh;
+  hhr_one_body<M, R>(sh, X, ldx, rows, ell, Q, ldq, Q32, ldq32, Rout);
+}
+
 // Tree level 1: panel b (rows split evenly over P panels) reduced; its
 // reflectors (and R's entries above them) to W, its triangle to rows
 // b ell .. of Rs (ld P ell), tau and vhead to tv.
 template <int M, int R>
-__global__ void __launch_bounds__(1024) hhr_panel_kernel(const double* __restrict__ X, int64_t ldx, int64_t rows,
-                                                         int ell, int P, double* __restrict__ W, int64_t ldw,
-                                                         double* __restrict__ Rs, double* __restrict__ tv,
-                                                         const int* status) {
-  if (!hhr_runs(status)) return;
-  __shared__ HhrLds<M> sh;
-  const int t = threadIdx.x, c = t & 15, r = t >> 4, b = blockIdx.x;
+__device__ __forceinline__ void hhr_panel_body(HhrLds<M>& sh, const double* __restrict__ X, int64_t ldx,
+                                               int64_t rows, int ell, int P, int b, double* __restrict__ W,
+                                               int64_t ldw, double* __restrict__ Rs, double* __restrict__ tv) {
+  const int t = threadIdx.x, c = t & 15, r = t >> 4;
   const int64_t r0 = (int64_t)b * rows / P, hb = (int64_t)(b + 1) * rows / P - r0;
   double w[M][R];
   hhr_load<M, R>(w, X, ldx, r0, (int)hb, ell);
@@ -1988,16 +2015,24 @@ __global__ void __launch_bounds__(1024) hhr_panel_kernel(const double* __restric
   }
 }
 
-// Tree level 2: panel b of Q = its reflectors applied to [Qr rows b ell ..; 0].
 template <int M, int R>
-__global__ void __launch_bounds__(1024) hhr_expand_kernel(const double* __restrict__ W, int64_t ldw, int64_t rows,
-                                                          int ell, int P, const double* __restrict__ Qr,
-                                                          const double* __restrict__ tv, double* __restrict__ Q,
-                                                          int64_t ldq, float* __restrict__ Q32, int64_t ldq32,
-                                                          const int* status) {
+__global__ void __launch_bounds__(1024) hhr_panel_kernel(const double* __restrict__ X, int64_t ldx, int64_t rows,
+                                                         int ell, int P, double* __restrict__ W, int64_t ldw,
+                                                         double* __restrict__ Rs, double* __restrict__ tv,
+                                                         const int* status) {
   if (!hhr_runs(status)) return;
   __shared__ HhrLds<M> sh;
-  const int t = threadIdx.x, c = t & 15, r = t >> 4, b = blockIdx.x;
+  hhr_panel_body<M, R>(sh, X, ldx, rows, ell, P, blockIdx.x, W, ldw, Rs, tv);
+}
+
+// Tree level 2: panel b of Q = its reflectors applied to [Qr rows b ell ..; 0].
+template <int M, int R>
+__device__ __forceinline__ void hhr_expand_body(HhrLds<M>& sh, const double* __restrict__ W, int64_t ldw,
+                                                int64_t rows, int ell, int P, int b,
+                                                const double* __restrict__ Qr, const double* __restrict__ tv,
+                                                double* __restrict__ Q, int64_t ldq, float* __restrict__ Q32,
+                                                int64_t ldq32) {
+  const int t = threadIdx.x, c = t & 15, r = t >> 4;
   const int64_t r0 = (int64_t)b * rows / P, hb = (int64_t)(b + 1) * rows / P - r0;
   const int64_t ldr = (int64_t)P * ell;
   if (t < ell) {
@@ -2034,6 +2069,17 @@ __global__ void __launch_bounds__(1024) hhr_expand_kernel(const double* __restri
       }
     }
   }
+}
+
+template <int M, int R>
+__global__ void __launch_bounds__(1024) hhr_expand_kernel(const double* __restrict__ W, int64_t ldw, int64_t rows,
+                                                          int ell, int P, const double* __restrict__ Qr,
+                                                          const double* __restrict__ tv, double* __restrict__ Q,
+                                                          int64_t ldq, float* __restrict__ Q32, int64_t ldq32,
+                                                          const int* status) {
+  if (!hhr_runs(status)) return;
+  __shared__ HhrLds<M> sh;
+  hhr_expand_body<M, R>(sh, W, ldw, rows, ell, P, blockIdx.x, Qr, tv, Q, ldq, Q32, ldq32);
 }
 
 // ---------------------------------------------------------------------------
@@ -2176,6 +2222,55 @@ hipError_t launch_add_cols(double* y, const double* x, int64_t rows, int cols, i
   return hipGetLastError();
 }
 
+// ---------------------------------------------------------------------------
+// CholeskyQR2 for at most 16 columns with the Householder fallback in the
+// same launches: after a breakdown (status bit 1 alone) the launch that
+// would have run the next CholeskyQR step runs the register-resident
+// Householder QR of X instead, so no launch is spent on a fallback that is
+// not needed.
+//   one workgroup (rows <= 1024): q16h_one_kernel<HR> factors X by
+//     Householder right after the failed Cholesky (HR rows per thread);
+//   tall (rows in nblk blocks of at most 1024, nblk l <= 1024): step 1
+//     factors each block as a panel of the two-level tree, the root (the
+//     stacked triangles) is reduced by hhr_one_kernel in a launch of its own
+//     between the steps (in the same launch, its registers would spill
+//     those of the others), and step 2 expands each panel's Q.
+namespace {
+
+struct Q16Hh {
+  double* W;    // panel reflectors (rows x l, ld ldw)
+  int64_t ldw;
+  double* Rs;   // stacked triangles (nblk l x l)
+  double* Qr;   // the root's Q
+  double* tv;   // per panel: tau[l], vhead[l]
+};
+
+template <int HR>
+__global__ void __launch_bounds__(1024) q16h_one_kernel(Q16Args a) {
+  __shared__ Q16Lds sh;
+  __shared__ HhrLds<1> hs;
+  if (q16_one_body(a, sh) == 1)
+    hhr_one_body<1, HR>(hs, a.x0, a.ld, a.rows, a.ell, a.q64, a.ld, a.q32, a.ld, a.rfac);
+}
+
+template <int STEP>
+__global__ void __launch_bounds__(1024) q16h_kernel(Q16Args a, Q16Hh h) {
+  __shared__ Q16Lds sh;
+  __shared__ HhrLds<1> hs;
+  const int sw = *a.status;
+  if ((sw & 3) != 1) {
+    q16_body<STEP>(a, sh, sw);
+    return;
+  }
+  if (STEP == 1)
+    hhr_panel_body<1, 16>(hs, a.x0, a.ld, a.rows, a.ell, a.nblk, blockIdx.x, h.W, h.ldw, h.Rs, h.tv);
+  else
+    hhr_expand_body<1, 16>(hs, h.W, h.ldw, a.rows, a.ell, a.nblk, blockIdx.x, h.Qr, h.tv, a.q64, a.ld, a.q32,
+                           a.ld);
+}
+
+}  // namespace
+
 int qr16_blocks(int64_t rows) {
   const int64_t b = (rows + kQ16Rows - 1) / kQ16Rows;
   return (int)std::max<int64_t>(1, std::min<int64_t>(kQ16MaxBlocks, b));
@@ -2183,8 +2278,12 @@ int qr16_blocks(int64_t rows) {
 
 size_t qr16_work_bytes() { return ((size_t)kQ16MaxBlocks * 256 + 4 * 256) * 8 + 256; }
 
+static int hhr_rows_per_thread(int M, int64_t nr);
+
 hipError_t launch_qr16(const double* X, int64_t ld, int64_t rows, int ell, double* Q, float* Q32, double* R,
-                       int* status, double* work, double single_thr, hipStream_t st) {
+                       int* status, double* work, double single_thr, hipStream_t st, double* W, int64_t ldw,
+                       double* hw, bool* covered) {
+  if (covered) *covered = false;
   if (ell < 1 || ell > 16 || rows < ell) return hipErrorInvalidValue;
   Q16Args a;
   a.x0 = X;
@@ -2201,10 +2300,41 @@ hipError_t launch_qr16(const double* X, int64_t ld, int64_t rows, int ell, doubl
   a.status = status;
   a.single_thr = single_thr;
   if (rows <= kQ16Rows) {
-    q16_one_kernel<<<dim3(1), dim3(1024), 0, st>>>(a);
+    if (covered) {
+      const int hr = hhr_rows_per_thread(1, rows);
+      if (hr == 4) q16h_one_kernel<4><<<dim3(1), dim3(1024), 0, st>>>(a);
+      else if (hr == 8) q16h_one_kernel<8><<<dim3(1), dim3(1024), 0, st>>>(a);
+      else q16h_one_kernel<16><<<dim3(1), dim3(1024), 0, st>>>(a);
+      *covered = true;
+    } else {
+      q16_one_kernel<<<dim3(1), dim3(1024), 0, st>>>(a);
+    }
     return hipGetLastError();
   }
   const dim3 grid((unsigned)a.nblk);
+  // the merged fallback: blocks of at most 1024 rows (the panels), their
+  // stacked triangles at most 1024 rows (the root)
+  const int64_t pe = (int64_t)a.nblk * ell;
+  const int hr = hhr_rows_per_thread(1, pe);
+  if (covered && W && hw && (rows + a.nblk - 1) / a.nblk <= kQ16Rows && pe <= kQ16Rows && hr > 0) {
+    Q16Hh h;
+    h.W = W;
+    h.ldw = ldw;
+    h.Rs = hw;  // the same layout as the separate tree's
+    h.Qr = hw + 2 * pe * ell;
+    h.tv = h.Qr + pe * ell;
+    q16_kernel<0><<<grid, dim3(1024), 0, st>>>(a);
+    q16h_kernel<1><<<grid, dim3(1024), 0, st>>>(a, h);
+    if (hr == 4)
+      hhr_one_kernel<1, 4><<<dim3(1), dim3(1024), 0, st>>>(h.Rs, pe, pe, ell, h.Qr, pe, nullptr, 0, R, status);
+    else if (hr == 8)
+      hhr_one_kernel<1, 8><<<dim3(1), dim3(1024), 0, st>>>(h.Rs, pe, pe, ell, h.Qr, pe, nullptr, 0, R, status);
+    else
+      hhr_one_kernel<1, 16><<<dim3(1), dim3(1024), 0, st>>>(h.Rs, pe, pe, ell, h.Qr, pe, nullptr, 0, R, status);
+    q16h_kernel<2><<<grid, dim3(1024), 0, st>>>(a, h);
+    *covered = true;
+    return hipGetLastError();
+  }
   q16_kernel<0><<<grid, dim3(1024), 0, st>>>(a);
   q16_kernel<1><<<grid, dim3(1024), 0, st>>>(a);
   q16_kernel<2><<<grid, dim3(1024), 0, st>>>(a);

@@ -165,8 +165,10 @@ def test_small_sketch_rank_deficient(ctx, rows, ell, rank):
     an exactly rank-`rank` matrix (rank 0: the zero matrix): the CholeskyQR2
     for at most 16 columns (one launch for 300 x 16 and 700 x 4, three for
     the taller ones) reports the breakdown and the Householder fallback takes
-    over (in one workgroup; by the register-resident two-level tree for
-    70001 x 10 and 5000 x 1; by the device-memory tree for 100003 x 16).  An
+    over: inside the CholeskyQR2 launches where the register-resident form
+    fits (one workgroup for 300 x 16 and 700 x 4; the two-level tree over the
+    row blocks for 70001 x 10 and 5000 x 1), by the device-memory tree for
+    100003 x 16 (100 blocks of 16 columns: 1568 stacked rows).  An
     orthonormal basis whose first `rank` columns (unique) equal the
     oracle's."""
     _say("small-l rank-deficient", rows, ell, rank)
