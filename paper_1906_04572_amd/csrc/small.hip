@@ -1662,9 +1662,10 @@ __global__ void __launch_bounds__(1024) hh_expand_s_kernel(const double* __restr
 
 // ---------------------------------------------------------------------------
 // Householder QR with the working matrix in registers (l <= 64, panels of at
-// most 1024 / M rows).  The columns are taken in M sets of 16 (M = 1, 2, 4):
+// most 1024 / M rows).  The columns are taken in M sets of 16 (M = 1, 2, 4),
+// the rows in G = 4 NW row groups (NW waves, G >= 16 M):
 // thread t serves columns c + 16 m (c = t % 16, m < M) of the rows
-// i = r + 64 q (r = t / 16, q < R), holding W(i, c + 16 m) in w[m][q], so
+// i = r + G q (r = t / 16, q < R), holding W(i, c + 16 m) in w[m][q], so
 // the 16 lanes of a row group (one DPP row) hold one row.  A step s needs
 // column s at every thread of a row group: a DPP row broadcast (row_newbcast,
 // an immediate lane, hence one code path per s % 16) from set s / 16.  Each
@@ -1676,9 +1677,10 @@ __global__ void __launch_bounds__(1024) hh_expand_s_kernel(const double* __restr
 // of a wave by two v_permlane swaps, then the first wave adds the waves'
 // sums in wave order and publishes the column totals (two barriers; every
 // thread reading all the waves' sums would cost more LDS bandwidth than the
-// second barrier).  Rows below s occur only among the first 64 (s < l <= 64),
+// second barrier).  Rows below s occur only among the first G (s < l <= G),
 // and rows at or beyond the panel's height hold zeros, so only q = 0 takes a
-// mask.
+// mask.  Fewer waves (a short panel or root) make the two barriers and the
+// sum over the waves of each step cheaper.
 template <int S>
 __device__ __forceinline__ double hhr_bc16_one(double v) {
   // v_mov_b64_dpp row_newbcast:S
@@ -1760,7 +1762,7 @@ struct HhrLds {
 // row groups of each wave, then (first wave) the 16 waves in order.  Barrier
 // 1 publishes the waves' sums (and whatever the caller wrote before it),
 // barrier 2 the totals in sh.tot.
-template <int M>
+template <int M, int NW>
 __device__ __forceinline__ void hhr_totals(const double (&p)[M], HhrLds<M>& sh) {
   constexpr int L = 16 * M;
   const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
@@ -1773,7 +1775,7 @@ __device__ __forceinline__ void hhr_totals(const double (&p)[M], HhrLds<M>& sh) 
   if (wave == 0 && lane < L) {
     double a = 0.0;
 #pragma unroll
-    for (int w = 0; w < 16; ++w) a += sh.part[w * L + lane];
+    for (int w = 0; w < NW; ++w) a += sh.part[w * L + lane];
     sh.tot[lane] = a;
   }
   __syncthreads();
@@ -1783,7 +1785,7 @@ __device__ __forceinline__ void hhr_totals(const double (&p)[M], HhrLds<M>& sh) 
 // Afterwards w holds R above the diagonal, the reflector tails below it and
 // the original x_s on the diagonal; tau, alpha (R's diagonal) and vhead (the
 // first entry of each reflector) go to LDS.  Ends with a barrier.
-template <int M, int R>
+template <int M, int R, int NW>
 __device__ void hhr_factor(double (&w)[M][R], int ell, HhrLds<M>& sh) {
   const int t = threadIdx.x, c = t & 15, r = t >> 4;
   for (int s = 0; s < ell; ++s) {
@@ -1805,7 +1807,7 @@ __device__ void hhr_factor(double (&w)[M][R], int ell, HhrLds<M>& sh) {
 #pragma unroll
       for (int m = 0; m < M; ++m) prow[c + 16 * m] = w[m][0];
     }
-    hhr_totals<M>(p, sh);
+    hhr_totals<M, NW>(p, sh);
     const double ts = sh.tot[s], x0 = prow[s];
     const double nrm = sqrt(ts);
     double tv = 0.0, v0 = 0.0, a = 0.0;
@@ -1864,7 +1866,7 @@ __device__ __forceinline__ double hhr_refl(const double (&w)[R], double (&y)[R],
 
 // qv <- H_0 ... H_{ell-1} qv with the reflectors of hhr_factor (w and the
 // tau, vhead in sh).
-template <int M, int R>
+template <int M, int R, int NW>
 __device__ void hhr_apply(const double (&w)[M][R], double (&qv)[M][R], int ell, HhrLds<M>& sh) {
   const int t = threadIdx.x, c = t & 15, r = t >> 4;
   for (int s = ell - 1; s >= 0; --s) {
@@ -1874,7 +1876,7 @@ __device__ void hhr_apply(const double (&w)[M][R], double (&qv)[M][R], int ell, 
     if constexpr (R == 16) {  // one set of columns (M R <= 16)
       static_assert(M == 1, "16 rows per thread with one set of columns only");
       double p[1] = {hhr_refl<R, 0>(w[0], qv[0], r, s, v0, 0.0)};
-      hhr_totals<M>(p, sh);
+      hhr_totals<M, NW>(p, sh);
       const double d = c < ell ? tv * sh.tot[c] : 0.0;
       hhr_refl<R, 1>(w[0], qv[0], r, s, v0, d);
       continue;
@@ -1889,7 +1891,7 @@ __device__ void hhr_apply(const double (&w)[M][R], double (&qv)[M][R], int ell, 
       for (int q = 0; q < R; ++q) a[q & 3] = fma(hhr_v(x, q, r, s, v0), qv[m][q], a[q & 3]);
       p[m] = (a[0] + a[1]) + (a[2] + a[3]);
     }
-    hhr_totals<M>(p, sh);
+    hhr_totals<M, NW>(p, sh);
 #pragma unroll
     for (int m = 0; m < M; ++m) {
       const double d = c + 16 * m < ell ? tv * sh.tot[c + 16 * m] : 0.0;
@@ -1902,15 +1904,16 @@ __device__ void hhr_apply(const double (&w)[M][R], double (&qv)[M][R], int ell, 
 // w[m][q] = X(r0 + i, c + 16 m) for own rows i < nr and columns < ell, else
 // 0.  Every load is unconditional, from a clamped address, and masked
 // afterwards: loads under per-lane branches are waited for one by one.
-template <int M, int R>
+template <int M, int R, int NW>
 __device__ __forceinline__ void hhr_load(double (&w)[M][R], const double* __restrict__ X, int64_t ldx, int64_t r0,
                                          int nr, int ell) {
+  constexpr int G = 4 * NW;  // row groups
   const int c = threadIdx.x & 15, r = threadIdx.x >> 4;
 #pragma unroll
   for (int m = 0; m < M; ++m)
 #pragma unroll
     for (int q = 0; q < R; ++q) {
-      const int i = r + 64 * q, j = c + 16 * m;
+      const int i = r + G * q, j = c + 16 * m;
       const int ic = i < nr ? i : nr - 1, jc = j < ell ? j : ell - 1;
       w[m][q] = X[(int64_t)jc * ldx + r0 + ic];
     }
@@ -1921,7 +1924,7 @@ __device__ __forceinline__ void hhr_load(double (&w)[M][R], const double* __rest
   for (int m = 0; m < M; ++m)
 #pragma unroll
     for (int q = 0; q < R; ++q) {
-      const int i = r + 64 * q, j = c + 16 * m;
+      const int i = r + G * q, j = c + 16 * m;
       double v = w[m][q];
       asm volatile("" : "+v"(v));
       w[m][q] = (i < nr && j < ell) ? v : 0.0;
@@ -1933,15 +1936,15 @@ __device__ __forceinline__ bool hhr_runs(const int* status) { return (*status & 
 
 // One workgroup: X (rows x ell, column-major) -> Q (diag R >= 0, FP64 and
 // optionally a float copy), R (nullable, ell x ell column-major).
-template <int M, int R>
+template <int M, int R, int NW>
 __device__ __forceinline__ void hhr_one_body(HhrLds<M>& sh, const double* __restrict__ X, int64_t ldx,
                                              int64_t rows, int ell, double* __restrict__ Q, int64_t ldq,
                                              float* __restrict__ Q32, int64_t ldq32, double* __restrict__ Rout) {
   const int t = threadIdx.x, c = t & 15, r = t >> 4;
   double w[M][R];
-  hhr_load<M, R>(w, X, ldx, 0, (int)rows, ell);
-  hhr_factor<M, R>(w, ell, sh);
-  if (Rout && r < ell) {  // rows i < ell are the first 64 (q = 0)
+  hhr_load<M, R, NW>(w, X, ldx, 0, (int)rows, ell);
+  hhr_factor<M, R, NW>(w, ell, sh);
+  if (Rout && r < ell) {  // rows i < ell are the first 4 NW (q = 0)
 #pragma unroll
     for (int m = 0; m < M; ++m) {
       const int j = c + 16 * m;
@@ -1957,7 +1960,7 @@ __device__ __forceinline__ void hhr_one_body(HhrLds<M>& sh, const double* __rest
   for (int m = 0; m < M; ++m)
 #pragma unroll
     for (int q = 0; q < R; ++q) qv[m][q] = (q == 0 && r == c + 16 * m && r < ell) ? 1.0 : 0.0;
-  hhr_apply<M, R>(w, qv, ell, sh);
+  hhr_apply<M, R, NW>(w, qv, ell, sh);
 #pragma unroll
   for (int m = 0; m < M; ++m) {
     const int j = c + 16 * m;
@@ -1965,7 +1968,7 @@ __device__ __forceinline__ void hhr_one_body(HhrLds<M>& sh, const double* __rest
     const bool flip = sh.alpha[j] < 0.0;
 #pragma unroll
     for (int q = 0; q < R; ++q) {
-      const int i = r + 64 * q;
+      const int i = r + 4 * NW * q;
       if (i < rows) {
         const double v = flip ? -qv[m][q] : qv[m][q];
         Q[(int64_t)j * ldq + i] = v;
@@ -1975,28 +1978,28 @@ __device__ __forceinline__ void hhr_one_body(HhrLds<M>& sh, const double* __rest
   }
 }
 
-template <int M, int R>
-__global__ void __launch_bounds__(1024) hhr_one_kernel(const double* __restrict__ X, int64_t ldx, int64_t rows,
+template <int M, int R, int NW>
+__global__ void __launch_bounds__(64 * NW) hhr_one_kernel(const double* __restrict__ X, int64_t ldx, int64_t rows,
                                                        int ell, double* __restrict__ Q, int64_t ldq,
                                                        float* __restrict__ Q32, int64_t ldq32,
                                                        double* __restrict__ Rout, const int* status) {
   if (!hhr_runs(status)) return;
   __shared__ HhrLds<M> sh;
-  hhr_one_body<M, R>(sh, X, ldx, rows, ell, Q, ldq, Q32, ldq32, Rout);
+  hhr_one_body<M, R, NW>(sh, X, ldx, rows, ell, Q, ldq, Q32, ldq32, Rout);
 }
 
 // Tree level 1: panel b (rows split evenly over P panels) reduced; its
 // reflectors (and R's entries above them) to W, its triangle to rows
 // b ell .. of Rs (ld P ell), tau and vhead to tv.
-template <int M, int R>
+template <int M, int R, int NW>
 __device__ __forceinline__ void hhr_panel_body(HhrLds<M>& sh, const double* __restrict__ X, int64_t ldx,
                                                int64_t rows, int ell, int P, int b, double* __restrict__ W,
                                                int64_t ldw, double* __restrict__ Rs, double* __restrict__ tv) {
   const int t = threadIdx.x, c = t & 15, r = t >> 4;
   const int64_t r0 = (int64_t)b * rows / P, hb = (int64_t)(b + 1) * rows / P - r0;
   double w[M][R];
-  hhr_load<M, R>(w, X, ldx, r0, (int)hb, ell);
-  hhr_factor<M, R>(w, ell, sh);
+  hhr_load<M, R, NW>(w, X, ldx, r0, (int)hb, ell);
+  hhr_factor<M, R, NW>(w, ell, sh);
   const int64_t ldr = (int64_t)P * ell;
 #pragma unroll
   for (int m = 0; m < M; ++m) {
@@ -2005,7 +2008,7 @@ __device__ __forceinline__ void hhr_panel_body(HhrLds<M>& sh, const double* __re
     if (r < ell) Rs[(int64_t)j * ldr + (int64_t)b * ell + r] = r < j ? w[m][0] : (r == j ? sh.alpha[r] : 0.0);
 #pragma unroll
     for (int q = 0; q < R; ++q) {
-      const int i = r + 64 * q;
+      const int i = r + 4 * NW * q;
       if (i < hb) W[(int64_t)j * ldw + r0 + i] = w[m][q];
     }
   }
@@ -2015,18 +2018,18 @@ __device__ __forceinline__ void hhr_panel_body(HhrLds<M>& sh, const double* __re
   }
 }
 
-template <int M, int R>
-__global__ void __launch_bounds__(1024) hhr_panel_kernel(const double* __restrict__ X, int64_t ldx, int64_t rows,
+template <int M, int R, int NW>
+__global__ void __launch_bounds__(64 * NW) hhr_panel_kernel(const double* __restrict__ X, int64_t ldx, int64_t rows,
                                                          int ell, int P, double* __restrict__ W, int64_t ldw,
                                                          double* __restrict__ Rs, double* __restrict__ tv,
                                                          const int* status) {
   if (!hhr_runs(status)) return;
   __shared__ HhrLds<M> sh;
-  hhr_panel_body<M, R>(sh, X, ldx, rows, ell, P, blockIdx.x, W, ldw, Rs, tv);
+  hhr_panel_body<M, R, NW>(sh, X, ldx, rows, ell, P, blockIdx.x, W, ldw, Rs, tv);
 }
 
 // Tree level 2: panel b of Q = its reflectors applied to [Qr rows b ell ..; 0].
-template <int M, int R>
+template <int M, int R, int NW>
 __device__ __forceinline__ void hhr_expand_body(HhrLds<M>& sh, const double* __restrict__ W, int64_t ldw,
                                                 int64_t rows, int ell, int P, int b,
                                                 const double* __restrict__ Qr, const double* __restrict__ tv,
@@ -2040,7 +2043,7 @@ __device__ __forceinline__ void hhr_expand_body(HhrLds<M>& sh, const double* __r
     sh.vhead[t] = tv[(int64_t)b * 2 * ell + ell + t];
   }
   double w[M][R], qv[M][R];
-  hhr_load<M, R>(w, W, ldw, r0, (int)hb, ell);
+  hhr_load<M, R, NW>(w, W, ldw, r0, (int)hb, ell);
 #pragma unroll
   for (int m = 0; m < M; ++m) {
     const int j = c + 16 * m;
@@ -2050,7 +2053,7 @@ __device__ __forceinline__ void hhr_expand_body(HhrLds<M>& sh, const double* __r
     for (int q = 0; q < R; ++q) qv[m][q] = (q == 0 && r < ell && j < ell) ? v : 0.0;
   }
   __syncthreads();
-  hhr_apply<M, R>(w, qv, ell, sh);
+  hhr_apply<M, R, NW>(w, qv, ell, sh);
   // the output addresses are formed here, not kept in registers across the
   // loop above (the empty asm hides where the bases come from)
   double* Qo = Q + r0;
@@ -2062,7 +2065,7 @@ __device__ __forceinline__ void hhr_expand_body(HhrLds<M>& sh, const double* __r
     if (j >= ell) continue;
 #pragma unroll
     for (int q = 0; q < R; ++q) {
-      const int i = r + 64 * q;
+      const int i = r + 4 * NW * q;
       if (i < hb) {
         Qo[(int64_t)j * ldq + i] = qv[m][q];
         if (Q32o) Q32o[(int64_t)j * ldq32 + i] = (float)qv[m][q];
@@ -2071,15 +2074,15 @@ __device__ __forceinline__ void hhr_expand_body(HhrLds<M>& sh, const double* __r
   }
 }
 
-template <int M, int R>
-__global__ void __launch_bounds__(1024) hhr_expand_kernel(const double* __restrict__ W, int64_t ldw, int64_t rows,
+template <int M, int R, int NW>
+__global__ void __launch_bounds__(64 * NW) hhr_expand_kernel(const double* __restrict__ W, int64_t ldw, int64_t rows,
                                                           int ell, int P, const double* __restrict__ Qr,
                                                           const double* __restrict__ tv, double* __restrict__ Q,
                                                           int64_t ldq, float* __restrict__ Q32, int64_t ldq32,
                                                           const int* status) {
   if (!hhr_runs(status)) return;
   __shared__ HhrLds<M> sh;
-  hhr_expand_body<M, R>(sh, W, ldw, rows, ell, P, blockIdx.x, Qr, tv, Q, ldq, Q32, ldq32);
+  hhr_expand_body<M, R, NW>(sh, W, ldw, rows, ell, P, blockIdx.x, Qr, tv, Q, ldq, Q32, ldq32);
 }
 
 // ---------------------------------------------------------------------------
@@ -2250,7 +2253,7 @@ __global__ void __launch_bounds__(1024) q16h_one_kernel(Q16Args a) {
   __shared__ Q16Lds sh;
   __shared__ HhrLds<1> hs;
   if (q16_one_body(a, sh) == 1)
-    hhr_one_body<1, HR>(hs, a.x0, a.ld, a.rows, a.ell, a.q64, a.ld, a.q32, a.ld, a.rfac);
+    hhr_one_body<1, HR, 16>(hs, a.x0, a.ld, a.rows, a.ell, a.q64, a.ld, a.q32, a.ld, a.rfac);
 }
 
 template <int STEP>
@@ -2263,9 +2266,9 @@ __global__ void __launch_bounds__(1024) q16h_kernel(Q16Args a, Q16Hh h) {
     return;
   }
   if (STEP == 1)
-    hhr_panel_body<1, 16>(hs, a.x0, a.ld, a.rows, a.ell, a.nblk, blockIdx.x, h.W, h.ldw, h.Rs, h.tv);
+    hhr_panel_body<1, 16, 16>(hs, a.x0, a.ld, a.rows, a.ell, a.nblk, blockIdx.x, h.W, h.ldw, h.Rs, h.tv);
   else
-    hhr_expand_body<1, 16>(hs, h.W, h.ldw, a.rows, a.ell, a.nblk, blockIdx.x, h.Qr, h.tv, a.q64, a.ld, a.q32,
+    hhr_expand_body<1, 16, 16>(hs, h.W, h.ldw, a.rows, a.ell, a.nblk, blockIdx.x, h.Qr, h.tv, a.q64, a.ld, a.q32,
                            a.ld);
 }
 
@@ -2326,11 +2329,11 @@ hipError_t launch_qr16(const double* X, int64_t ld, int64_t rows, int ell, doubl
     q16_kernel<0><<<grid, dim3(1024), 0, st>>>(a);
     q16h_kernel<1><<<grid, dim3(1024), 0, st>>>(a, h);
     if (hr == 4)
-      hhr_one_kernel<1, 4><<<dim3(1), dim3(1024), 0, st>>>(h.Rs, pe, pe, ell, h.Qr, pe, nullptr, 0, R, status);
+      hhr_one_kernel<1, 4, 16><<<dim3(1), dim3(1024), 0, st>>>(h.Rs, pe, pe, ell, h.Qr, pe, nullptr, 0, R, status);
     else if (hr == 8)
-      hhr_one_kernel<1, 8><<<dim3(1), dim3(1024), 0, st>>>(h.Rs, pe, pe, ell, h.Qr, pe, nullptr, 0, R, status);
+      hhr_one_kernel<1, 8, 16><<<dim3(1), dim3(1024), 0, st>>>(h.Rs, pe, pe, ell, h.Qr, pe, nullptr, 0, R, status);
     else
-      hhr_one_kernel<1, 16><<<dim3(1), dim3(1024), 0, st>>>(h.Rs, pe, pe, ell, h.Qr, pe, nullptr, 0, R, status);
+      hhr_one_kernel<1, 16, 16><<<dim3(1), dim3(1024), 0, st>>>(h.Rs, pe, pe, ell, h.Qr, pe, nullptr, 0, R, status);
     q16h_kernel<2><<<grid, dim3(1024), 0, st>>>(a, h);
     *covered = true;
     return hipGetLastError();
@@ -2481,10 +2484,17 @@ static int hhr_rows_per_thread(int M, int64_t nr) {
   const int r = q <= 4 ? 4 : (q <= 8 ? 8 : (q <= 16 ? 16 : 0));
   return M * r <= 16 ? r : 0;
 }
+struct HhrShape {
+  int R = 0, NW = 0;
+};
+static HhrShape hhr_shape(int M, int64_t nr);
+
 // Panels of the register-resident tree: 1 (one workgroup), P >= 2, or 0
 // when rows is too large for two levels.  Within panel rows <= 1024 / M,
 // stacked triangles P ell <= 1024 / M and panel rows >= ell, the P whose
-// panel and root need the fewest rows per thread in all, the smallest such P.
+// launches (panels and expansion with the panel's shape, the root with its
+// own) need the fewest waves plus rows per thread in all (a step's cost
+// grows with both), the smallest such P.
 static int hhr_panels(int64_t rows, int ell) {
   const int M = hhr_sets(ell);
   if (M == 0) return 0;
@@ -2495,7 +2505,8 @@ static int hhr_panels(int64_t rows, int ell) {
   int64_t best = pmin;
   int best_cost = 1 << 30;
   for (int64_t P = pmin; P <= pmax; ++P) {
-    const int cost = hhr_rows_per_thread(M, (rows + P - 1) / P) + hhr_rows_per_thread(M, P * ell);
+    const HhrShape a = hhr_shape(M, (rows + P - 1) / P), b = hhr_shape(M, P * ell);
+    const int cost = 2 * (a.NW + a.R) + b.NW + b.R;
     if (cost < best_cost) {
       best_cost = cost;
       best = P;
@@ -2513,26 +2524,46 @@ size_t hh_work_bytes(int64_t rows, int ell) {
 
 // Householder QR by the register-resident kernels (one workgroup, or the
 // two-level tree); false when they do not apply.
+// Rows per thread and waves of one register-resident launch over nr rows:
+// the fewest waves (at least 4 M, so that the first row groups hold every
+// row above the diagonal) that hold the rows with at most 16 / M rows per
+// thread, then the fewest rows per thread.
+static HhrShape hhr_shape(int M, int64_t nr) {
+  HhrShape sh;
+  for (const int nw : {4, 8, 16}) {
+    if (4 * nw < 16 * M) continue;
+    for (const int r : {4, 8, 16}) {
+      if (M * r > 16) break;
+      if ((int64_t)4 * nw * r >= nr) {
+        sh.R = r;
+        sh.NW = nw;
+        return sh;
+      }
+    }
+  }
+  return sh;
+}
+
+// the launch shapes hhr_shape picks
+#define CORUTV_HHR_SHAPES(X) X(1, 4, 4) X(1, 8, 4) X(1, 16, 4) X(1, 16, 8) X(1, 16, 16) X(2, 4, 8) X(2, 8, 8) \
+  X(2, 8, 16) X(4, 4, 16)
+
 static bool launch_hhr(const double* X, int64_t ldx, int64_t rows, int ell, double* work, int64_t ldw, double* Q,
                        int64_t ldq, float* Q32, int64_t ldq32, double* R, const int* status, double* hw,
                        hipStream_t st) {
   const int P = hhr_panels(rows, ell);
   const int M = hhr_sets(ell);
   if (P == 0) return false;
-#define CORUTV_HHR_ONE(MM, RR)                                                                                \
-  if (M == MM && RP == RR)                                                                                    \
-  hhr_one_kernel<MM, RR><<<dim3(1), dim3(1024), 0, st>>>(x, ldxx, nr, ell, q, ldqq, q32, ldq32x, rr, status)
   auto one = [&](const double* x, int64_t ldxx, int64_t nr, double* q, int64_t ldqq, float* q32, int64_t ldq32x,
                  double* rr) {
-    const int RP = hhr_rows_per_thread(M, nr);
-    CORUTV_HHR_ONE(1, 4);
-    CORUTV_HHR_ONE(1, 8);
-    CORUTV_HHR_ONE(1, 16);
-    CORUTV_HHR_ONE(2, 4);
-    CORUTV_HHR_ONE(2, 8);
-    CORUTV_HHR_ONE(4, 4);
-  };
+    const HhrShape h = hhr_shape(M, nr);
+#define CORUTV_HHR_ONE(MM, RR, NWW)                                                                            \
+  if (M == MM && h.R == RR && h.NW == NWW)                                                                     \
+    hhr_one_kernel<MM, RR, NWW><<<dim3(1), dim3(64 * NWW), 0, st>>>(x, ldxx, nr, ell, q, ldqq, q32, ldq32x, rr, \
+                                                                    status);
+    CORUTV_HHR_SHAPES(CORUTV_HHR_ONE)
 #undef CORUTV_HHR_ONE
+  };
   if (P == 1) {
     one(X, ldx, rows, Q, ldq, Q32, ldq32, R);
     return true;
@@ -2542,31 +2573,23 @@ static bool launch_hhr(const double* X, int64_t ldx, int64_t rows, int ell, doub
   double* Rs = hw;                  // stacked triangles, pe x ell
   double* Qr = Rs + 2 * pe * ell;   // the root's Q
   double* tv = Qr + pe * ell;       // per panel: tau[ell], vhead[ell]
-  const int RP = hhr_rows_per_thread(M, (rows + P - 1) / P);
-#define CORUTV_HHR_PANEL(MM, RR)                                                                                \
-  if (M == MM && RP == RR)                                                                                     \
-    hhr_panel_kernel<MM, RR><<<dim3(P), dim3(1024), 0, st>>>(X, ldx, rows, ell, P, work, ldw, Rs, tv, status)
-#define CORUTV_HHR_EXPAND(MM, RR)                                                                               \
-  if (M == MM && RP == RR)                                                                                     \
-    hhr_expand_kernel<MM, RR><<<dim3(P), dim3(1024), 0, st>>>(work, ldw, rows, ell, P, Qr, tv, Q, ldq, Q32, ldq32, \
-                                                              status)
-  CORUTV_HHR_PANEL(1, 4);
-  CORUTV_HHR_PANEL(1, 8);
-  CORUTV_HHR_PANEL(1, 16);
-  CORUTV_HHR_PANEL(2, 4);
-  CORUTV_HHR_PANEL(2, 8);
-  CORUTV_HHR_PANEL(4, 4);
+  const HhrShape h = hhr_shape(M, (rows + P - 1) / P);
+#define CORUTV_HHR_PANEL(MM, RR, NWW)                                                                            \
+  if (M == MM && h.R == RR && h.NW == NWW)                                                                       \
+    hhr_panel_kernel<MM, RR, NWW><<<dim3(P), dim3(64 * NWW), 0, st>>>(X, ldx, rows, ell, P, work, ldw, Rs, tv, \
+                                                                      status);
+#define CORUTV_HHR_EXPAND(MM, RR, NWW)                                                                           \
+  if (M == MM && h.R == RR && h.NW == NWW)                                                                       \
+    hhr_expand_kernel<MM, RR, NWW><<<dim3(P), dim3(64 * NWW), 0, st>>>(work, ldw, rows, ell, P, Qr, tv, Q, ldq, \
+                                                                       Q32, ldq32, status);
+  CORUTV_HHR_SHAPES(CORUTV_HHR_PANEL)
   one(Rs, pe, pe, Qr, pe, nullptr, 0, R);
-  CORUTV_HHR_EXPAND(1, 4);
-  CORUTV_HHR_EXPAND(1, 8);
-  CORUTV_HHR_EXPAND(1, 16);
-  CORUTV_HHR_EXPAND(2, 4);
-  CORUTV_HHR_EXPAND(2, 8);
-  CORUTV_HHR_EXPAND(4, 4);
+  CORUTV_HHR_SHAPES(CORUTV_HHR_EXPAND)
 #undef CORUTV_HHR_PANEL
 #undef CORUTV_HHR_EXPAND
   return true;
 }
+#undef CORUTV_HHR_SHAPES
 
 hipError_t launch_householder_qr(const double* X, int64_t ldx, int64_t rows, int ell, double* work,
                                  int64_t ldw, double* Q, int64_t ldq, float* Q32, int64_t ldq32,
