@@ -229,6 +229,10 @@ struct DecArgs {
   corutv_mat A, U, V;
   double* T = nullptr;
   int64_t ldt = 0;
+  // optional: T's transpose with the other triangle zeroed, written by the
+  // same launch as T (ld ldt2)
+  double* T2 = nullptr;
+  int64_t ldt2 = 0;
   int32_t* piv = nullptr;
   int k = 0, p = 0, q = 0;
   uint64_t seed = 0;
@@ -518,9 +522,14 @@ int enqueue_decompose(corutv_ctx* ctx, const Plan& pl, char* ws, const DecArgs& 
     HIPOK(launch_rowmat(q2, ldn, nn, ell, qt, ell, nullptr, ov, 0, v64, 0, nullptr, s));
   }
   // To (oriented) into tt; user T = To (not transposed) or To^T (transposed)
-  HIPOK(launch_copy_tri(rt, ell, lower_inner ? 1 : 0, lower_inner ? 0 : 1, tt, ell, s));
   const bool t_lower_user = transposed ? !lower_inner : lower_inner;
-  HIPOK(launch_copy_tri(tt, ell, transposed ? 1 : 0, t_lower_user ? 0 : 1, d.T, d.ldt, s));
+  {
+    double* dst[3] = {tt, d.T, d.T2};
+    const int64_t ld[3] = {ell, d.ldt, d.ldt2};
+    const int tr[3] = {lower_inner ? 1 : 0, transposed ? 1 : 0, 1};
+    const int up[3] = {lower_inner ? 0 : 1, t_lower_user ? 0 : 1, t_lower_user ? 1 : 0};
+    HIPOK(launch_copy_tri_chain(rt, ell, d.T2 ? 3 : 2, dst, ld, tr, up, s));
+  }
   if (d.piv) HIPOK(hipMemcpyAsync(d.piv, piv, (size_t)ell * 4, hipMemcpyDeviceToDevice, s));
   int passes = 2 * d.q + (core_rz ? 2 : 3);
   double* sum = (double*)(ws + pl.o_sum);
@@ -1456,6 +1465,8 @@ extern "C" int corutv_rpca(corutv_ctx* ctx, const corutv_mat* M, double lambda, 
   d.V = corutv_mat{V, n, ell, n, CORUTV_F64, CORUTV_COL_MAJOR};
   d.T = T;
   d.ldt = ell;
+  d.T2 = Tt;  // T^T for the rank-r factors below, from the same launch as T
+  d.ldt2 = ell;
   d.k = k;
   d.p = p;
   d.q = q;
@@ -1494,7 +1505,6 @@ extern "C" int corutv_rpca(corutv_ctx* ctx, const corutv_mat* M, double lambda, 
     MatOut o;
     o.ptr = lower ? Pm : Qm;
     o.ld = lower ? m : n;
-    HIPOK(launch_copy_tri(T, ell, 1, lower ? 1 : 0, Tt, ell, s));
     if (lower)
       HIPOK(launch_rowmat(U, m, m, ell, T, ell, nullptr, o, 0, MatOut(), 0, nullptr, s));
     else

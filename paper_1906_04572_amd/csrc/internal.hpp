@@ -168,6 +168,11 @@ hipError_t launch_qrcp(const double* D, int64_t ldd, int trans, int ell, double*
 // zeroed strict lower (upper=1) or strict upper (upper=0) part) to dst.
 hipError_t launch_copy_tri(const double* src, int ell, int trans, int upper, double* dst, int64_t ldd,
                            hipStream_t st);
+// n (1..3) chained copies in one launch: stage 0 is launch_copy_tri(src,
+// ell, trans[0], upper[0], dst[0], ld[0]); stage k the same copy of stage
+// k - 1's result into dst[k].
+hipError_t launch_copy_tri_chain(const double* src, int ell, int n, double* const* dst, const int64_t* ld,
+                                 const int* trans, const int* upper, hipStream_t st);
 
 // Residual: part[b] = { sum (A - B V^T)^2, sum A^2 } over row block b, with
 // A row-major R x C (dtype F64/F32), B (R x ell) and V (C x ell) column-major

@@ -2086,6 +2086,36 @@ __global__ void __launch_bounds__(64 * NW) hhr_expand_kernel(const double* __res
 }
 
 // ---------------------------------------------------------------------------
+// A chain of up to three triangle copies in one launch: stage k copies stage
+// k - 1's result (stage 0 copies src) as copy_tri_kernel would; every entry
+// of every stage is traced back to src through the stages' transposes and
+// masks.
+struct TriChain {
+  double* dst[3];
+  int64_t ld[3];
+  int trans[3], upper[3];
+  int n;
+};
+
+__global__ void copy_tri_chain_kernel(const double* __restrict__ src, int ell, TriChain c) {
+  const int e = blockIdx.x * blockDim.x + threadIdx.x;
+  if (e >= ell * ell) return;
+  const int i0 = e % ell, j0 = e / ell;
+  for (int k = 0; k < c.n; ++k) {
+    int i = i0, j = j0;
+    bool zero = false;
+    for (int t = k; t >= 0; --t) {
+      if (c.upper[t] ? (i > j) : (i < j)) zero = true;
+      if (c.trans[t]) {
+        const int x = i;
+        i = j;
+        j = x;
+      }
+    }
+    c.dst[k][(int64_t)j0 * c.ld[k] + i0] = zero ? 0.0 : src[(int64_t)j * ell + i];
+  }
+}
+
 __global__ void copy_tri_kernel(const double* __restrict__ src, int ell, int trans, int upper,
                                 double* __restrict__ dst, int64_t ldd) {
   const int e = blockIdx.x * blockDim.x + threadIdx.x;
@@ -2668,6 +2698,22 @@ hipError_t launch_copy_tri(const double* src, int ell, int trans, int upper, dou
                            hipStream_t st) {
   const int n = ell * ell;
   copy_tri_kernel<<<dim3((n + 255) / 256), dim3(256), 0, st>>>(src, ell, trans, upper, dst, ldd);
+  return hipGetLastError();
+}
+
+hipError_t launch_copy_tri_chain(const double* src, int ell, int n, double* const* dst, const int64_t* ld,
+                                 const int* trans, const int* upper, hipStream_t st) {
+  if (n < 1 || n > 3) return hipErrorInvalidValue;
+  TriChain c;
+  c.n = n;
+  for (int k = 0; k < 3; ++k) {
+    c.dst[k] = k < n ? dst[k] : nullptr;
+    c.ld[k] = k < n ? ld[k] : 0;
+    c.trans[k] = k < n ? trans[k] : 0;
+    c.upper[k] = k < n ? upper[k] : 0;
+  }
+  const int e = ell * ell;
+  copy_tri_chain_kernel<<<dim3((e + 255) / 256), dim3(256), 0, st>>>(src, ell, c);
   return hipGetLastError();
 }
 
