@@ -554,12 +554,19 @@ __global__ void __launch_bounds__(64 * WG) __attribute__((amdgpu_waves_per_eu(MB
 #pragma unroll
           for (int e = 0; e < NB * KB * 8; ++e) bcur[e] = bnx[e];
           load_b(kb + 3 < gk1 ? kb + 3 : gk1 - 1, bnx);
+          // the next body's stores wait for the skinny loads issued above:
+          // keep them behind this body's work
+          __builtin_amdgcn_sched_barrier(0);
           ++iter;
         };
-        for (int kb = gk0; kb < gk1; kb += 2) {
+        // pairs of bodies with no branch between them (a load whose only use
+        // sits behind a branch is moved down to it and then waited for)
+        int kb = gk0;
+        for (; kb + 1 < gk1; kb += 2) {
           body(kb, bna);
-          if (kb + 1 < gk1) body(kb + 1, bnb);
+          body(kb + 1, bnb);
         }
+        if (kb < gk1) body(kb, bna);
       } else {
         // DEPTH A buffers in rotation (the stage is written DEPTH times), so
         // no register copy waits for a load in flight; the A loads run
