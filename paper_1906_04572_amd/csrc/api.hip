@@ -302,13 +302,9 @@ hipError_t qr_from_partials(const Plan& pl, char* ws, const Partials& pp, int64_
     return launch_householder_qr(x0, ld, rows, ell, x1, ld, q64, ld, q32, ld, rfac, st,
                                  (double*)(ws + pl.o_hh), s);
   }
-  // after a breakdown in an earlier QR of this decomposition (the word past
-  // the QRs' status words), the first Gram and Cholesky return at once and
-  // the Householder fallback factors X
-  int* seen = (int*)(ws + pl.o_st) + (kMaxQr - 1);
-  if ((e = launch_xty(x0, ld, x0, ld, rows, ell, xp, splits, seen, s)) != hipSuccess) return e;
-  if ((e = launch_reduce(xp, splits, l2, G, seen, s)) != hipSuccess) return e;
-  if ((e = launch_chol(G, ell, R, Ri, st, nullptr, cw, s, one_step ? kOneStepThr : 0.0, seen)) != hipSuccess)
+  if ((e = launch_xty(x0, ld, x0, ld, rows, ell, xp, splits, nullptr, s)) != hipSuccess) return e;
+  if ((e = launch_reduce(xp, splits, l2, G, nullptr, s)) != hipSuccess) return e;
+  if ((e = launch_chol(G, ell, R, Ri, st, nullptr, cw, s, one_step ? kOneStepThr : 0.0)) != hipSuccess)
     return e;
   MatOut ox1;
   ox1.ptr = x1;
@@ -331,7 +327,7 @@ hipError_t qr_from_partials(const Plan& pl, char* ws, const Partials& pp, int64_
   if ((e = launch_xty(x1, ld, x1, ld, rows, ell, xp, splits, st, s)) != hipSuccess) return e;
   if ((e = launch_reduce(xp, splits, l2, G, st, s)) != hipSuccess) return e;
   double* R2 = R + l2;  // the second factor goes beside the first
-  if ((e = launch_chol(G, ell, R2, Ri, st, st, cw, s, 0.0, seen)) != hipSuccess) return e;
+  if ((e = launch_chol(G, ell, R2, Ri, st, st, cw, s)) != hipSuccess) return e;
   if ((e = launch_rowmat(x1, ld, rows, ell, Ri, ell, nullptr, o1, 1, o2, 1, st, s, true)) != hipSuccess)
     return e;
   // optional R factor: R2 R1 on the Cholesky route, the Householder R after a

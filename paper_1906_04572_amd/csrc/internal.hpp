@@ -109,13 +109,9 @@ hipError_t launch_rowmat(const double* X, int64_t ldx, int64_t rows, int ell, co
 // single_thr > 0: on success, status also gets bit 3 (value 4) when
 // u * ell * ||R||_F^2 * ||R^-1||_F^2 <= single_thr, i.e. when one CholeskyQR
 // step already leaves an orthogonality loss below that level.
-// seen (nullable): a word shared by the QRs of one decomposition; a breakdown
-// sets it, and while it is set the kernel only records a breakdown (status
-// bit 1), so the Householder fallback takes over without a Cholesky.
 size_t chol_work_bytes(int ell);
 hipError_t launch_chol(const double* G, int ell, double* R, double* Rinv, int* status,
-                       const int* skip, double* work, hipStream_t st, double single_thr = 0.0,
-                       int* seen = nullptr);
+                       const int* skip, double* work, hipStream_t st, double single_thr = 0.0);
 
 // R = R2 R1 (upper triangular, column-major ld ell) when *status shows the
 // Cholesky route was taken; otherwise does nothing.

@@ -593,16 +593,8 @@ template <bool kLds>
 __global__ void __launch_bounds__(1024) chol_kernel(const double* __restrict__ G, int ell,
                                                     double* __restrict__ R, double* __restrict__ Rinv,
                                                     int* status, const int* skip, double* work,
-                                                    double single_thr, int* seen) {
+                                                    double single_thr) {
   if (skip && *skip) return;
-  // an earlier QR of the same decomposition broke down: its sketches come
-  // from the same subspace, so this one is taken to break down too and goes
-  // to the Householder fallback directly (the launches before this one read
-  // the same word and returned)
-  if (seen && *seen) {
-    if (threadIdx.x == 0) atomicOr(status, 1);
-    return;
-  }
   constexpr int kLdsTiles = kLds ? kCholLdsNb * (kCholLdsNb + 1) : 1;
   __shared__ double lds_tiles[kLdsTiles * 256];
   __shared__ double xt[256], dbuf[256];
@@ -660,10 +652,7 @@ __global__ void __launch_bounds__(1024) chol_kernel(const double* __restrict__ G
   if (wave == 0 && !chol_diag16(W(0, 0), 0, ell, thr, W(0, 0), E(0, 0), xt, lane) && lane == 0) flag = 1;
   __syncthreads();
   if (flag) {
-    if (tid == 0) {
-      atomicOr(status, 1);
-      if (seen) atomicOr(seen, 1);
-    }
+    if (tid == 0) atomicOr(status, 1);
     return;
   }
   for (int J = 0; J < nb; ++J) {
@@ -714,10 +703,7 @@ __global__ void __launch_bounds__(1024) chol_kernel(const double* __restrict__ G
     }
     __syncthreads();
     if (flag) {
-      if (tid == 0) {
-        atomicOr(status, 1);
-        if (seen) atomicOr(seen, 1);
-      }
+      if (tid == 0) atomicOr(status, 1);
       return;
     }
   }
@@ -2472,11 +2458,11 @@ size_t chol_work_bytes(int ell) {
 }
 
 hipError_t launch_chol(const double* G, int ell, double* R, double* Rinv, int* status,
-                       const int* skip, double* work, hipStream_t st, double single_thr, int* seen) {
+                       const int* skip, double* work, hipStream_t st, double single_thr) {
   if ((ell + 15) / 16 <= kCholLdsNb)
-    chol_kernel<true><<<dim3(1), dim3(1024), 0, st>>>(G, ell, R, Rinv, status, skip, nullptr, single_thr, seen);
+    chol_kernel<true><<<dim3(1), dim3(1024), 0, st>>>(G, ell, R, Rinv, status, skip, nullptr, single_thr);
   else
-    chol_kernel<false><<<dim3(1), dim3(1024), 0, st>>>(G, ell, R, Rinv, status, skip, work, single_thr, seen);
+    chol_kernel<false><<<dim3(1), dim3(1024), 0, st>>>(G, ell, R, Rinv, status, skip, work, single_thr);
   return hipGetLastError();
 }
 
