@@ -572,3 +572,29 @@ def test_zero_matrix(ctx, prec, k, p):
     ell = k + p
     assert np.max(np.abs(U.T @ U - np.eye(ell))) <= tol
     assert np.max(np.abs(V.T @ V - np.eye(ell))) <= tol
+
+
+@pytest.mark.parametrize("prec", ["f64", "f32", "bf16x3", "bf16"])
+@pytest.mark.parametrize("m,n,rank,k", [(3000, 2000, 30, 80), (900, 5000, 20, 100)])
+def test_wide_sketch_breakdown_fp32_storage(ctx, prec, m, n, rank, k):
+    """An exactly rank-`rank` matrix with l = k + 10 > 64: in F64 and F32 every
+    sketch is numerically rank-deficient, so the CholeskyQR of the general
+    form breaks down and the LDS or device-memory Householder tree (l > 64)
+    takes over (F32 storage of the bases included); in the BF16 forms the
+    rounding of A to bf16 may leave the sketches full rank.  Every form:
+    finite, orthonormal bases and the matrix reproduced to its rounding."""
+    _say("wide-sketch breakdown", prec, m, n, rank, k)
+    rng = np.random.default_rng(m + n + rank)
+    A64 = rng.standard_normal((m, rank)) @ rng.standard_normal((rank, n))
+    A = A64 if prec == "f64" else A64.astype(np.float32)
+    U, T, V, piv, info = _run(ctx, A, k, 10, 1, 9, prec, "auto")
+    ell = k + 10
+    if prec in ("f64", "f32"):
+        assert info["qr_fallbacks"] >= 1
+    print("fallbacks", info["qr_fallbacks"])
+    assert np.all(np.isfinite(U)) and np.all(np.isfinite(V)) and np.all(np.isfinite(T))
+    tol = 1e-13 if prec == "f64" else 1e-5
+    assert np.max(np.abs(U.T @ U - np.eye(ell))) <= tol
+    assert np.max(np.abs(V.T @ V - np.eye(ell))) <= tol
+    bar = 1e-12 if prec == "f64" else (2e-3 if prec == "bf16" else 1e-5)
+    assert np.linalg.norm(A.astype(np.float64) - U @ T @ V.T) <= bar * np.linalg.norm(A64)
